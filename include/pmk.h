@@ -1,0 +1,175 @@
+/*
+ * pmk.h -- C ABI of the PMKRSA batched modular-exponentiation library (MI355X, gfx950).
+ *
+ * The library runs the data-parallel part of the parallelised multi-key RSA
+ * scheme of "A Variant RSA Acceleration with Parallelization" (arXiv
+ * 2111.11924): a message is split into chunks, chunk i is encrypted under its
+ * own key pair (Sec. 3.1 and Algorithm 1), with c = m^e mod N (Sec. 1.1, step 2)
+ * and decrypted with the private exponent through the Chinese Remainder
+ * Theorem (Sec. 2.1, equation CRT-RSA).  Modular exponentiation and Montgomery
+ * multiplication follow Sec. 3.2 (Algorithms 2 and 3); all of it runs in HIP
+ * kernels on the GPU.
+ *
+ * Conventions
+ *   - Big integers are little-endian arrays of uint32_t limbs.
+ *   - Plaintext chunk i holds kb_i - 4 message bytes, kb_i = bits/8 of its key;
+ *     the last chunk holds the remaining 1..kb_i-4 bytes.  A chunk is read as a
+ *     big-endian integer, so every chunk is below its modulus.
+ *   - Ciphertext block i is kb_i bytes, big-endian; blocks are concatenated in
+ *     chunk order.  The ciphertext length is the sum of kb_i.
+ *   - Functions return PMK_OK (0) or a negative status; on a validation error
+ *     no output buffer is touched.  pmk_last_error() gives a message.
+ *   - "Device pointer" means memory of the context's GPU (hipMalloc, or a torch
+ *     CUDA tensor); "stream" is a hipStream_t passed as void* (NULL = the
+ *     default stream).  Work on a stream is asynchronous: a zero return covers
+ *     host-side validation and launch; errors the GPU detects (a ciphertext
+ *     block not below its modulus) are reported by pmk_plan_check().
+ *   - One context per host thread; a context is not thread-safe.
+ */
+#ifndef PMK_H
+#define PMK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PMK_OK = 0,
+    PMK_EINVAL = -1,      /* bad argument or inconsistent key material */
+    PMK_EKEY = -2,        /* a chunk names a key index >= number of loaded keys */
+    PMK_ERANGE = -3,      /* a ciphertext block is not below its modulus (C must lie in Z_N, Sec. 1.1) */
+    PMK_ESIZE = -4,       /* chunk count / buffer sizes do not match the message */
+    PMK_ENOMEM = -5,      /* device or host allocation failed */
+    PMK_EDEVICE = -6,     /* HIP runtime error */
+    PMK_EBUSY = -7,       /* keys replaced while plans made from them still exist */
+    PMK_EUNSUPPORTED = -8 /* modulus size or exponent the library has no kernel for */
+};
+
+typedef struct pmk_ctx pmk_ctx;
+typedef struct pmk_plan pmk_plan;
+
+/*
+ * One key pair (Sec. 1.1 step 1; Algorithm 1, Initialization: N = p q, public
+ * exponent e, private exponent split for CRT decryption into
+ * dp = d mod (p-1), dq = d mod (q-1) and qinv = q^-1 mod p, Sec. 2.1).
+ *   bits    modulus length: a multiple of 64, 128..4096; N must have exactly
+ *           this many bits.
+ *   n       bits/32 limbs.
+ *   n0inv   -N^-1 mod 2^32 (Montgomery constant of Algorithm 3 for r = 2^32).
+ *   rr      bits/32 limbs: R^2 mod N with R = 2^bits.
+ *   e       e_limbs limbs (1 or 2): the public exponent, odd, >= 3, < 2^64.
+ *   p, q    bits/64 limbs each, p > q, p q = N.
+ *   dp, dq  bits/64 limbs each.
+ *   qinv    bits/64 limbs: q^-1 mod p.
+ * n0inv, rr and p q = N, q qinv = 1 mod p are checked at load time.
+ * The caller keeps ownership of every array; the library copies them.
+ */
+typedef struct {
+    uint32_t bits;
+    const uint32_t *n;
+    uint32_t n0inv;
+    const uint32_t *rr;
+    const uint32_t *e;
+    uint32_t e_limbs;
+    const uint32_t *p;
+    const uint32_t *q;
+    const uint32_t *dp;
+    const uint32_t *dq;
+    const uint32_t *qinv;
+} pmk_key;
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+int pmk_create(int device, pmk_ctx **out);
+
+/* Free the context, its device key table and every plan still attached to it. */
+void pmk_destroy(pmk_ctx *ctx);
+
+/* Message of the last error on this context (never NULL; "" when none). */
+const char *pmk_last_error(const pmk_ctx *ctx);
+
+/*
+ * Load (replace) the device key table: the key vectors E, D, N of Sec. 3.1
+ * (one key pair per row of the chunk matrix).  Validates every key, derives the
+ * per-prime Montgomery constants used by the kernels, and uploads the table.
+ * Synchronous.  PMK_EINVAL names the first bad key in pmk_last_error();
+ * PMK_EBUSY if plans made from the previous table are still alive.
+ */
+int pmk_keys_load(pmk_ctx *ctx, const pmk_key *keys, uint32_t nkeys);
+
+/*
+ * Host-only check of one key pair, the same checks pmk_keys_load makes (no GPU
+ * needed).  Returns PMK_OK, PMK_EINVAL (reason written to msg[0..msg_cap),
+ * msg may be NULL) or PMK_EUNSUPPORTED (no kernel for the modulus size).
+ */
+int pmk_key_check(const pmk_key *key, char *msg, size_t msg_cap);
+
+/*
+ * Host-only form of the chunk planning (no GPU needed): given the modulus bits
+ * of nkeys keys, check key_map[0..nchunks) against a msg_len-byte message as
+ * pmk_plan_create does (PMK_EKEY, PMK_ESIZE; PMK_EINVAL for bad key sizes) and
+ * return the ciphertext length in *ct_len (may be NULL).
+ */
+int pmk_plan_validate(const uint32_t *key_bits, uint32_t nkeys, const uint32_t *key_map,
+                      uint64_t nchunks, uint64_t msg_len, uint64_t *ct_len);
+
+/* Number of keys loaded and the modulus bits of key `index` (0 if out of range). */
+uint32_t pmk_key_count(const pmk_ctx *ctx);
+uint32_t pmk_key_bits(const pmk_ctx *ctx, uint32_t index);
+
+/*
+ * Plan the chunking of a msg_len-byte message over the chunk-to-key map
+ * key_map[0..nchunks) (HOST memory; chunk i uses key key_map[i]; Sec. 3.1).
+ * Checks every key index (PMK_EKEY) and that nchunks is exactly the number of
+ * chunks the message needs (PMK_ESIZE); msg_len = 0 requires nchunks = 0.
+ * Sorts chunks by modulus size, computes chunk offsets, uploads them and
+ * allocates the device scratch the kernels need.  *ct_len (may be NULL)
+ * receives the ciphertext length.  The plan stays valid until destroyed or
+ * until its context is destroyed.
+ */
+int pmk_plan_create(pmk_ctx *ctx, const uint32_t *key_map, uint64_t nchunks, uint64_t msg_len,
+                    pmk_plan **out, uint64_t *ct_len);
+void pmk_plan_destroy(pmk_plan *plan);
+
+/* Sizes recorded in a plan. */
+int pmk_plan_info(const pmk_plan *plan, uint64_t *msg_len, uint64_t *nchunks, uint64_t *ct_len);
+
+/*
+ * Encrypt (Algorithm 1, Encryption, without the blinding factor): for every
+ * chunk c_i = m_i^e mod N_key(i).  d_msg: plan msg_len bytes (device);
+ * d_ct: plan ct_len bytes (device).  Asynchronous on `stream`.
+ */
+int pmk_encrypt_plan(pmk_plan *plan, const uint8_t *d_msg, uint8_t *d_ct, void *stream);
+
+/*
+ * Decrypt by CRT (Sec. 2.1): m_p = c^dp mod p, m_q = c^dq mod q,
+ * h = qinv (m_p - m_q) mod p, m = m_q + h q; writes msg_len bytes.  d_ct: plan
+ * ct_len bytes (device); d_msg: plan msg_len bytes (device).  A block that is
+ * not below its modulus sets the plan's device error flag (PMK_ERANGE from
+ * pmk_plan_check); that chunk's output bytes are then unspecified.
+ */
+int pmk_decrypt_plan(pmk_plan *plan, const uint8_t *d_ct, uint8_t *d_msg, void *stream);
+
+/*
+ * Wait for `stream`, then return and clear the plan's device-detected error
+ * (PMK_OK or PMK_ERANGE).
+ */
+int pmk_plan_check(pmk_plan *plan, void *stream);
+
+/*
+ * One-shot forms: plan, run, check and free in one call; synchronous on
+ * `stream`.  key_map is host memory; d_msg / d_ct are device memory.
+ * ct_cap / msg_len are checked against the plan (PMK_ESIZE).
+ */
+int pmk_encrypt(pmk_ctx *ctx, const uint8_t *d_msg, uint64_t msg_len, const uint32_t *key_map,
+                uint64_t nchunks, uint8_t *d_ct, uint64_t ct_cap, void *stream);
+int pmk_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uint32_t *key_map,
+                uint64_t nchunks, uint8_t *d_msg, uint64_t msg_len, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMK_H */

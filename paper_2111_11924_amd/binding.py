@@ -1,0 +1,311 @@
+"""ctypes binding of libpmk.so (include/pmk.h): argument marshalling only.
+
+Every function of the C ABI appears here under the same name.  Device buffers
+are passed as torch CUDA tensors (or raw integer device addresses); streams as
+torch streams, raw hipStream_t integers, or None for the current torch stream.
+All arithmetic happens in the library's HIP kernels; if libpmk.so has not been
+built this module raises on first use instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmk.so")
+
+PMK_OK = 0
+PMK_EINVAL = -1
+PMK_EKEY = -2
+PMK_ERANGE = -3
+PMK_ESIZE = -4
+PMK_ENOMEM = -5
+PMK_EDEVICE = -6
+PMK_EBUSY = -7
+PMK_EUNSUPPORTED = -8
+
+STATUS_NAMES = {0: "PMK_OK", -1: "PMK_EINVAL", -2: "PMK_EKEY", -3: "PMK_ERANGE", -4: "PMK_ESIZE",
+                -5: "PMK_ENOMEM", -6: "PMK_EDEVICE", -7: "PMK_EBUSY", -8: "PMK_EUNSUPPORTED"}
+
+U32P = C.POINTER(C.c_uint32)
+
+
+class PmkError(RuntimeError):
+    def __init__(self, status: int, message: str = ""):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class pmk_key(C.Structure):
+    _fields_ = [("bits", C.c_uint32), ("n", U32P), ("n0inv", C.c_uint32), ("rr", U32P),
+                ("e", U32P), ("e_limbs", C.c_uint32), ("p", U32P), ("q", U32P), ("dp", U32P),
+                ("dq", U32P), ("qinv", U32P)]
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None) -> C.CDLL:
+    """Load libpmk.so (raises RuntimeError when it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build the HIP library first "
+                           "(python -m paper_2111_11924_amd.build)")
+    L = C.CDLL(p)
+    vp, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
+    sig = {
+        "pmk_create": (C.c_int, [C.c_int, C.POINTER(vp)]),
+        "pmk_destroy": (None, [vp]),
+        "pmk_last_error": (C.c_char_p, [vp]),
+        "pmk_keys_load": (C.c_int, [vp, C.POINTER(pmk_key), u32]),
+        "pmk_key_check": (C.c_int, [C.POINTER(pmk_key), C.c_char_p, C.c_size_t]),
+        "pmk_plan_validate": (C.c_int, [U32P, u32, U32P, u64, u64, C.POINTER(u64)]),
+        "pmk_key_count": (u32, [vp]),
+        "pmk_key_bits": (u32, [vp, u32]),
+        "pmk_plan_create": (C.c_int, [vp, U32P, u64, u64, C.POINTER(vp), C.POINTER(u64)]),
+        "pmk_plan_destroy": (None, [vp]),
+        "pmk_plan_info": (C.c_int, [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]),
+        "pmk_encrypt_plan": (C.c_int, [vp, vp, vp, vp]),
+        "pmk_decrypt_plan": (C.c_int, [vp, vp, vp, vp]),
+        "pmk_plan_check": (C.c_int, [vp, vp]),
+        "pmk_encrypt": (C.c_int, [vp, vp, u64, U32P, u64, vp, u64, vp]),
+        "pmk_decrypt": (C.c_int, [vp, vp, u64, U32P, u64, vp, u64, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = L
+    return L
+
+
+# ---------- marshalling helpers ------------------------------------------------------------
+
+def _limbs(x: int, n: int) -> np.ndarray:
+    if x < 0 or x.bit_length() > 32 * n:
+        raise ValueError("value does not fit its field")
+    return np.frombuffer(int(x).to_bytes(4 * n, "little"), dtype=np.uint32).copy()
+
+
+class KeyArray:
+    """pmk_key structs for a list of key objects with int fields
+    (bits, n, n0inv, rr, e, p, q, dp, dq, qinv); keeps the limb arrays alive."""
+
+    def __init__(self, keys: Sequence):
+        self.count = len(keys)
+        self.arr = (pmk_key * max(1, self.count))()
+        self._keep: List[np.ndarray] = []
+        for i, k in enumerate(keys):
+            bits = int(k.bits)
+            s, sh = bits // 32, bits // 64
+            el = 1 if int(k.e) < (1 << 32) else 2
+            fields = {"n": _limbs(k.n, s), "rr": _limbs(k.rr, s), "e": _limbs(k.e, el),
+                      "p": _limbs(k.p, sh), "q": _limbs(k.q, sh), "dp": _limbs(k.dp, sh),
+                      "dq": _limbs(k.dq, sh), "qinv": _limbs(k.qinv, sh)}
+            st = self.arr[i]
+            st.bits = bits
+            st.n0inv = int(k.n0inv)
+            st.e_limbs = el
+            for f, a in fields.items():
+                self._keep.append(a)
+                setattr(st, f, a.ctypes.data_as(U32P))
+
+    def ptr(self):
+        return self.arr
+
+
+def _map_array(key_map) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(key_map, dtype=np.uint32))
+
+
+def _dev_ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _stream(s) -> Optional[int]:
+    if s is None:
+        import torch
+
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(s, int):
+        return s
+    return int(s.cuda_stream)
+
+
+def _check(rc: int, ctx=None):
+    if rc != PMK_OK:
+        msg = pmk_last_error(ctx) if ctx else ""
+        raise PmkError(rc, msg)
+
+
+# ---------- the C ABI, one function each -------------------------------------------------
+
+def pmk_create(device: int = 0) -> int:
+    h = C.c_void_p()
+    _check(load_library().pmk_create(int(device), C.byref(h)))
+    return h.value
+
+
+def pmk_destroy(ctx: int) -> None:
+    load_library().pmk_destroy(ctx)
+
+
+def pmk_last_error(ctx: int) -> str:
+    r = load_library().pmk_last_error(ctx)
+    return r.decode() if r else ""
+
+
+def pmk_keys_load(ctx: int, keys: Sequence) -> None:
+    ka = keys if isinstance(keys, KeyArray) else KeyArray(keys)
+    _check(load_library().pmk_keys_load(ctx, ka.ptr(), ka.count), ctx)
+
+
+def pmk_key_check(key) -> Tuple[int, str]:
+    ka = KeyArray([key])
+    buf = C.create_string_buffer(256)
+    rc = load_library().pmk_key_check(ka.ptr(), buf, 256)
+    return rc, buf.value.decode()
+
+
+def pmk_plan_validate(key_bits: Sequence[int], key_map, msg_len: int) -> Tuple[int, int]:
+    kb = np.ascontiguousarray(np.asarray(key_bits, dtype=np.uint32))
+    km = _map_array(key_map)
+    out = C.c_uint64(0)
+    rc = load_library().pmk_plan_validate(kb.ctypes.data_as(U32P), len(kb), km.ctypes.data_as(U32P),
+                                          len(km), int(msg_len), C.byref(out))
+    return rc, out.value
+
+
+def pmk_key_count(ctx: int) -> int:
+    return load_library().pmk_key_count(ctx)
+
+
+def pmk_key_bits(ctx: int, index: int) -> int:
+    return load_library().pmk_key_bits(ctx, index)
+
+
+def pmk_plan_create(ctx: int, key_map, msg_len: int) -> Tuple[int, int]:
+    km = _map_array(key_map)
+    h = C.c_void_p()
+    ct = C.c_uint64(0)
+    _check(load_library().pmk_plan_create(ctx, km.ctypes.data_as(U32P), len(km), int(msg_len),
+                                          C.byref(h), C.byref(ct)), ctx)
+    return h.value, ct.value
+
+
+def pmk_plan_destroy(plan: int) -> None:
+    load_library().pmk_plan_destroy(plan)
+
+
+def pmk_plan_info(plan: int) -> Tuple[int, int, int]:
+    a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+    _check(load_library().pmk_plan_info(plan, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def pmk_encrypt_plan(plan: int, d_msg, d_ct, stream=None, ctx: Optional[int] = None) -> None:
+    _check(load_library().pmk_encrypt_plan(plan, _dev_ptr(d_msg), _dev_ptr(d_ct), _stream(stream)), ctx)
+
+
+def pmk_decrypt_plan(plan: int, d_ct, d_msg, stream=None, ctx: Optional[int] = None) -> None:
+    _check(load_library().pmk_decrypt_plan(plan, _dev_ptr(d_ct), _dev_ptr(d_msg), _stream(stream)), ctx)
+
+
+def pmk_plan_check(plan: int, stream=None) -> int:
+    return load_library().pmk_plan_check(plan, _stream(stream))
+
+
+def pmk_encrypt(ctx: int, d_msg, msg_len: int, key_map, d_ct, ct_cap: int, stream=None) -> int:
+    km = _map_array(key_map)
+    return load_library().pmk_encrypt(ctx, _dev_ptr(d_msg), int(msg_len), km.ctypes.data_as(U32P), len(km),
+                                      _dev_ptr(d_ct), int(ct_cap), _stream(stream))
+
+
+def pmk_decrypt(ctx: int, d_ct, ct_len: int, key_map, d_msg, msg_len: int, stream=None) -> int:
+    km = _map_array(key_map)
+    return load_library().pmk_decrypt(ctx, _dev_ptr(d_ct), int(ct_len), km.ctypes.data_as(U32P), len(km),
+                                      _dev_ptr(d_msg), int(msg_len), _stream(stream))
+
+
+# ---------- a small object layer over the same calls -------------------------------------
+
+class Plan:
+    """A chunk plan (pmk_plan_create) bound to its context."""
+
+    def __init__(self, ctx: "Context", key_map, msg_len: int):
+        self.ctx = ctx
+        self.handle, self.ct_len = pmk_plan_create(ctx.handle, key_map, msg_len)
+        self.msg_len = int(msg_len)
+
+    def encrypt(self, msg, ct=None, stream=None):
+        import torch
+
+        if ct is None:
+            ct = torch.empty(max(self.ct_len, 4), dtype=torch.uint8, device=msg.device)
+        pmk_encrypt_plan(self.handle, msg, ct, stream, self.ctx.handle)
+        return ct
+
+    def decrypt(self, ct, msg=None, stream=None):
+        import torch
+
+        if msg is None:
+            msg = torch.empty(max(self.msg_len, 4), dtype=torch.uint8, device=ct.device)
+        pmk_decrypt_plan(self.handle, ct, msg, stream, self.ctx.handle)
+        return msg
+
+    def check(self, stream=None) -> int:
+        return pmk_plan_check(self.handle, stream)
+
+    def close(self):
+        if self.handle:
+            pmk_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """pmk_create / pmk_keys_load / plans on one GPU."""
+
+    def __init__(self, device: int = 0):
+        import weakref
+
+        self.handle = pmk_create(device)
+        self.device = device
+        self._plans = weakref.WeakSet()
+
+    def load_keys(self, keys: Sequence) -> None:
+        pmk_keys_load(self.handle, keys)
+
+    def plan(self, key_map, msg_len: int) -> Plan:
+        p = Plan(self, key_map, msg_len)
+        self._plans.add(p)
+        return p
+
+    def close(self):
+        for p in list(self._plans):
+            p.close()
+        if self.handle:
+            pmk_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,551 @@
+// HIP kernels of the PMKRSA hot path for gfx950 (wave64).
+//
+//   pack      chunk bytes -> 32-bit limbs in [tile][word][lane] tiles
+//             (Sec. 3.1: the message as a vector of chunk integers)
+//   encrypt   c = m^e mod N, left-to-right binary exponentiation
+//             (Sec. 1.1 step 2; Algorithm 2 in its left-to-right form)
+//   halves    m_p = c^dp mod p and m_q = c^dq mod q, fixed-window
+//             exponentiation (Sec. 2.1, equation CRT-RSA; Algorithm 2 with
+//             w-bit digits instead of bits)
+//   garner    h = qinv (m_p - m_q) mod p, m = m_q + h q (Sec. 2.1)
+//   unpack    32-bit limbs -> big-endian bytes of each block
+//
+// Every bignum operation is one lane's work (64 bignums per wavefront); the
+// Montgomery products (Sec. 3.2, Algorithm 3) are in mont.hpp.  The
+// exponentiation kernels are persistent: each 64-thread block owns a scratch
+// slot for its window table and walks tiles blockIdx.x, +gridDim.x, ...
+#include <hip/hip_runtime.h>
+
+#include "mont.hpp"
+#include "pmk_internal.hpp"
+
+namespace pmk {
+
+#define PMK_DEV __device__ __forceinline__
+
+PMK_DEV uint32_t bswap32(uint32_t x) { return __builtin_bswap32(x); }
+
+// word k (little-endian order) of the big-endian integer stored in
+// src[base .. base+len): bytes [base+len-4k-4, base+len-4k); bytes before base are 0
+PMK_DEV uint32_t be_word(const uint8_t *src, uint64_t base, int64_t len, int k) {
+    const int64_t hi = len - 4 * (int64_t)k;
+    if (hi <= 0) return 0u;
+    const int64_t lo = hi - 4;
+    if (lo >= 0 && ((base + (uint64_t)lo) & 3u) == 0)
+        return bswap32(*reinterpret_cast<const uint32_t *>(src + base + lo));
+    uint32_t w = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int64_t pos = lo + b;
+        if (pos >= 0) w |= (uint32_t)src[base + pos] << (8 * (3 - b));
+    }
+    return w;
+}
+
+// store word k (little-endian order) of a value into its big-endian byte field
+// dst[base .. base+len)
+PMK_DEV void be_store(uint8_t *dst, uint64_t base, int64_t len, int k, uint32_t w) {
+    const int64_t hi = len - 4 * (int64_t)k;
+    if (hi <= 0) return;
+    const int64_t lo = hi - 4;
+    if (lo >= 0 && ((base + (uint64_t)lo) & 3u) == 0) {
+        *reinterpret_cast<uint32_t *>(dst + base + lo) = bswap32(w);
+        return;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int64_t pos = lo + b;
+        if (pos >= 0) dst[base + pos] = (uint8_t)(w >> (8 * (3 - b)));
+    }
+}
+
+// ------------------------------------------------------------------ pack / unpack
+// One 256-thread block per tile of 64 chunks.  Reads walk each chunk's bytes in
+// order (coalesced), the tile is transposed in LDS, writes are whole rows of 64
+// lanes (coalesced).
+
+template <int S>
+__global__ __launch_bounds__(256) void pack_kernel(const uint8_t *__restrict__ src,
+                                                   const ChunkDesc *__restrict__ desc,
+                                                   const uint32_t *__restrict__ keys, int stride,
+                                                   int off_kbytes, uint32_t count,
+                                                   uint32_t *__restrict__ x32, int decrypt) {
+    __shared__ uint32_t tile[S * (kTile + 1)];
+    const uint32_t t = blockIdx.x;
+    for (int i = threadIdx.x; i < S * kTile; i += blockDim.x) {
+        const int c = i / S, k = i % S;
+        const uint32_t rank = t * kTile + c;
+        uint32_t w = 0;
+        if (rank < count) {
+            const ChunkDesc d = desc[rank];
+            if (decrypt) {
+                const int64_t kb = keys[(uint64_t)d.key * stride + off_kbytes];
+                w = be_word(src, d.ct_off, kb, k);
+            } else {
+                w = be_word(src, d.msg_off, d.msg_len, k);
+            }
+        }
+        tile[k * (kTile + 1) + c] = w;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < S * kTile; i += blockDim.x) {
+        const int k = i / kTile, lane = i % kTile;
+        x32[((uint64_t)t * S + k) * kTile + lane] = tile[k * (kTile + 1) + lane];
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void unpack_kernel(const uint32_t *__restrict__ y32,
+                                                     const ChunkDesc *__restrict__ desc,
+                                                     const uint32_t *__restrict__ keys, int stride,
+                                                     int off_kbytes, uint32_t count,
+                                                     uint8_t *__restrict__ dst, int decrypt) {
+    __shared__ uint32_t tile[S * (kTile + 1)];
+    const uint32_t t = blockIdx.x;
+    for (int i = threadIdx.x; i < S * kTile; i += blockDim.x) {
+        const int k = i / kTile, lane = i % kTile;
+        tile[k * (kTile + 1) + lane] = y32[((uint64_t)t * S + k) * kTile + lane];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < S * kTile; i += blockDim.x) {
+        const int c = i / S, k = i % S;
+        const uint32_t rank = t * kTile + c;
+        if (rank >= count) continue;
+        const ChunkDesc d = desc[rank];
+        const uint32_t w = tile[k * (kTile + 1) + c];
+        if (decrypt) {
+            be_store(dst, d.msg_off, d.msg_len, k, w);
+        } else {
+            const int64_t kb = keys[(uint64_t)d.key * stride + off_kbytes];
+            be_store(dst, d.ct_off, kb, k, w);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ helpers
+template <int NL>
+PMK_DEV void load_limbs(uint32_t (&x)[NL], const uint32_t *p) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) x[j] = p[j];
+}
+
+// Window-table entries live in global memory as [entry][group][lane] uint4,
+// one scratch slot per resident wave: lane-consecutive 16-byte accesses.
+template <int NL>
+PMK_DEV void store_entry(uint4 *tbl, uint32_t e, int lane, const uint32_t (&x)[NL]) {
+    constexpr int NG = groups_of(NL);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const uint32_t x1 = 4 * g + 1 < NL ? x[4 * g + 1] : 0u;
+        const uint32_t x2 = 4 * g + 2 < NL ? x[4 * g + 2] : 0u;
+        const uint32_t x3 = 4 * g + 3 < NL ? x[4 * g + 3] : 0u;
+        tbl[((size_t)e * NG + g) * kTile + lane] = make_uint4(x[4 * g], x1, x2, x3);
+    }
+}
+template <int NL>
+PMK_DEV void load_entry(uint32_t (&x)[NL], const uint4 *tbl, uint32_t e, int lane) {
+    constexpr int NG = groups_of(NL);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const uint4 v = tbl[((size_t)e * NG + g) * kTile + lane];
+        const uint32_t c[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (4 * g + u < NL) x[4 * g + u] = c[u];
+    }
+}
+template <int NL>
+PMK_DEV const uint4 *entry_ptr(const uint4 *tbl, uint32_t e, int lane) {
+    return tbl + (size_t)e * groups_of(NL) * kTile + lane;
+}
+
+PMK_DEV uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint32_t o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// ------------------------------------------------------------------ encryption
+// One lane per chunk: x~ = MM(x, R^2), then for the exponent bits below the top
+// one: square, and multiply by x~ where the bit is set; MM(., 1) leaves
+// Montgomery form.  Lanes whose key has a shorter exponent multiply by the
+// Montgomery one until their own top bit, so the whole wave follows one
+// schedule; a multiply step is skipped when no lane has its bit set.
+template <int CB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encrypt_kernel(
+    const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc, uint32_t count,
+    const uint32_t *__restrict__ x32, uint32_t *__restrict__ y32, uint4 *__restrict__ table) {
+    constexpr Geom G = make_geom(CB);
+    constexpr int NL = G.nlf, LB = G.lbf, S = G.S, NG = groups_of(NL);
+    __shared__ uint4 bbuf[NG * kTile];
+    const int lane = threadIdx.x;
+    uint4 *bl = bbuf + lane;
+    const uint32_t ntiles = (count + kTile - 1) / kTile;
+    uint4 *tbl = table + (size_t)blockIdx.x * 2 * NG * kTile;
+
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t rank = tile * kTile + lane;
+        const uint32_t rk = rank < count ? rank : count - 1;
+        const uint32_t *kr = keys + (size_t)desc[rk].key * G.stride;
+        uint32_t n[NL];
+        load_limbs(n, kr + G.off_nf);
+        const uint32_t n0 = kr[G.off_n0f];
+        const uint32_t e0 = kr[G.off_e], e1 = kr[G.off_e + 1];
+        const uint32_t ebits = kr[G.off_ebits];
+        const int top = (int)wave_max(ebits) - 1;  // wave-uniform
+        const uint4 *one_f = reinterpret_cast<const uint4 *>(kr + G.off_onef);
+
+        uint32_t acc[NL];
+        {
+            uint32_t w[S];
+#pragma unroll
+            for (int k = 0; k < S; ++k) w[k] = x32[((size_t)tile * S + k) * kTile + lane];
+#pragma unroll
+            for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j);
+        }
+        stage_global<NL>(bl, reinterpret_cast<const uint4 *>(kr + G.off_rrf), 1);
+
+        // phase 0: to Montgomery, 1: square, 2: multiply, 3: from Montgomery
+        int phase = 0, bit = top;
+        for (;;) {
+            mont_mul<NL, LB>(acc, acc, bl, n, n0);
+            if (phase == 3) break;
+            if (phase == 0) {
+                store_entry(tbl, 1, lane, acc);  // x~
+                if (ebits != (uint32_t)(top + 1)) load_limbs(acc, kr + G.off_onef);
+                bit = top - 1;
+                phase = bit >= 0 ? 1 : 3;
+            } else if (phase == 1) {
+                const uint32_t eb = bit >= 32 ? (e1 >> (bit - 32)) & 1u : (e0 >> bit) & 1u;
+                if (__any(eb)) {
+                    phase = 2;
+                } else {
+                    --bit;
+                    phase = bit >= 0 ? 1 : 3;
+                }
+            } else {  // phase 2 done
+                --bit;
+                phase = bit >= 0 ? 1 : 3;
+            }
+            if (phase == 1) {
+                stage_regs<NL>(bl, acc);
+            } else if (phase == 2) {
+                const uint32_t eb = bit >= 32 ? (e1 >> (bit - 32)) & 1u : (e0 >> bit) & 1u;
+                stage_global<NL>(bl, eb ? entry_ptr<NL>(tbl, 1, lane) : one_f, eb ? kTile : 1);
+            } else {
+                stage_one<NL>(bl);
+            }
+        }
+        canonicalize<NL, LB>(acc, n);
+#pragma unroll
+        for (int k = 0; k < S; ++k)
+            y32[((size_t)tile * S + k) * kTile + lane] = radix_word<NL, LB>(acc, k);
+    }
+}
+
+// ------------------------------------------------------------------ CRT halves
+// Lane l of tile t works on job j = 64 t + l: chunk rank j/2, prime p (j even) or
+// q (j odd).  Reduction and entry into Montgomery form at once:
+// x~ = MM(c_lo, R^2) + MM(c_hi, R^3) = c R mod p (below 4p), with
+// c = c_hi 2^(LB NL) + c_lo.  Table T[k] = x~^k (T[0] = R mod p), then
+// fixed windows from the top: WIN squarings and one multiply by T[digit].
+PMK_DEV uint32_t digit_of(const uint32_t *d, int SH, int k, int w) {
+    const int pos = k * w;
+    const int wd = pos >> 5, sh = pos & 31;
+    const uint32_t lo = d[wd];
+    const uint32_t hi = (wd + 1) < SH ? d[wd + 1] : 0u;
+    return (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & ((1u << w) - 1u);
+}
+
+template <int CB, int WIN>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void halves_kernel(
+    const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc, uint32_t count,
+    const uint32_t *__restrict__ x32, uint32_t *__restrict__ half, uint4 *__restrict__ table,
+    uint32_t *__restrict__ err) {
+    constexpr Geom G = make_geom(CB);
+    constexpr int NL = G.nlh, LB = G.lbh, S = G.S, SH = G.SH, NG = groups_of(NL);
+    constexpr int T = 1 << WIN;
+    constexpr int NW = (32 * SH + WIN - 1) / WIN;  // digits of the exponent
+    __shared__ uint4 bbuf[NG * kTile];
+    const int lane = threadIdx.x;
+    uint4 *bl = bbuf + lane;
+    const uint32_t njobs = 2 * count;
+    const uint32_t ntiles = (njobs + kTile - 1) / kTile;
+    uint4 *tbl = table + (size_t)blockIdx.x * T * NG * kTile;
+
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t job = tile * kTile + lane;
+        const uint32_t rank = job >> 1;
+        const int h = job & 1;
+        const uint32_t rk = rank < count ? rank : count - 1;
+        const uint32_t *kr = keys + (size_t)desc[rk].key * G.stride;
+        const uint32_t *hr = kr + G.off_half[0] + h * G.h_size;
+        uint32_t n[NL];
+        load_limbs(n, hr + G.h_m);
+        const uint32_t n0 = hr[G.h_m0];
+        const uint32_t *dexp = hr + G.h_d;
+        const uint4 *one_h = reinterpret_cast<const uint4 *>(hr + G.h_one);
+        const uint32_t *src = x32 + ((size_t)(rk / kTile) * S) * kTile + (rk % kTile);
+
+        uint32_t acc[NL];
+        {
+            uint32_t w[S];
+#pragma unroll
+            for (int k = 0; k < S; ++k) w[k] = src[(size_t)k * kTile];
+            if (h == 0 && rank < count) {
+                // C must lie in Z_N: compare with N, most significant word first
+                const uint32_t *n32 = kr + G.off_n32;
+                int cmp = 0;
+#pragma unroll
+                for (int k = S - 1; k >= 0; --k)
+                    if (cmp == 0 && w[k] != n32[k]) cmp = w[k] > n32[k] ? 1 : -1;
+                if (cmp >= 0) atomicOr(err, 1u);
+            }
+#pragma unroll
+            for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j + NL);
+            store_entry(tbl, 0, lane, acc);  // c_hi until step 1 (entry 0 is never read as T[0])
+#pragma unroll
+            for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j);
+        }
+        stage_global<NL>(bl, reinterpret_cast<const uint4 *>(hr + G.h_rr), 1);
+
+        // step 0 = MM(c_lo, R^2), 1 = MM(c_hi, R^3), 2..T-1 = table entries,
+        // then NW-1 digits of (WIN squarings + 1 multiply), then MM(., 1)
+        int step = 0, digit = NW - 1, sq = 0;
+        bool done = false;
+        for (;;) {
+            mont_mul<NL, LB>(acc, acc, bl, n, n0);
+            if (done) break;
+            if (step == 0) {
+                store_entry(tbl, 1, lane, acc);
+                load_entry(acc, tbl, 0, lane);  // c_hi, parked in the unused entry 0
+                stage_global<NL>(bl, reinterpret_cast<const uint4 *>(hr + G.h_rrr), 1);
+                step = 1;
+                continue;
+            }
+            if (step == 1) {
+                // x~ = acc + T[1] (both below 2p; the sum stays below 4p < R)
+                uint32_t lo[NL];
+                load_entry(lo, tbl, 1, lane);
+                uint32_t c = 0;
+#pragma unroll
+                for (int j = 0; j < NL; ++j) {
+                    const uint32_t v = acc[j] + lo[j] + c;
+                    acc[j] = v & Radix<LB>::MASK;
+                    c = v >> LB;
+                }
+                store_entry(tbl, 1, lane, acc);
+                stage_regs<NL>(bl, acc);  // x~ stays staged for the whole table build
+                step = 2;
+                if (T > 2) continue;
+            } else if (step < T) {
+                store_entry(tbl, step, lane, acc);
+                ++step;
+                if (step < T) continue;  // multiplier x~ still staged
+            }
+            if (step == T) {
+                // all entries written: start from the top digit
+                ++step;
+                const uint32_t dg = digit_of(dexp, SH, digit, WIN);
+                if (dg == 0)
+                    load_limbs(acc, hr + G.h_one);
+                else
+                    load_entry(acc, tbl, dg, lane);
+                --digit;
+                sq = 0;
+            } else if (sq == WIN + 1) {
+                // the multiply of the current digit is done: next digit
+                --digit;
+                sq = 0;
+            }
+            if (digit < 0) {
+                stage_one<NL>(bl);
+                done = true;
+            } else if (sq < WIN) {
+                stage_regs<NL>(bl, acc);
+                ++sq;
+            } else {
+                const uint32_t dg = digit_of(dexp, SH, digit, WIN);
+                stage_global<NL>(bl, dg ? entry_ptr<NL>(tbl, dg, lane) : one_h, dg ? kTile : 1);
+                sq = WIN + 1;  // multiply issued
+            }
+        }
+        canonicalize<NL, LB>(acc, n);
+        uint32_t *dst = half + ((size_t)tile * NL) * kTile + lane;
+#pragma unroll
+        for (int j = 0; j < NL; ++j) dst[(size_t)j * kTile] = acc[j];
+    }
+}
+
+// ------------------------------------------------------------------ Garner
+// One lane per chunk: h = MM(m_p + p - m_q, qinv R mod p) = qinv (m_p - m_q) mod p,
+// canonical; m = m_q + h q by schoolbook columns.
+template <int CB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void garner_kernel(
+    const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc, uint32_t count,
+    const uint32_t *__restrict__ half, uint32_t *__restrict__ y32) {
+    constexpr Geom G = make_geom(CB);
+    constexpr int NL = G.nlh, LB = G.lbh, S = G.S, NG = groups_of(NL);
+    constexpr uint32_t MASK = Radix<LB>::MASK;
+    __shared__ uint4 bbuf[NG * kTile];
+    uint4 *bl = bbuf + threadIdx.x;
+    const uint32_t rank = blockIdx.x * kTile + threadIdx.x;
+    const uint32_t rk = rank < count ? rank : count - 1;
+    const uint32_t *kr = keys + (size_t)desc[rk].key * G.stride;
+    const uint32_t *hp = kr + G.off_half[0];
+    const uint32_t *hq = kr + G.off_half[1];
+    const uint32_t jp = 2 * rk, jq = 2 * rk + 1;
+    const uint32_t *mp_src = half + ((size_t)(jp / kTile) * NL) * kTile + (jp % kTile);
+    const uint32_t *mq_src = half + ((size_t)(jq / kTile) * NL) * kTile + (jq % kTile);
+
+    uint32_t p[NL], mq[NL], a[NL];
+    load_limbs(p, hp + G.h_m);
+#pragma unroll
+    for (int j = 0; j < NL; ++j) mq[j] = mq_src[(size_t)j * kTile];
+    {
+        // a = m_p + p - m_q, in (0, 2p): limb-wise with signed carries
+        int32_t c = 0;
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+            const int32_t v = (int32_t)mp_src[(size_t)j * kTile] + (int32_t)p[j] - (int32_t)mq[j] + c;
+            a[j] = (uint32_t)v & MASK;
+            c = v >> LB;  // arithmetic shift: -1, 0 or 1
+        }
+    }
+    stage_global<NL>(bl, reinterpret_cast<const uint4 *>(kr + G.off_qinvr), 1);
+    mont_mul<NL, LB>(a, a, bl, p, hp[G.h_m0]);
+    canonicalize<NL, LB>(a, p);  // h
+
+    uint32_t q[NL];
+    load_limbs(q, hq + G.h_m);
+    uint64_t col[2 * NL];
+#pragma unroll
+    for (int k = 0; k < 2 * NL; ++k) col[k] = k < NL ? mq[k] : 0u;
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+#pragma unroll
+        for (int j = 0; j < NL; ++j) col[i + j] += (uint64_t)a[i] * q[j];
+    uint32_t m[2 * NL];
+    uint64_t c = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * NL; ++k) {
+        const uint64_t v = col[k] + c;
+        m[k] = (uint32_t)v & MASK;
+        c = v >> LB;
+    }
+    if (rank < count) {
+#pragma unroll
+        for (int k = 0; k < S; ++k)
+            y32[((size_t)(rank / kTile) * S + k) * kTile + (rank % kTile)] = radix_word<2 * NL, LB>(m, k);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+namespace {
+
+template <int CB>
+constexpr int kWin = window_for(CB / 2);
+
+template <int CB>
+int occupancy_blocks(const void *fn) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64, 0) != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+template <int CB>
+uint32_t slots_for(int decrypt, int num_cus) {
+    const void *fn = decrypt ? (const void *)halves_kernel<CB, kWin<CB>> : (const void *)encrypt_kernel<CB>;
+    return (uint32_t)(occupancy_blocks<CB>(fn) * num_cus);
+}
+
+template <int CB>
+int do_pack(const ClassRun &r, const uint8_t *src, int decrypt, hipStream_t s) {
+    constexpr Geom G = make_geom(CB);
+    const uint32_t tiles = (r.count + kTile - 1) / kTile;
+    hipLaunchKernelGGL(pack_kernel<G.S>, dim3(tiles), dim3(256), 0, s, src, r.desc, r.keys, G.stride,
+                       G.off_kbytes, r.count, r.x32, decrypt);
+    return (int)hipGetLastError();
+}
+
+template <int CB>
+int do_unpack(const ClassRun &r, uint8_t *dst, int decrypt, hipStream_t s) {
+    constexpr Geom G = make_geom(CB);
+    const uint32_t tiles = (r.count + kTile - 1) / kTile;
+    hipLaunchKernelGGL(unpack_kernel<G.S>, dim3(tiles), dim3(256), 0, s, r.y32, r.desc, r.keys, G.stride,
+                       G.off_kbytes, r.count, dst, decrypt);
+    return (int)hipGetLastError();
+}
+
+template <int CB>
+int do_encrypt(const ClassRun &r, hipStream_t s) {
+    const uint32_t tiles = (r.count + kTile - 1) / kTile;
+    const uint32_t grid = tiles < r.slots_enc ? tiles : r.slots_enc;
+    hipLaunchKernelGGL(encrypt_kernel<CB>, dim3(grid), dim3(64), 0, s, r.keys, r.desc, r.count, r.x32, r.y32,
+                       reinterpret_cast<uint4 *>(r.table));
+    return (int)hipGetLastError();
+}
+
+template <int CB>
+int do_halves(const ClassRun &r, hipStream_t s) {
+    const uint32_t tiles = (2 * r.count + kTile - 1) / kTile;
+    const uint32_t grid = tiles < r.slots_dec ? tiles : r.slots_dec;
+    hipLaunchKernelGGL((halves_kernel<CB, kWin<CB>>), dim3(grid), dim3(64), 0, s, r.keys, r.desc, r.count,
+                       r.x32, r.half, reinterpret_cast<uint4 *>(r.table), r.err);
+    return (int)hipGetLastError();
+}
+
+template <int CB>
+int do_garner(const ClassRun &r, hipStream_t s) {
+    const uint32_t tiles = (r.count + kTile - 1) / kTile;
+    hipLaunchKernelGGL(garner_kernel<CB>, dim3(tiles), dim3(64), 0, s, r.keys, r.desc, r.count, r.half, r.y32);
+    return (int)hipGetLastError();
+}
+
+#define PMK_DISPATCH(cls, CALL)           \
+    switch (cls) {                        \
+        case 0: { constexpr int CB = 128; CALL; } \
+        case 1: { constexpr int CB = 256; CALL; } \
+        case 2: { constexpr int CB = 512; CALL; } \
+        case 3: { constexpr int CB = 1024; CALL; } \
+        case 4: { constexpr int CB = 2048; CALL; } \
+        default: return (int)hipErrorInvalidValue; \
+    }
+
+}  // namespace
+
+int launch_pack(const ClassRun &r, const uint8_t *src, int decrypt, void *stream) {
+    if (r.count == 0) return 0;
+    PMK_DISPATCH(r.cls, return do_pack<CB>(r, src, decrypt, (hipStream_t)stream));
+}
+int launch_unpack(const ClassRun &r, uint8_t *dst, int decrypt, void *stream) {
+    if (r.count == 0) return 0;
+    PMK_DISPATCH(r.cls, return do_unpack<CB>(r, dst, decrypt, (hipStream_t)stream));
+}
+int launch_encrypt(const ClassRun &r, void *stream) {
+    if (r.count == 0) return 0;
+    PMK_DISPATCH(r.cls, return do_encrypt<CB>(r, (hipStream_t)stream));
+}
+int launch_decrypt_halves(const ClassRun &r, void *stream) {
+    if (r.count == 0) return 0;
+    PMK_DISPATCH(r.cls, return do_halves<CB>(r, (hipStream_t)stream));
+}
+int launch_garner(const ClassRun &r, void *stream) {
+    if (r.count == 0) return 0;
+    PMK_DISPATCH(r.cls, return do_garner<CB>(r, (hipStream_t)stream));
+}
+
+uint64_t table_words_per_slot(int cls, int decrypt) {
+    const Geom g = make_geom(kClassBits[cls]);
+    if (!decrypt) return (uint64_t)2 * 4 * groups_of(g.nlf) * kTile;
+    return (uint64_t)(1u << window_for(kClassBits[cls] / 2)) * 4 * groups_of(g.nlh) * kTile;
+}
+
+uint32_t wave_slots(int cls, int decrypt, int num_cus) {
+    PMK_DISPATCH(cls, return slots_for<CB>(decrypt, num_cus));
+}
+
+}  // namespace pmk

@@ -1,0 +1,120 @@
+// Internal layout shared by the host side of the library and its kernels.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define PMK_HD __host__ __device__
+#else
+#define PMK_HD
+#endif
+
+namespace pmk {
+
+// Modulus size classes the kernels are instantiated for (kMaxClass: the
+// largest one built).  A key of `bits`
+// bits runs in the smallest class with at least that many bits: Montgomery
+// arithmetic only needs R > 4m, so a smaller modulus fits a larger class.
+constexpr int kNumClasses = 7;
+constexpr int kClassBits[kNumClasses] = {128, 256, 512, 1024, 2048, 3072, 4096};
+constexpr int kMaxClass = 4;
+
+PMK_HD constexpr int nl_for(int bits, int lb) { return (bits + 2 + lb - 1) / lb; }
+
+// Radix of the full-size modulus: 28-bit limbs keep every column sum of a
+// Montgomery product below 2^64 up to 3072 bits; 4096-bit moduli use 27 bits.
+PMK_HD constexpr int lb_full(int bits) { return bits > 3072 ? 27 : 28; }
+PMK_HD constexpr int lb_half(int bits) { return lb_full(bits / 2); }
+
+// Window width of the fixed-window exponentiation of the CRT halves.
+PMK_HD constexpr int window_for(int bits) { return bits <= 256 ? 3 : (bits <= 1024 ? 4 : 5); }
+
+// Offsets (uint32 words) of one key record of a class.
+struct Geom {
+    int bits, S, SH;
+    int lbf, nlf, lbh, nlh;
+    int ew;  // words of the public exponent
+    // full-modulus part
+    int off_n32, off_nf, off_n0f, off_rrf, off_onef, off_e, off_ebits, off_kbytes;
+    // half records (p then q): m, m0, rr, rrr, one, d
+    int off_half[2];
+    int h_m, h_m0, h_rr, h_rrr, h_one, h_d, h_size;
+    int off_qinvr;
+    int stride;
+};
+
+PMK_HD constexpr int pad4(int x) { return (x + 3) & ~3; }
+
+// Every radix-form field starts on a 16-byte boundary and is padded to a
+// multiple of 4 limbs, so kernels read it with 128-bit loads.
+PMK_HD constexpr Geom make_geom(int bits) {
+    Geom g{};
+    g.bits = bits;
+    g.S = bits / 32;
+    g.SH = bits / 64;
+    g.lbf = lb_full(bits);
+    g.nlf = nl_for(bits, g.lbf);
+    g.lbh = lb_half(bits);
+    g.nlh = nl_for(bits / 2, g.lbh);
+    g.ew = 2;
+    const int pf = pad4(g.nlf), ph = pad4(g.nlh);
+    int o = 0;
+    g.off_nf = o; o += pf;
+    g.off_rrf = o; o += pf;
+    g.off_onef = o; o += pf;
+    g.off_n32 = o; o += pad4(g.S);
+    g.off_n0f = o; o += 1;
+    g.off_e = o; o += g.ew;
+    g.off_ebits = o; o += 1;
+    g.off_kbytes = o; o += 4;
+    // half record: m, rr, rrr, one (radix form), then m0, d
+    g.h_m = 0;
+    g.h_rr = ph;
+    g.h_rrr = 2 * ph;
+    g.h_one = 3 * ph;
+    g.h_m0 = 4 * ph;
+    g.h_d = 4 * ph + 4;
+    g.h_size = pad4(4 * ph + 4 + g.SH);
+    g.off_half[0] = o; o += g.h_size;
+    g.off_half[1] = o; o += g.h_size;
+    g.off_qinvr = o; o += ph;
+    g.stride = pad4(o);
+    return g;
+}
+
+// Chunk descriptor, one per chunk, stored per class in rank order.
+struct ChunkDesc {
+    uint64_t msg_off;  // first plaintext byte of the chunk
+    uint64_t ct_off;   // first ciphertext byte of the chunk's block
+    uint32_t key;      // record index inside the class key table
+    uint32_t msg_len;  // plaintext bytes of this chunk (kb - 4, or the remainder)
+};
+
+constexpr int kTile = 64;  // bignums per wavefront
+
+// Arguments of one class's launches inside a plan.
+struct ClassRun {
+    int cls;                   // index into kClassBits
+    uint32_t count;            // chunks of this class
+    const uint32_t *keys;      // class key table (device), Geom::stride words per key
+    const ChunkDesc *desc;     // count descriptors (device)
+    uint32_t *x32;             // ceil(count/64) * S * 64 words: packed input limbs
+    uint32_t *y32;             // same shape: result limbs before unpacking
+    uint32_t *half;            // ceil(2 count/64) * nlh * 64 words: CRT half results
+    uint32_t *table;           // per resident wave: window table scratch
+    uint32_t slots_enc;        // wave slots in `table` for the encryption kernel
+    uint32_t slots_dec;        // wave slots in `table` for the CRT-halves kernel
+    uint32_t *err;             // device error word
+};
+
+// Launchers (kernels.hip).  All asynchronous on `stream`; return hipError_t as int.
+int launch_pack(const ClassRun &r, const uint8_t *src, int decrypt, void *stream);
+int launch_encrypt(const ClassRun &r, void *stream);
+int launch_decrypt_halves(const ClassRun &r, void *stream);
+int launch_garner(const ClassRun &r, void *stream);
+int launch_unpack(const ClassRun &r, uint8_t *dst, int decrypt, void *stream);
+// table words needed per wave slot for a class
+uint64_t table_words_per_slot(int cls, int decrypt);
+// resident wave slots the persistent kernels of a class use
+uint32_t wave_slots(int cls, int decrypt, int num_cus);
+
+}  // namespace pmk

@@ -1,0 +1,225 @@
+"""GPU parity: the HIP path against the CPU oracle, byte for byte.
+
+Every comparison is exact (integer arithmetic: tolerance 0).  Sizes span
+several 64-chunk tiles per size class plus a ragged last tile; the 100 MiB
+workload is checked on sampled chunks against the oracle and in full through
+the decrypt(encrypt(m)) = m identity (Sec. 1.1 correctness of RSA).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2111_11924_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def dev(torch, arr):
+    a = np.ascontiguousarray(arr, dtype=np.uint8)
+    t = torch.empty(max(len(a), 4), dtype=torch.uint8, device="cuda")
+    if len(a):
+        t[: len(a)].copy_(torch.from_numpy(a))
+    return t
+
+
+def host(t, n):
+    return t[:n].cpu().numpy()
+
+
+def gpu_roundtrip(torch, ctx, keys, msg, km):
+    """(ciphertext, decrypted) from the GPU, decrypting the GPU's own ciphertext."""
+    print(f"[gpu] {len(keys)} keys, {len(msg)} bytes, {len(km)} chunks", flush=True)
+    ctx.load_keys(keys)
+    plan = ctx.plan(km, len(msg))
+    try:
+        d_msg = dev(torch, msg)
+        d_ct = plan.encrypt(d_msg)
+        assert plan.check() == binding.PMK_OK
+        ct = host(d_ct, plan.ct_len)
+        d_pt = plan.decrypt(d_ct)
+        assert plan.check() == binding.PMK_OK
+        pt = host(d_pt, len(msg))
+    finally:
+        plan.close()
+    return ct, pt
+
+
+def check_against_oracle(torch, ctx, keys, msg, km):
+    T = oracle.KeyTable(keys)
+    ct, pt = gpu_roundtrip(torch, ctx, keys, msg, km)
+    ref_ct = oracle.encrypt(T, msg, km)
+    assert len(ct) == len(ref_ct)
+    bad = np.nonzero(ct != ref_ct)[0]
+    assert len(bad) == 0, f"ciphertext differs at byte {bad[0]} ({len(bad)} bytes)"
+    ref_pt, rc = oracle.decrypt(T, ref_ct, len(msg), km, crt=True)
+    assert rc == 0 and (ref_pt == msg).all()
+    bad = np.nonzero(pt != msg)[0]
+    assert len(bad) == 0, f"plaintext differs at byte {bad[0]} ({len(bad)} bytes)"
+
+
+def test_config1_small_512bit(torch, ctx):
+    w = inputs.config(1)
+    check_against_oracle(torch, ctx, w.keys(), w.message(), w.key_map())
+
+
+@pytest.mark.parametrize("bits", [128, 256, 512, 1024, 2048])
+def test_each_size_class_several_tiles_ragged(torch, ctx, bits):
+    keys = inputs.make_keys([bits] * 5, 700 + bits)
+    kb = bits // 8
+    nch = 64 * 3 + 17  # three full tiles and a ragged one
+    msg_len = (nch - 1) * (kb - 4) + 3  # last chunk: 3 bytes
+    msg = inputs.make_message(msg_len, bits)
+    km = inputs.round_robin_map(msg_len, [bits] * 5)
+    assert len(km) == nch
+    check_against_oracle(torch, ctx, keys, msg, km)
+
+
+def test_mixed_sizes_random_map(torch, ctx):
+    # sizes that are not class sizes run in the next class up
+    bits = [128, 512, 2048, 256, 1024, 768, 192, 1536, 384, 2048]
+    keys = inputs.make_keys(bits, 801)
+    msg = inputs.make_message(150_000 + 7, 801)
+    km = inputs.random_map(len(msg), bits, 801)
+    check_against_oracle(torch, ctx, keys, msg, km)
+
+
+def test_special_chunk_values(torch, ctx):
+    bits = [512, 1024]
+    keys = inputs.make_keys(bits, 802)
+    caps = [b // 8 - 4 for b in bits]
+    parts = [
+        np.zeros(caps[0], np.uint8),                                   # m = 0
+        np.concatenate([np.zeros(caps[1] - 1, np.uint8), [1]]),        # m = 1
+        np.full(caps[0], 0xFF, np.uint8),                              # largest chunk value
+        np.concatenate([np.zeros(caps[1] - 2, np.uint8), [1, 0]]),     # leading zero bytes
+        np.concatenate([[0x80], np.zeros(caps[0] - 1, np.uint8)]),
+        np.array([7], np.uint8),                                       # 1-byte last chunk
+    ]
+    msg = np.concatenate(parts).astype(np.uint8)
+    km = np.array([0, 1, 0, 1, 0, 1], np.uint32)
+    T = oracle.KeyTable(keys)
+    ct, pt = gpu_roundtrip(torch, ctx, keys, msg, km)
+    assert (ct == oracle.encrypt(T, msg, km)).all()
+    assert (pt == msg).all()
+    # m = 0 and m = 1 are fixed points
+    assert not ct[:64].any()
+    assert ct[64:192].tolist() == [0] * 127 + [1]
+
+
+def test_decrypt_of_zero_and_one_blocks(torch, ctx):
+    keys = inputs.make_keys([1024], 803)
+    msg_len = 2 * 124
+    km = np.zeros(2, np.uint32)
+    ct = np.zeros(256, np.uint8)
+    ct[255] = 1  # block 0 = 0, block 1 = 1
+    ctx.load_keys(keys)
+    plan = ctx.plan(km, msg_len)
+    try:
+        d_pt = plan.decrypt(dev(torch, ct))
+        assert plan.check() == binding.PMK_OK
+        pt = host(d_pt, msg_len)
+    finally:
+        plan.close()
+    ref, rc = oracle.decrypt(oracle.KeyTable(keys), ct, msg_len, km)
+    assert rc == 0 and (pt == ref).all()
+    assert not pt[:124].any() and pt[124:].tolist() == [0] * 123 + [1]
+
+
+def test_block_not_below_modulus_is_reported(torch, ctx):
+    keys = inputs.make_keys([512, 512], 804)
+    msg = inputs.make_message(600, 804)
+    km = inputs.round_robin_map(600, [512, 512])
+    T = oracle.KeyTable(keys)
+    ct = oracle.encrypt(T, msg, km)
+    bad = ct.copy()
+    bad[64:128] = np.frombuffer(keys[1].n.to_bytes(64, "big"), np.uint8)  # block 1 = N
+    ctx.load_keys(keys)
+    plan = ctx.plan(km, len(msg))
+    try:
+        d_pt = plan.decrypt(dev(torch, bad))
+        assert plan.check() == binding.PMK_ERANGE
+        pt = host(d_pt, len(msg))
+        assert plan.check() == binding.PMK_OK  # the flag was cleared
+    finally:
+        plan.close()
+    assert (pt[:60] == msg[:60]).all() and (pt[120:] == msg[120:]).all()
+
+
+def test_empty_message(torch, ctx):
+    keys = inputs.make_keys([512], 805)
+    ctx.load_keys(keys)
+    plan = ctx.plan(np.zeros(0, np.uint32), 0)
+    try:
+        assert plan.ct_len == 0
+        buf = torch.zeros(4, dtype=torch.uint8, device="cuda")
+        plan.encrypt(buf, buf)
+        plan.decrypt(buf, buf)
+        assert plan.check() == binding.PMK_OK
+    finally:
+        plan.close()
+
+
+def test_one_shot_entry_points_and_errors(torch, ctx):
+    keys = inputs.make_keys([1024, 1024], 806)
+    msg = inputs.make_message(1000, 806)
+    km = inputs.round_robin_map(1000, [1024, 1024])
+    ctx.load_keys(keys)
+    d_msg = dev(torch, msg)
+    ct_len = 128 * len(km)
+    d_ct = torch.empty(ct_len, dtype=torch.uint8, device="cuda")
+    assert binding.pmk_encrypt(ctx.handle, d_msg, len(msg), km, d_ct, ct_len) == binding.PMK_OK
+    assert binding.pmk_encrypt(ctx.handle, d_msg, len(msg), km, d_ct, ct_len - 1) == binding.PMK_ESIZE
+    assert binding.pmk_encrypt(ctx.handle, d_msg, len(msg), km[:-1], d_ct, ct_len) == binding.PMK_ESIZE
+    bad = km.copy()
+    bad[0] = 9
+    assert binding.pmk_encrypt(ctx.handle, d_msg, len(msg), bad, d_ct, ct_len) == binding.PMK_EKEY
+    d_pt = torch.empty(len(msg), dtype=torch.uint8, device="cuda")
+    assert binding.pmk_decrypt(ctx.handle, d_ct, ct_len, km, d_pt, len(msg)) == binding.PMK_OK
+    assert (host(d_pt, len(msg)) == msg).all()
+    assert (host(d_ct, ct_len) == oracle.encrypt(oracle.KeyTable(keys), msg, km)).all()
+    # replacing keys while a plan is alive is refused
+    plan = ctx.plan(km, len(msg))
+    with pytest.raises(binding.PmkError) as ei:
+        ctx.load_keys(keys)
+    assert ei.value.status == binding.PMK_EBUSY
+    plan.close()
+    ctx.load_keys(keys)
+
+
+def test_config2_1MiB_2048bit(torch, ctx):
+    w = inputs.config(2)
+    check_against_oracle(torch, ctx, w.keys(), w.message(), w.key_map())
+
+
+def test_config4_100MiB_sampled_and_roundtrip(torch, ctx):
+    w = inputs.config(4)
+    keys, msg, km = w.keys(), w.message(), w.key_map()
+    assert len(km) == 416_102
+    ct, pt = gpu_roundtrip(torch, ctx, keys, msg, km)
+    bad = np.nonzero(pt != msg)[0]
+    assert len(bad) == 0, f"roundtrip differs at byte {bad[0]}"
+    T = oracle.KeyTable(keys)
+    rng = np.random.default_rng(4)
+    sample = np.unique(np.concatenate([rng.choice(len(km), 200, replace=False), [0, 1, len(km) - 1]]))
+    for i in sample.tolist():
+        k = int(km[i])
+        lo = i * 252
+        m = int.from_bytes(bytes(msg[lo:lo + 252]), "big")
+        c = oracle.rsa_int(T, k, "enc", m)
+        assert bytes(ct[i * 256:(i + 1) * 256]) == c.to_bytes(256, "big"), i
+        assert oracle.rsa_int(T, k, "crt", c) == m
