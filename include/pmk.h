@@ -159,6 +159,25 @@ int pmk_decrypt_plan(pmk_plan *plan, const uint8_t *d_ct, uint8_t *d_msg, void *
 int pmk_plan_check(pmk_plan *plan, void *stream);
 
 /*
+ * Kernel timing (profiling aid).  pmk_plan_profile(plan, 1) waits for the
+ * device, forgets earlier timings and from then on brackets every kernel the
+ * plan launches with HIP events recorded on the launch stream;
+ * pmk_plan_profile(plan, 0) stops.  pmk_plan_kernel_time sums, over the
+ * recorded launches of one kernel kind, the event-measured durations in
+ * milliseconds (waiting for them to complete) and their count.
+ */
+enum {
+    PMK_KERNEL_PACK = 0,       /* bytes -> limbs */
+    PMK_KERNEL_ENCRYPT = 1,    /* c = m^e mod N */
+    PMK_KERNEL_CRT_HALVES = 2, /* m_p = c^dp mod p, m_q = c^dq mod q */
+    PMK_KERNEL_GARNER = 3,     /* CRT recombination */
+    PMK_KERNEL_UNPACK = 4,     /* limbs -> bytes */
+    PMK_KERNEL_KINDS = 5
+};
+int pmk_plan_profile(pmk_plan *plan, int enable);
+int pmk_plan_kernel_time(pmk_plan *plan, int kind, double *ms_total, uint64_t *launches);
+
+/*
  * One-shot forms: plan, run, check and free in one call; synchronous on
  * `stream`.  key_map is host memory; d_msg / d_ct are device memory.
  * ct_cap / msg_len are checked against the plan (PMK_ESIZE).

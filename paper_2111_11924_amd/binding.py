@@ -27,6 +27,13 @@ PMK_EDEVICE = -6
 PMK_EBUSY = -7
 PMK_EUNSUPPORTED = -8
 
+PMK_KERNEL_PACK = 0
+PMK_KERNEL_ENCRYPT = 1
+PMK_KERNEL_CRT_HALVES = 2
+PMK_KERNEL_GARNER = 3
+PMK_KERNEL_UNPACK = 4
+KERNEL_NAMES = {0: "pack", 1: "encrypt", 2: "crt_halves", 3: "garner", 4: "unpack"}
+
 STATUS_NAMES = {0: "PMK_OK", -1: "PMK_EINVAL", -2: "PMK_EKEY", -3: "PMK_ERANGE", -4: "PMK_ESIZE",
                 -5: "PMK_ENOMEM", -6: "PMK_EDEVICE", -7: "PMK_EBUSY", -8: "PMK_EUNSUPPORTED"}
 
@@ -74,6 +81,8 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "pmk_encrypt_plan": (C.c_int, [vp, vp, vp, vp]),
         "pmk_decrypt_plan": (C.c_int, [vp, vp, vp, vp]),
         "pmk_plan_check": (C.c_int, [vp, vp]),
+        "pmk_plan_profile": (C.c_int, [vp, C.c_int]),
+        "pmk_plan_kernel_time": (C.c_int, [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(u64)]),
         "pmk_encrypt": (C.c_int, [vp, vp, u64, U32P, u64, vp, u64, vp]),
         "pmk_decrypt": (C.c_int, [vp, vp, u64, U32P, u64, vp, u64, vp]),
     }
@@ -226,6 +235,16 @@ def pmk_plan_check(plan: int, stream=None) -> int:
     return load_library().pmk_plan_check(plan, _stream(stream))
 
 
+def pmk_plan_profile(plan: int, enable: bool) -> None:
+    _check(load_library().pmk_plan_profile(plan, 1 if enable else 0))
+
+
+def pmk_plan_kernel_time(plan: int, kind: int) -> Tuple[float, int]:
+    ms, n = C.c_double(0.0), C.c_uint64(0)
+    _check(load_library().pmk_plan_kernel_time(plan, int(kind), C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
 def pmk_encrypt(ctx: int, d_msg, msg_len: int, key_map, d_ct, ct_cap: int, stream=None) -> int:
     km = _map_array(key_map)
     return load_library().pmk_encrypt(ctx, _dev_ptr(d_msg), int(msg_len), km.ctypes.data_as(U32P), len(km),
@@ -266,6 +285,13 @@ class Plan:
 
     def check(self, stream=None) -> int:
         return pmk_plan_check(self.handle, stream)
+
+    def profile(self, enable: bool = True) -> None:
+        pmk_plan_profile(self.handle, enable)
+
+    def kernel_time(self, kind: int) -> Tuple[float, int]:
+        """(total ms, launches) of one kernel kind since profiling was switched on."""
+        return pmk_plan_kernel_time(self.handle, kind)
 
     def close(self):
         if self.handle:

@@ -34,12 +34,19 @@ struct pmk_ctx {
     std::set<pmk_plan *> plans;
 };
 
+struct TimedLaunch {
+    int kind;
+    hipEvent_t start, stop;
+};
+
 struct pmk_plan {
     pmk_ctx *ctx = nullptr;
     uint64_t msg_len = 0, nchunks = 0, ct_len = 0;
     ClassRun runs[kNumClasses] = {};
     std::vector<void *> allocs;
     uint32_t *d_err = nullptr;
+    bool profile = false;
+    std::vector<TimedLaunch> timed;
 };
 
 namespace {
@@ -70,9 +77,35 @@ hipError_t dev_alloc(pmk_plan *pl, T **p, size_t bytes) {
     return e;
 }
 
+void drop_timings(pmk_plan *pl) {
+    for (auto &t : pl->timed) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    pl->timed.clear();
+}
+
 void free_plan_memory(pmk_plan *pl) {
+    drop_timings(pl);
     for (void *p : pl->allocs) (void)hipFree(p);
     pl->allocs.clear();
+}
+
+// Runs one launcher; with profiling on, brackets it with events on `stream`.
+template <typename F>
+int timed_launch(pmk_plan *pl, int kind, void *stream, F launch) {
+    if (!pl->profile) return launch();
+    TimedLaunch t{kind, nullptr, nullptr};
+    if (hipEventCreate(&t.start) != hipSuccess) return (int)hipErrorOutOfMemory;
+    if (hipEventCreate(&t.stop) != hipSuccess) {
+        (void)hipEventDestroy(t.start);
+        return (int)hipErrorOutOfMemory;
+    }
+    (void)hipEventRecord(t.start, (hipStream_t)stream);
+    const int e = launch();
+    (void)hipEventRecord(t.stop, (hipStream_t)stream);
+    pl->timed.push_back(t);
+    return e;
 }
 
 // Host-side chunk planning shared by pmk_plan_create and pmk_plan_validate.
@@ -320,9 +353,9 @@ int pmk_encrypt_plan(pmk_plan *pl, const uint8_t *d_msg, uint8_t *d_ct, void *st
     for (int c = 0; c < kNumClasses; ++c) {
         const ClassRun &r = pl->runs[c];
         if (!r.count) continue;
-        int e = launch_pack(r, d_msg, 0, stream);
-        if (!e) e = launch_encrypt(r, stream);
-        if (!e) e = launch_unpack(r, d_ct, 0, stream);
+        int e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(r, d_msg, 0, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_ENCRYPT, stream, [&] { return launch_encrypt(r, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, d_ct, 0, stream); });
         if (e) return hip_err(ctx, (hipError_t)e, "encrypt launch");
     }
     return PMK_OK;
@@ -338,12 +371,39 @@ int pmk_decrypt_plan(pmk_plan *pl, const uint8_t *d_ct, uint8_t *d_msg, void *st
     for (int c = 0; c < kNumClasses; ++c) {
         const ClassRun &r = pl->runs[c];
         if (!r.count) continue;
-        int e = launch_pack(r, d_ct, 1, stream);
-        if (!e) e = launch_decrypt_halves(r, stream);
-        if (!e) e = launch_garner(r, stream);
-        if (!e) e = launch_unpack(r, d_msg, 1, stream);
+        int e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(r, d_ct, 1, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_CRT_HALVES, stream, [&] { return launch_decrypt_halves(r, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_GARNER, stream, [&] { return launch_garner(r, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, d_msg, 1, stream); });
         if (e) return hip_err(ctx, (hipError_t)e, "decrypt launch");
     }
+    return PMK_OK;
+}
+
+int pmk_plan_profile(pmk_plan *pl, int enable) {
+    if (!pl) return PMK_EINVAL;
+    (void)hipSetDevice(pl->ctx->device);
+    (void)hipDeviceSynchronize();
+    drop_timings(pl);
+    pl->profile = enable != 0;
+    return PMK_OK;
+}
+
+int pmk_plan_kernel_time(pmk_plan *pl, int kind, double *ms_total, uint64_t *launches) {
+    if (!pl || kind < 0 || kind >= PMK_KERNEL_KINDS) return PMK_EINVAL;
+    double total = 0;
+    uint64_t n = 0;
+    for (auto &t : pl->timed) {
+        if (t.kind != kind) continue;
+        float ms = 0;
+        hipError_t e = hipEventSynchronize(t.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.start, t.stop);
+        if (e != hipSuccess) return hip_err(pl->ctx, e, "kernel timing");
+        total += ms;
+        ++n;
+    }
+    if (ms_total) *ms_total = total;
+    if (launches) *launches = n;
     return PMK_OK;
 }
 
