@@ -129,34 +129,38 @@ PMK_DEV void load_limbs(uint32_t (&x)[NL], const uint32_t *p) {
     for (int j = 0; j < NL; ++j) x[j] = p[j];
 }
 
-// Window-table entries live in global memory as [entry][group][lane] uint4,
-// one scratch slot per resident wave: lane-consecutive 16-byte accesses.
+// An opaque copy of a wave-uniform pointer.  Table addresses are otherwise
+// loop-invariant, and the compiler hoists all NL per-limb addresses of every
+// access out of the loops, where they occupy registers for the whole kernel;
+// through this copy they are formed at each access from the scalar base.
+template <typename T>
+PMK_DEV T *fresh(T *p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// Window-table entries live in global memory as [entry][limb][lane] words, one
+// scratch slot per resident wave: every access of a wave is 64 consecutive words.
 template <int NL>
-PMK_DEV void store_entry(uint4 *tbl, uint32_t e, int lane, const uint32_t (&x)[NL]) {
-    constexpr int NG = groups_of(NL);
+PMK_DEV void store_entry(uint32_t *tbl, uint32_t e, int lane, const uint32_t (&x)[NL]) {
+    uint32_t *t = fresh(tbl) + (size_t)e * NL * kTile + lane;
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-        const uint32_t x1 = 4 * g + 1 < NL ? x[4 * g + 1] : 0u;
-        const uint32_t x2 = 4 * g + 2 < NL ? x[4 * g + 2] : 0u;
-        const uint32_t x3 = 4 * g + 3 < NL ? x[4 * g + 3] : 0u;
-        tbl[((size_t)e * NG + g) * kTile + lane] = make_uint4(x[4 * g], x1, x2, x3);
-    }
+    for (int j = 0; j < NL; ++j) t[(size_t)j * kTile] = x[j];
 }
 template <int NL>
-PMK_DEV void load_entry(uint32_t (&x)[NL], const uint4 *tbl, uint32_t e, int lane) {
-    constexpr int NG = groups_of(NL);
+PMK_DEV void load_entry(uint32_t (&x)[NL], const uint32_t *tbl, uint32_t e, int lane) {
+    const uint32_t *t = fresh(tbl) + (size_t)e * NL * kTile + lane;
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-        const uint4 v = tbl[((size_t)e * NG + g) * kTile + lane];
-        const uint32_t c[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (4 * g + u < NL) x[4 * g + u] = c[u];
-    }
+    for (int j = 0; j < NL; ++j) x[j] = t[(size_t)j * kTile];
 }
+// x = table entry e (e > 0) or, for e = 0, the Montgomery one of the key record
 template <int NL>
-PMK_DEV const uint4 *entry_ptr(const uint4 *tbl, uint32_t e, int lane) {
-    return tbl + (size_t)e * groups_of(NL) * kTile + lane;
+PMK_DEV void load_digit(uint32_t (&x)[NL], const uint32_t *tbl, uint32_t e, int lane, const uint32_t *one) {
+    if (e) {
+        load_entry(x, tbl, e, lane);
+    } else {
+        load_limbs(x, one);
+    }
 }
 
 PMK_DEV uint32_t wave_max(uint32_t v) {
@@ -177,14 +181,12 @@ PMK_DEV uint32_t wave_max(uint32_t v) {
 template <int CB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encrypt_kernel(
     const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc, uint32_t count,
-    const uint32_t *__restrict__ x32, uint32_t *__restrict__ y32, uint4 *__restrict__ table) {
+    const uint32_t *__restrict__ x32, uint32_t *__restrict__ y32, uint32_t *__restrict__ table) {
     constexpr Geom G = make_geom(CB);
-    constexpr int NL = G.nlf, LB = G.lbf, S = G.S, NG = groups_of(NL);
-    __shared__ uint4 bbuf[NG * kTile];
+    constexpr int NL = G.nlf, LB = G.lbf, S = G.S;
     const int lane = threadIdx.x;
-    uint4 *bl = bbuf + lane;
     const uint32_t ntiles = (count + kTile - 1) / kTile;
-    uint4 *tbl = table + (size_t)blockIdx.x * 2 * NG * kTile;
+    uint32_t *tbl = table + (size_t)blockIdx.x * 2 * NL * kTile;
 
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint32_t rank = tile * kTile + lane;
@@ -196,9 +198,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
         const uint32_t e0 = kr[G.off_e], e1 = kr[G.off_e + 1];
         const uint32_t ebits = kr[G.off_ebits];
         const int top = (int)wave_max(ebits) - 1;  // wave-uniform
-        const uint4 *one_f = reinterpret_cast<const uint4 *>(kr + G.off_onef);
+        const uint32_t *one_f = kr + G.off_onef;
 
-        uint32_t acc[NL];
+        uint32_t acc[NL], b[NL];
         {
             uint32_t w[S];
 #pragma unroll
@@ -206,39 +208,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
 #pragma unroll
             for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j);
         }
-        stage_global<NL>(bl, reinterpret_cast<const uint4 *>(kr + G.off_rrf), 1);
-
-        // phase 0: to Montgomery, 1: square, 2: multiply, 3: from Montgomery
-        int phase = 0, bit = top;
-        for (;;) {
-            mont_mul<NL, LB>(acc, acc, bl, n, n0);
-            if (phase == 3) break;
-            if (phase == 0) {
-                store_entry(tbl, 1, lane, acc);  // x~
-                if (ebits != (uint32_t)(top + 1)) load_limbs(acc, kr + G.off_onef);
-                bit = top - 1;
-                phase = bit >= 0 ? 1 : 3;
-            } else if (phase == 1) {
-                const uint32_t eb = bit >= 32 ? (e1 >> (bit - 32)) & 1u : (e0 >> bit) & 1u;
-                if (__any(eb)) {
-                    phase = 2;
-                } else {
-                    --bit;
-                    phase = bit >= 0 ? 1 : 3;
-                }
-            } else {  // phase 2 done
-                --bit;
-                phase = bit >= 0 ? 1 : 3;
-            }
-            if (phase == 1) {
-                stage_regs<NL>(bl, acc);
-            } else if (phase == 2) {
-                const uint32_t eb = bit >= 32 ? (e1 >> (bit - 32)) & 1u : (e0 >> bit) & 1u;
-                stage_global<NL>(bl, eb ? entry_ptr<NL>(tbl, 1, lane) : one_f, eb ? kTile : 1);
-            } else {
-                stage_one<NL>(bl);
+        load_limbs(b, kr + G.off_rrf);
+        mont_mul<NL, LB>(acc, acc, b, n, n0);  // x~ = x R mod N
+        store_entry(tbl, 1, lane, acc);
+        if (ebits != (uint32_t)(top + 1)) load_limbs(acc, one_f);
+        for (int bit = top - 1; bit >= 0; --bit) {
+            mont_sqr<NL, LB>(acc, acc, n, n0);
+            const uint32_t eb = bit >= 32 ? (e1 >> (bit - 32)) & 1u : (e0 >> bit) & 1u;
+            if (__any(eb)) {
+                load_digit(b, tbl, eb, lane, one_f);
+                mont_mul<NL, LB>(acc, acc, b, n, n0);
             }
         }
+#pragma unroll
+        for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
+        mont_mul<NL, LB>(acc, acc, b, n, n0);  // leave Montgomery form
         canonicalize<NL, LB>(acc, n);
 #pragma unroll
         for (int k = 0; k < S; ++k)
@@ -263,18 +247,16 @@ PMK_DEV uint32_t digit_of(const uint32_t *d, int SH, int k, int w) {
 template <int CB, int WIN>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void halves_kernel(
     const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc, uint32_t count,
-    const uint32_t *__restrict__ x32, uint32_t *__restrict__ half, uint4 *__restrict__ table,
+    const uint32_t *__restrict__ x32, uint32_t *__restrict__ half, uint32_t *__restrict__ table,
     uint32_t *__restrict__ err) {
     constexpr Geom G = make_geom(CB);
-    constexpr int NL = G.nlh, LB = G.lbh, S = G.S, SH = G.SH, NG = groups_of(NL);
+    constexpr int NL = G.nlh, LB = G.lbh, S = G.S, SH = G.SH;
     constexpr int T = 1 << WIN;
     constexpr int NW = (32 * SH + WIN - 1) / WIN;  // digits of the exponent
-    __shared__ uint4 bbuf[NG * kTile];
     const int lane = threadIdx.x;
-    uint4 *bl = bbuf + lane;
     const uint32_t njobs = 2 * count;
     const uint32_t ntiles = (njobs + kTile - 1) / kTile;
-    uint4 *tbl = table + (size_t)blockIdx.x * T * NG * kTile;
+    uint32_t *tbl = table + (size_t)blockIdx.x * T * NL * kTile;
 
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint32_t job = tile * kTile + lane;
@@ -287,10 +269,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ha
         load_limbs(n, hr + G.h_m);
         const uint32_t n0 = hr[G.h_m0];
         const uint32_t *dexp = hr + G.h_d;
-        const uint4 *one_h = reinterpret_cast<const uint4 *>(hr + G.h_one);
+        const uint32_t *one_h = hr + G.h_one;
         const uint32_t *src = x32 + ((size_t)(rk / kTile) * S) * kTile + (rk % kTile);
 
-        uint32_t acc[NL];
+        uint32_t acc[NL], b[NL];
         {
             uint32_t w[S];
 #pragma unroll
@@ -306,71 +288,69 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ha
             }
 #pragma unroll
             for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j + NL);
-            store_entry(tbl, 0, lane, acc);  // c_hi until step 1 (entry 0 is never read as T[0])
+            store_entry(tbl, 0, lane, acc);  // c_hi, parked in entry 0 until it is used
 #pragma unroll
             for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j);
         }
-        stage_global<NL>(bl, reinterpret_cast<const uint4 *>(hr + G.h_rr), 1);
+        load_limbs(b, hr + G.h_rr);
 
-        // step 0 = MM(c_lo, R^2), 1 = MM(c_hi, R^3), 2..T-1 = table entries,
-        // then NW-1 digits of (WIN squarings + 1 multiply), then MM(., 1)
-        int step = 0, digit = NW - 1, sq = 0;
-        bool done = false;
+        // One call site each for the product and the square keeps the loop's
+        // code within the instruction cache.  Phases:
+        //   0  MM(c_lo, R^2) = c_lo R mod p            (parked in T[1])
+        //   1  MM(c_hi, R^3) = c_hi R^2 mod p; x~ = sum (below 4p), T[1] = x~
+        //   2  T[e] = T[e-1] x~ for e = 2 .. T-1
+        //   3  per digit below the top one: WIN squarings, then times T[digit]
+        //   4  MM(., 1): leave Montgomery form
+        int phase = 0, e = 2, digit = NW - 2, sq = 0;
         for (;;) {
-            mont_mul<NL, LB>(acc, acc, bl, n, n0);
-            if (done) break;
-            if (step == 0) {
+            if (phase == 3) {
+                if (sq < WIN) {
+                    mont_sqr<NL, LB>(acc, acc, n, n0);
+                    ++sq;
+                    continue;
+                }
+                const uint32_t dg = digit_of(dexp, SH, digit, WIN);
+                load_digit(b, tbl, dg, lane, one_h);
+            }
+            mont_mul<NL, LB>(acc, acc, b, n, n0);
+            if (phase == 4) break;
+            if (phase == 0) {
                 store_entry(tbl, 1, lane, acc);
-                load_entry(acc, tbl, 0, lane);  // c_hi, parked in the unused entry 0
-                stage_global<NL>(bl, reinterpret_cast<const uint4 *>(hr + G.h_rrr), 1);
-                step = 1;
+                load_entry(acc, tbl, 0, lane);
+                load_limbs(b, hr + G.h_rrr);
+                phase = 1;
                 continue;
             }
-            if (step == 1) {
-                // x~ = acc + T[1] (both below 2p; the sum stays below 4p < R)
-                uint32_t lo[NL];
-                load_entry(lo, tbl, 1, lane);
+            if (phase == 1) {
+                load_entry(b, tbl, 1, lane);
                 uint32_t c = 0;
 #pragma unroll
                 for (int j = 0; j < NL; ++j) {
-                    const uint32_t v = acc[j] + lo[j] + c;
+                    const uint32_t v = acc[j] + b[j] + c;
                     acc[j] = v & Radix<LB>::MASK;
                     c = v >> LB;
                 }
                 store_entry(tbl, 1, lane, acc);
-                stage_regs<NL>(bl, acc);  // x~ stays staged for the whole table build
-                step = 2;
-                if (T > 2) continue;
-            } else if (step < T) {
-                store_entry(tbl, step, lane, acc);
-                ++step;
-                if (step < T) continue;  // multiplier x~ still staged
-            }
-            if (step == T) {
-                // all entries written: start from the top digit
-                ++step;
-                const uint32_t dg = digit_of(dexp, SH, digit, WIN);
-                if (dg == 0)
-                    load_limbs(acc, hr + G.h_one);
-                else
-                    load_entry(acc, tbl, dg, lane);
-                --digit;
-                sq = 0;
-            } else if (sq == WIN + 1) {
-                // the multiply of the current digit is done: next digit
+#pragma unroll
+                for (int j = 0; j < NL; ++j) b[j] = acc[j];  // x~, the multiplier of phase 2
+                phase = 2;
+            } else if (phase == 2) {
+                store_entry(tbl, e, lane, acc);
+                ++e;
+            } else {  // phase 3: the digit's multiply is done
                 --digit;
                 sq = 0;
             }
-            if (digit < 0) {
-                stage_one<NL>(bl);
-                done = true;
-            } else if (sq < WIN) {
-                stage_regs<NL>(bl, acc);
-                ++sq;
-            } else {
-                const uint32_t dg = digit_of(dexp, SH, digit, WIN);
-                stage_global<NL>(bl, dg ? entry_ptr<NL>(tbl, dg, lane) : one_h, dg ? kTile : 1);
-                sq = WIN + 1;  // multiply issued
+            if (phase == 2 && e == T) {
+                // table complete: start from the top digit
+                const uint32_t dg = digit_of(dexp, SH, NW - 1, WIN);
+                load_digit(acc, tbl, dg, lane, one_h);
+                phase = 3;
+            }
+            if (phase == 3 && digit < 0) {
+#pragma unroll
+                for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
+                phase = 4;
             }
         }
         canonicalize<NL, LB>(acc, n);
@@ -388,10 +368,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ga
     const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc, uint32_t count,
     const uint32_t *__restrict__ half, uint32_t *__restrict__ y32) {
     constexpr Geom G = make_geom(CB);
-    constexpr int NL = G.nlh, LB = G.lbh, S = G.S, NG = groups_of(NL);
+    constexpr int NL = G.nlh, LB = G.lbh, S = G.S;
     constexpr uint32_t MASK = Radix<LB>::MASK;
-    __shared__ uint4 bbuf[NG * kTile];
-    uint4 *bl = bbuf + threadIdx.x;
     const uint32_t rank = blockIdx.x * kTile + threadIdx.x;
     const uint32_t rk = rank < count ? rank : count - 1;
     const uint32_t *kr = keys + (size_t)desc[rk].key * G.stride;
@@ -401,7 +379,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ga
     const uint32_t *mp_src = half + ((size_t)(jp / kTile) * NL) * kTile + (jp % kTile);
     const uint32_t *mq_src = half + ((size_t)(jq / kTile) * NL) * kTile + (jq % kTile);
 
-    uint32_t p[NL], mq[NL], a[NL];
+    uint32_t p[NL], mq[NL], a[NL], b[NL];
     load_limbs(p, hp + G.h_m);
 #pragma unroll
     for (int j = 0; j < NL; ++j) mq[j] = mq_src[(size_t)j * kTile];
@@ -415,26 +393,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ga
             c = v >> LB;  // arithmetic shift: -1, 0 or 1
         }
     }
-    stage_global<NL>(bl, reinterpret_cast<const uint4 *>(kr + G.off_qinvr), 1);
-    mont_mul<NL, LB>(a, a, bl, p, hp[G.h_m0]);
+    load_limbs(b, kr + G.off_qinvr);
+    mont_mul<NL, LB>(a, a, b, p, hp[G.h_m0]);
     canonicalize<NL, LB>(a, p);  // h
 
     uint32_t q[NL];
     load_limbs(q, hq + G.h_m);
-    uint64_t col[2 * NL];
-#pragma unroll
-    for (int k = 0; k < 2 * NL; ++k) col[k] = k < NL ? mq[k] : 0u;
-#pragma unroll
-    for (int i = 0; i < NL; ++i)
-#pragma unroll
-        for (int j = 0; j < NL; ++j) col[i + j] += (uint64_t)a[i] * q[j];
     uint32_t m[2 * NL];
     uint64_t c = 0;
 #pragma unroll
-    for (int k = 0; k < 2 * NL; ++k) {
-        const uint64_t v = col[k] + c;
-        m[k] = (uint32_t)v & MASK;
-        c = v >> LB;
+    for (int k = 0; k < 2 * NL; ++k) {  // m = m_q + h q, column by column
+        uint64_t acc = c + (k < NL ? mq[k] : 0u);
+#pragma unroll
+        for (int i = (k - NL + 1 > 0 ? k - NL + 1 : 0); i <= (k < NL ? k : NL - 1); ++i)
+            acc += (uint64_t)a[i] * q[k - i];
+        m[k] = (uint32_t)acc & MASK;
+        c = acc >> LB;
     }
     if (rank < count) {
 #pragma unroll
@@ -485,7 +459,7 @@ int do_encrypt(const ClassRun &r, hipStream_t s) {
     const uint32_t tiles = (r.count + kTile - 1) / kTile;
     const uint32_t grid = tiles < r.slots_enc ? tiles : r.slots_enc;
     hipLaunchKernelGGL(encrypt_kernel<CB>, dim3(grid), dim3(64), 0, s, r.keys, r.desc, r.count, r.x32, r.y32,
-                       reinterpret_cast<uint4 *>(r.table));
+                       r.table);
     return (int)hipGetLastError();
 }
 
@@ -494,7 +468,7 @@ int do_halves(const ClassRun &r, hipStream_t s) {
     const uint32_t tiles = (2 * r.count + kTile - 1) / kTile;
     const uint32_t grid = tiles < r.slots_dec ? tiles : r.slots_dec;
     hipLaunchKernelGGL((halves_kernel<CB, kWin<CB>>), dim3(grid), dim3(64), 0, s, r.keys, r.desc, r.count,
-                       r.x32, r.half, reinterpret_cast<uint4 *>(r.table), r.err);
+                       r.x32, r.half, r.table, r.err);
     return (int)hipGetLastError();
 }
 
@@ -540,8 +514,8 @@ int launch_garner(const ClassRun &r, void *stream) {
 
 uint64_t table_words_per_slot(int cls, int decrypt) {
     const Geom g = make_geom(kClassBits[cls]);
-    if (!decrypt) return (uint64_t)2 * 4 * groups_of(g.nlf) * kTile;
-    return (uint64_t)(1u << window_for(kClassBits[cls] / 2)) * 4 * groups_of(g.nlh) * kTile;
+    if (!decrypt) return (uint64_t)2 * g.nlf * kTile;
+    return (uint64_t)(1u << window_for(kClassBits[cls] / 2)) * g.nlh * kTile;
 }
 
 uint32_t wave_slots(int cls, int decrypt, int num_cus) {

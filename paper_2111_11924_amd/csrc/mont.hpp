@@ -1,14 +1,12 @@
 // Montgomery arithmetic for gfx950 in a redundant 2^LB radix (LB = 28 or 27).
 //
 // The operation is Montgomery multiplication (paper, Sec. 3.2, Algorithm 3):
-// t = a b R^-1 mod m with R = 2^(LB*NL), reached word by word (CIOS: one
-// multiplier limb b_i per step, one reduction multiple m_i = t_0 n' mod 2^LB per
-// step, then a one-limb shift).  Limbs hold LB bits in 32-bit registers and
-// every column is accumulated in 64 bits, so a partial product is exactly one
-// v_mad_u64_u32 and no carry is resolved inside the loop: with a, b, m, n
-// limbs below 2^LB a column collects at most 2*NL products below 2^(2LB), which
-// stays below 2^64 for the sizes instantiated here (checked by static_assert).
-// Carries are propagated once, after the last step.
+// t = a b R^-1 mod m with R = 2^(LB*NL), reached word by word with one
+// reduction digit m_k = t_k n' mod 2^LB per word.  Limbs hold LB bits in 32-bit
+// registers and every column is accumulated in 64 bits, so a partial product is
+// exactly one v_mad_u64_u32 and no carry flag is ever handled: a column collects
+// at most 2*NL products below 2^(2LB) plus a carry, which stays below 2^64 for
+// the sizes instantiated here (checked by static_assert).
 //
 // Lazy reduction: with 4m < R and a, b < 2m (more generally a*b < R*m) the
 // result is below 2m, so no conditional subtraction is needed between the
@@ -31,82 +29,118 @@ constexpr int limbs_for(int bits, int lb) { return (bits + 2 + lb - 1) / lb; }
 // Number of 4-limb groups of an NL-limb number (multiplier staging unit).
 constexpr int groups_of(int nl) { return (nl + 3) / 4; }
 
-// r = a * b * R^-1 mod m, result in [0, 2m) as NL normalised LB-bit limbs.
-// a: NL limbs in registers; b: staged in LDS as groups_of(NL) uint4 values,
-// group g of this lane at bl[g * 64] (bl = base + lane), limb 4g+u in
-// component u; n: modulus limbs; n0 = -m^-1 mod 2^LB.  r may alias a.
-// Bounds: every limb below 2^LB and a*b < R*m.
+// Product-scanning Montgomery multiplication (the "finely integrated product
+// scanning" order of Koc, Acar and Kaliski): column k of the double-length
+// result collects every a_i b_j and m_i n_j with i + j = k in one 64-bit
+// accumulator (one v_mad_u64_u32 each); for the low NL columns the reduction
+// digit m_k = acc n0 mod 2^LB is chosen so the column becomes a multiple of
+// 2^LB; only the carry acc >> LB moves on.  The high NL columns are the result.
+//
+// r = a * b * R^-1 mod m in [0, 2m) as NL normalised LB-bit limbs, for limbs of
+// a, b, n below 2^LB, n0 = -m^-1 mod 2^LB and a*b < R*m.  r may alias a or b:
+// limb k-NL of r is written at column k, after the last column that reads
+// limb k-NL of a or b.
 template <int NL, int LB>
 __device__ __forceinline__ void mont_mul(uint32_t (&r)[NL], const uint32_t (&a)[NL],
-                                         const uint4 *bl, const uint32_t (&n)[NL], uint32_t n0) {
-    static_assert(2.0 * NL * (double)(1ull << LB) * (double)(1ull << LB) < 18446744073709551615.0,
+                                         const uint32_t (&b)[NL], const uint32_t (&n)[NL],
+                                         uint32_t n0) {
+    static_assert((2.0 * NL + 1) * (double)(1ull << LB) * (double)(1ull << LB) < 18446744073709551615.0,
                   "column sums may overflow 64 bits");
     constexpr uint32_t MASK = Radix<LB>::MASK;
-    // keep the surrounding step logic (loads of the next operand, table stores)
-    // out of the product: mixing them in only lengthens live ranges
+    uint32_t m[NL];
+    uint64_t carry = 0;
     __builtin_amdgcn_sched_barrier(0);
-    uint64_t t[NL];
 #pragma unroll
-    for (int j = 0; j < NL; ++j) t[j] = 0;
+    for (int k = 0; k < 2 * NL - 1; ++k) {
+        const int lo = k - NL + 1 > 0 ? k - NL + 1 : 0;
+        // two interleaved accumulators halve the length of the dependent chain
+        uint64_t acc0 = carry, acc1 = 0;
+        int t = 0;
 #pragma unroll
-    for (int g = 0; g < groups_of(NL); ++g) {
-        const uint4 bq = bl[g * 64];
-        const uint32_t bg[4] = {bq.x, bq.y, bq.z, bq.w};
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (4 * g + u >= NL) break;
-            const uint32_t bi = bg[u];
-#pragma unroll
-            for (int j = 0; j < NL; ++j) t[j] += (uint64_t)a[j] * bi;
-            const uint32_t m = ((uint32_t)t[0] * n0) & MASK;
-#pragma unroll
-            for (int j = 0; j < NL; ++j) t[j] += (uint64_t)m * n[j];
-            // t[0] is now a multiple of 2^LB: divide the whole accumulator by 2^LB
-            const uint64_t c = t[0] >> LB;
-#pragma unroll
-            for (int j = 0; j < NL - 1; ++j) t[j] = t[j + 1];
-            t[NL - 1] = 0;
-            t[0] += c;
+        for (int i = lo; i <= (k < NL ? k : NL - 1); ++i, ++t) {
+            if (t & 1)
+                acc1 += (uint64_t)a[i] * b[k - i];
+            else
+                acc0 += (uint64_t)a[i] * b[k - i];
         }
-    }
-    uint64_t c = 0;
 #pragma unroll
-    for (int j = 0; j < NL; ++j) {
-        const uint64_t v = t[j] + c;
-        r[j] = (uint32_t)v & MASK;
-        c = v >> LB;
+        for (int i = lo; i < (k < NL ? k : NL); ++i, ++t) {
+            if (t & 1)
+                acc1 += (uint64_t)m[i] * n[k - i];
+            else
+                acc0 += (uint64_t)m[i] * n[k - i];
+        }
+        uint64_t acc = acc0 + acc1;
+        if (k < NL) {
+            m[k] = ((uint32_t)acc * n0) & MASK;
+            acc += (uint64_t)m[k] * n[0];  // now a multiple of 2^LB
+        } else {
+            r[k - NL] = (uint32_t)acc & MASK;
+        }
+        carry = acc >> LB;
+        // keep the schedule column by column: interleaving columns only adds
+        // live accumulators and pushes the register count past 3 waves per SIMD
+        __builtin_amdgcn_sched_barrier(0);
     }
-    __builtin_amdgcn_sched_barrier(0);
+    r[NL - 1] = (uint32_t)carry;
 }
 
-// Stage a register number as the multiplier of the next mont_mul.
+// Montgomery squaring r = a^2 R^-1 mod m, same order and bounds as mont_mul,
+// with each cross product a_i a_j (i < j) formed once and doubled: about
+// NL^2/2 fewer multiply-adds than mont_mul(a, a).
+template <int NL, int LB>
+__device__ __forceinline__ void mont_sqr(uint32_t (&r)[NL], const uint32_t (&a)[NL],
+                                         const uint32_t (&n)[NL], uint32_t n0) {
+    constexpr uint32_t MASK = Radix<LB>::MASK;
+    uint32_t m[NL];
+    uint64_t carry = 0;
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < 2 * NL - 1; ++k) {
+        const int lo = k - NL + 1 > 0 ? k - NL + 1 : 0;
+        uint64_t x0 = 0, x1 = 0;
+        int t = 0;
+#pragma unroll
+        for (int i = lo; i < k - i; ++i, ++t) {
+            if (t & 1)
+                x1 += (uint64_t)a[i] * a[k - i];
+            else
+                x0 += (uint64_t)a[i] * a[k - i];
+        }
+        uint64_t y0 = ((x0 + x1) << 1) + carry, y1 = 0;
+        if ((k & 1) == 0) y1 += (uint64_t)a[k / 2] * a[k / 2];
+        t = 0;
+#pragma unroll
+        for (int i = lo; i < (k < NL ? k : NL); ++i, ++t) {
+            if (t & 1)
+                y1 += (uint64_t)m[i] * n[k - i];
+            else
+                y0 += (uint64_t)m[i] * n[k - i];
+        }
+        uint64_t acc = y0 + y1;
+        if (k < NL) {
+            m[k] = ((uint32_t)acc * n0) & MASK;
+            acc += (uint64_t)m[k] * n[0];
+        } else {
+            r[k - NL] = (uint32_t)acc & MASK;
+        }
+        carry = acc >> LB;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    r[NL - 1] = (uint32_t)carry;
+}
+
+// Load an NL-limb number stored as groups_of(NL) uint4 values at src[g * stride].
 template <int NL>
-__device__ __forceinline__ void stage_regs(uint4 *bl, const uint32_t (&x)[NL]) {
+__device__ __forceinline__ void load_groups(uint32_t (&x)[NL], const uint4 *src, int stride) {
 #pragma unroll
     for (int g = 0; g < groups_of(NL); ++g) {
-        const uint32_t x0 = x[4 * g];
-        const uint32_t x1 = 4 * g + 1 < NL ? x[4 * g + 1] : 0u;
-        const uint32_t x2 = 4 * g + 2 < NL ? x[4 * g + 2] : 0u;
-        const uint32_t x3 = 4 * g + 3 < NL ? x[4 * g + 3] : 0u;
-        bl[g * 64] = make_uint4(x0, x1, x2, x3);
+        const uint4 v = src[(size_t)g * stride];
+        const uint32_t c[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (4 * g + u < NL) x[4 * g + u] = c[u];
     }
-}
-
-// Stage groups_of(NL) uint4 values read from global memory at src[g * stride].
-template <int NL>
-__device__ __forceinline__ void stage_global(uint4 *bl, const uint4 *src, int stride) {
-    uint4 v[groups_of(NL)];
-#pragma unroll
-    for (int g = 0; g < groups_of(NL); ++g) v[g] = src[(size_t)g * stride];
-#pragma unroll
-    for (int g = 0; g < groups_of(NL); ++g) bl[g * 64] = v[g];
-}
-
-// Stage the constant 1 (leaves Montgomery form: MM(x, 1) = x R^-1).
-template <int NL>
-__device__ __forceinline__ void stage_one(uint4 *bl) {
-#pragma unroll
-    for (int g = 0; g < groups_of(NL); ++g) bl[g * 64] = make_uint4(g == 0 ? 1u : 0u, 0u, 0u, 0u);
 }
 
 // x < 2m  ->  x mod m (canonical).  Subtract m, keep the difference when no
