@@ -11,9 +11,11 @@
 //   unpack    32-bit limbs -> big-endian bytes of each block
 //
 // Every bignum operation is one lane's work (64 bignums per wavefront); the
-// Montgomery products (Sec. 3.2, Algorithm 3) are in mont.hpp.  The
-// exponentiation kernels are persistent: each 64-thread block owns a scratch
-// slot for its window table and walks tiles blockIdx.x, +gridDim.x, ...
+// Montgomery products (Sec. 3.2, Algorithm 3) are in mont.hpp.  A tile holds up
+// to 64 chunks under one key, so modulus, exponent and window digits are
+// wave-uniform.  The exponentiation kernels are persistent: each 64-thread block
+// owns a scratch slot for its window table and walks tiles blockIdx.x,
+// +gridDim.x, ...
 #include <hip/hip_runtime.h>
 
 #include "mont.hpp"
@@ -67,58 +69,49 @@ PMK_DEV void be_store(uint8_t *dst, uint64_t base, int64_t len, int k, uint32_t 
 template <int S>
 __global__ __launch_bounds__(256) void pack_kernel(const uint8_t *__restrict__ src,
                                                    const ChunkDesc *__restrict__ desc,
-                                                   const uint32_t *__restrict__ keys, int stride,
-                                                   int off_kbytes, uint32_t count,
-                                                   uint32_t *__restrict__ x32, int decrypt) {
+                                                   const uint32_t *__restrict__ keys,
+                                                   const uint32_t *__restrict__ tile_key, int stride,
+                                                   int off_kbytes, uint32_t *__restrict__ x32, int decrypt) {
     __shared__ uint32_t tile[S * (kTile + 1)];
     const uint32_t t = blockIdx.x;
+    const int64_t kb = keys[(size_t)tile_key[t] * stride + off_kbytes];
     for (int i = threadIdx.x; i < S * kTile; i += blockDim.x) {
         const int c = i / S, k = i % S;
-        const uint32_t rank = t * kTile + c;
+        const ChunkDesc d = desc[(size_t)t * kTile + c];
         uint32_t w = 0;
-        if (rank < count) {
-            const ChunkDesc d = desc[rank];
-            if (decrypt) {
-                const int64_t kb = keys[(uint64_t)d.key * stride + off_kbytes];
-                w = be_word(src, d.ct_off, kb, k);
-            } else {
-                w = be_word(src, d.msg_off, d.msg_len, k);
-            }
-        }
+        if (d.msg_len) w = decrypt ? be_word(src, d.ct_off, kb, k) : be_word(src, d.msg_off, d.msg_len, k);
         tile[k * (kTile + 1) + c] = w;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < S * kTile; i += blockDim.x) {
         const int k = i / kTile, lane = i % kTile;
-        x32[((uint64_t)t * S + k) * kTile + lane] = tile[k * (kTile + 1) + lane];
+        x32[((size_t)t * S + k) * kTile + lane] = tile[k * (kTile + 1) + lane];
     }
 }
 
 template <int S>
 __global__ __launch_bounds__(256) void unpack_kernel(const uint32_t *__restrict__ y32,
                                                      const ChunkDesc *__restrict__ desc,
-                                                     const uint32_t *__restrict__ keys, int stride,
-                                                     int off_kbytes, uint32_t count,
-                                                     uint8_t *__restrict__ dst, int decrypt) {
+                                                     const uint32_t *__restrict__ keys,
+                                                     const uint32_t *__restrict__ tile_key, int stride,
+                                                     int off_kbytes, uint8_t *__restrict__ dst, int decrypt) {
     __shared__ uint32_t tile[S * (kTile + 1)];
     const uint32_t t = blockIdx.x;
+    const int64_t kb = keys[(size_t)tile_key[t] * stride + off_kbytes];
     for (int i = threadIdx.x; i < S * kTile; i += blockDim.x) {
         const int k = i / kTile, lane = i % kTile;
-        tile[k * (kTile + 1) + lane] = y32[((uint64_t)t * S + k) * kTile + lane];
+        tile[k * (kTile + 1) + lane] = y32[((size_t)t * S + k) * kTile + lane];
     }
     __syncthreads();
     for (int i = threadIdx.x; i < S * kTile; i += blockDim.x) {
         const int c = i / S, k = i % S;
-        const uint32_t rank = t * kTile + c;
-        if (rank >= count) continue;
-        const ChunkDesc d = desc[rank];
+        const ChunkDesc d = desc[(size_t)t * kTile + c];
+        if (!d.msg_len) continue;
         const uint32_t w = tile[k * (kTile + 1) + c];
-        if (decrypt) {
+        if (decrypt)
             be_store(dst, d.msg_off, d.msg_len, k, w);
-        } else {
-            const int64_t kb = keys[(uint64_t)d.key * stride + off_kbytes];
+        else
             be_store(dst, d.ct_off, kb, k, w);
-        }
     }
 }
 
@@ -175,30 +168,23 @@ PMK_DEV uint32_t wave_max(uint32_t v) {
 // ------------------------------------------------------------------ encryption
 // One lane per chunk: x~ = MM(x, R^2), then for the exponent bits below the top
 // one: square, and multiply by x~ where the bit is set; MM(., 1) leaves
-// Montgomery form.  Lanes whose key has a shorter exponent multiply by the
-// Montgomery one until their own top bit, so the whole wave follows one
-// schedule; a multiply step is skipped when no lane has its bit set.
+// Montgomery form.
 template <int CB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encrypt_kernel(
-    const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc, uint32_t count,
+    const uint32_t *__restrict__ keys, const uint32_t *__restrict__ tile_key, uint32_t ntiles,
     const uint32_t *__restrict__ x32, uint32_t *__restrict__ y32, uint32_t *__restrict__ table) {
     constexpr Geom G = make_geom(CB);
     constexpr int NL = G.nlf, LB = G.lbf, S = G.S;
     const int lane = threadIdx.x;
-    const uint32_t ntiles = (count + kTile - 1) / kTile;
     uint32_t *tbl = table + (size_t)blockIdx.x * 2 * NL * kTile;
 
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t rank = tile * kTile + lane;
-        const uint32_t rk = rank < count ? rank : count - 1;
-        const uint32_t *kr = keys + (size_t)desc[rk].key * G.stride;
+        const uint32_t *kr = keys + (size_t)tile_key[tile] * G.stride;  // wave-uniform
         uint32_t n[NL];
         load_limbs(n, kr + G.off_nf);
         const uint32_t n0 = kr[G.off_n0f];
         const uint32_t e0 = kr[G.off_e], e1 = kr[G.off_e + 1];
-        const uint32_t ebits = kr[G.off_ebits];
-        const int top = (int)wave_max(ebits) - 1;  // wave-uniform
-        const uint32_t *one_f = kr + G.off_onef;
+        const int top = (int)kr[G.off_ebits] - 1;
 
         uint32_t acc[NL], b[NL];
         {
@@ -211,12 +197,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
         load_limbs(b, kr + G.off_rrf);
         mont_mul<NL, LB>(acc, acc, b, n, n0);  // x~ = x R mod N
         store_entry(tbl, 1, lane, acc);
-        if (ebits != (uint32_t)(top + 1)) load_limbs(acc, one_f);
         for (int bit = top - 1; bit >= 0; --bit) {
             mont_sqr<NL, LB>(acc, acc, n, n0);
             const uint32_t eb = bit >= 32 ? (e1 >> (bit - 32)) & 1u : (e0 >> bit) & 1u;
-            if (__any(eb)) {
-                load_digit(b, tbl, eb, lane, one_f);
+            if (eb) {
+                load_entry(b, tbl, 1, lane);
                 mont_mul<NL, LB>(acc, acc, b, n, n0);
             }
         }
@@ -231,8 +216,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
 }
 
 // ------------------------------------------------------------------ CRT halves
-// Lane l of tile t works on job j = 64 t + l: chunk rank j/2, prime p (j even) or
-// q (j odd).  Reduction and entry into Montgomery form at once:
+// Job tile jt = 2 t + h works on tile t's chunks modulo p (h = 0) or q (h = 1).
+// Reduction and entry into Montgomery form at once:
 // x~ = MM(c_lo, R^2) + MM(c_hi, R^3) = c R mod p (below 4p), with
 // c = c_hi 2^(LB NL) + c_lo.  Table T[k] = x~^k (T[0] = R mod p), then
 // fixed windows from the top: WIN squarings and one multiply by T[digit].
@@ -245,45 +230,40 @@ PMK_DEV uint32_t digit_of(const uint32_t *d, int SH, int k, int w) {
 }
 
 template <int CB, int WIN>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void halves_kernel(
-    const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc, uint32_t count,
-    const uint32_t *__restrict__ x32, uint32_t *__restrict__ half, uint32_t *__restrict__ table,
-    uint32_t *__restrict__ err) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void halves_kernel(
+    const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc,
+    const uint32_t *__restrict__ tile_key, uint32_t ntiles, const uint32_t *__restrict__ x32,
+    uint32_t *__restrict__ half, uint32_t *__restrict__ table, uint32_t *__restrict__ err) {
     constexpr Geom G = make_geom(CB);
     constexpr int NL = G.nlh, LB = G.lbh, S = G.S, SH = G.SH;
     constexpr int T = 1 << WIN;
     constexpr int NW = (32 * SH + WIN - 1) / WIN;  // digits of the exponent
     const int lane = threadIdx.x;
-    const uint32_t njobs = 2 * count;
-    const uint32_t ntiles = (njobs + kTile - 1) / kTile;
+    const uint32_t njobs = 2 * ntiles;
     uint32_t *tbl = table + (size_t)blockIdx.x * T * NL * kTile;
 
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t job = tile * kTile + lane;
-        const uint32_t rank = job >> 1;
-        const int h = job & 1;
-        const uint32_t rk = rank < count ? rank : count - 1;
-        const uint32_t *kr = keys + (size_t)desc[rk].key * G.stride;
+    for (uint32_t jt = blockIdx.x; jt < njobs; jt += gridDim.x) {
+        const uint32_t tile = jt >> 1;
+        const int h = jt & 1;
+        const uint32_t *kr = keys + (size_t)tile_key[tile] * G.stride;  // wave-uniform
         const uint32_t *hr = kr + G.off_half[0] + h * G.h_size;
         uint32_t n[NL];
         load_limbs(n, hr + G.h_m);
         const uint32_t n0 = hr[G.h_m0];
         const uint32_t *dexp = hr + G.h_d;
         const uint32_t *one_h = hr + G.h_one;
-        const uint32_t *src = x32 + ((size_t)(rk / kTile) * S) * kTile + (rk % kTile);
 
         uint32_t acc[NL], b[NL];
         {
             uint32_t w[S];
 #pragma unroll
-            for (int k = 0; k < S; ++k) w[k] = src[(size_t)k * kTile];
-            if (h == 0 && rank < count) {
+            for (int k = 0; k < S; ++k) w[k] = x32[((size_t)tile * S + k) * kTile + lane];
+            if (h == 0 && desc[(size_t)tile * kTile + lane].msg_len) {
                 // C must lie in Z_N: compare with N, most significant word first
                 const uint32_t *n32 = kr + G.off_n32;
                 int cmp = 0;
 #pragma unroll
-                for (int k = S - 1; k >= 0; --k)
-                    if (cmp == 0 && w[k] != n32[k]) cmp = w[k] > n32[k] ? 1 : -1;
+                for (int k = S - 1; k >= 0; --k) cmp = cmp ? cmp : (w[k] > n32[k]) - (w[k] < n32[k]);
                 if (cmp >= 0) atomicOr(err, 1u);
             }
 #pragma unroll
@@ -309,8 +289,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ha
                     ++sq;
                     continue;
                 }
-                const uint32_t dg = digit_of(dexp, SH, digit, WIN);
-                load_digit(b, tbl, dg, lane, one_h);
+                load_digit(b, tbl, digit_of(dexp, SH, digit, WIN), lane, one_h);
             }
             mont_mul<NL, LB>(acc, acc, b, n, n0);
             if (phase == 4) break;
@@ -343,8 +322,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ha
             }
             if (phase == 2 && e == T) {
                 // table complete: start from the top digit
-                const uint32_t dg = digit_of(dexp, SH, NW - 1, WIN);
-                load_digit(acc, tbl, dg, lane, one_h);
+                load_digit(acc, tbl, digit_of(dexp, SH, NW - 1, WIN), lane, one_h);
                 phase = 3;
             }
             if (phase == 3 && digit < 0) {
@@ -354,7 +332,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ha
             }
         }
         canonicalize<NL, LB>(acc, n);
-        uint32_t *dst = half + ((size_t)tile * NL) * kTile + lane;
+        uint32_t *dst = half + ((size_t)jt * NL) * kTile + lane;
 #pragma unroll
         for (int j = 0; j < NL; ++j) dst[(size_t)j * kTile] = acc[j];
     }
@@ -365,19 +343,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ha
 // canonical; m = m_q + h q by schoolbook columns.
 template <int CB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void garner_kernel(
-    const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc, uint32_t count,
+    const uint32_t *__restrict__ keys, const uint32_t *__restrict__ tile_key,
     const uint32_t *__restrict__ half, uint32_t *__restrict__ y32) {
     constexpr Geom G = make_geom(CB);
     constexpr int NL = G.nlh, LB = G.lbh, S = G.S;
     constexpr uint32_t MASK = Radix<LB>::MASK;
-    const uint32_t rank = blockIdx.x * kTile + threadIdx.x;
-    const uint32_t rk = rank < count ? rank : count - 1;
-    const uint32_t *kr = keys + (size_t)desc[rk].key * G.stride;
+    const uint32_t tile = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint32_t *kr = keys + (size_t)tile_key[tile] * G.stride;  // wave-uniform
     const uint32_t *hp = kr + G.off_half[0];
     const uint32_t *hq = kr + G.off_half[1];
-    const uint32_t jp = 2 * rk, jq = 2 * rk + 1;
-    const uint32_t *mp_src = half + ((size_t)(jp / kTile) * NL) * kTile + (jp % kTile);
-    const uint32_t *mq_src = half + ((size_t)(jq / kTile) * NL) * kTile + (jq % kTile);
+    const uint32_t *mp_src = half + ((size_t)(2 * tile) * NL) * kTile + lane;
+    const uint32_t *mq_src = half + ((size_t)(2 * tile + 1) * NL) * kTile + lane;
 
     uint32_t p[NL], mq[NL], a[NL], b[NL];
     load_limbs(p, hp + G.h_m);
@@ -410,11 +387,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ga
         m[k] = (uint32_t)acc & MASK;
         c = acc >> LB;
     }
-    if (rank < count) {
 #pragma unroll
-        for (int k = 0; k < S; ++k)
-            y32[((size_t)(rank / kTile) * S + k) * kTile + (rank % kTile)] = radix_word<2 * NL, LB>(m, k);
-    }
+    for (int k = 0; k < S; ++k) y32[((size_t)tile * S + k) * kTile + lane] = radix_word<2 * NL, LB>(m, k);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -439,43 +413,39 @@ uint32_t slots_for(int decrypt, int num_cus) {
 template <int CB>
 int do_pack(const ClassRun &r, const uint8_t *src, int decrypt, hipStream_t s) {
     constexpr Geom G = make_geom(CB);
-    const uint32_t tiles = (r.count + kTile - 1) / kTile;
-    hipLaunchKernelGGL(pack_kernel<G.S>, dim3(tiles), dim3(256), 0, s, src, r.desc, r.keys, G.stride,
-                       G.off_kbytes, r.count, r.x32, decrypt);
+    hipLaunchKernelGGL(pack_kernel<G.S>, dim3(r.ntiles), dim3(256), 0, s, src, r.desc, r.keys, r.tile_key,
+                       G.stride, G.off_kbytes, r.x32, decrypt);
     return (int)hipGetLastError();
 }
 
 template <int CB>
 int do_unpack(const ClassRun &r, uint8_t *dst, int decrypt, hipStream_t s) {
     constexpr Geom G = make_geom(CB);
-    const uint32_t tiles = (r.count + kTile - 1) / kTile;
-    hipLaunchKernelGGL(unpack_kernel<G.S>, dim3(tiles), dim3(256), 0, s, r.y32, r.desc, r.keys, G.stride,
-                       G.off_kbytes, r.count, dst, decrypt);
+    hipLaunchKernelGGL(unpack_kernel<G.S>, dim3(r.ntiles), dim3(256), 0, s, r.y32, r.desc, r.keys, r.tile_key,
+                       G.stride, G.off_kbytes, dst, decrypt);
     return (int)hipGetLastError();
 }
 
 template <int CB>
 int do_encrypt(const ClassRun &r, hipStream_t s) {
-    const uint32_t tiles = (r.count + kTile - 1) / kTile;
-    const uint32_t grid = tiles < r.slots_enc ? tiles : r.slots_enc;
-    hipLaunchKernelGGL(encrypt_kernel<CB>, dim3(grid), dim3(64), 0, s, r.keys, r.desc, r.count, r.x32, r.y32,
-                       r.table);
+    const uint32_t grid = r.ntiles < r.slots_enc ? r.ntiles : r.slots_enc;
+    hipLaunchKernelGGL(encrypt_kernel<CB>, dim3(grid), dim3(64), 0, s, r.keys, r.tile_key, r.ntiles, r.x32,
+                       r.y32, r.table);
     return (int)hipGetLastError();
 }
 
 template <int CB>
 int do_halves(const ClassRun &r, hipStream_t s) {
-    const uint32_t tiles = (2 * r.count + kTile - 1) / kTile;
-    const uint32_t grid = tiles < r.slots_dec ? tiles : r.slots_dec;
-    hipLaunchKernelGGL((halves_kernel<CB, kWin<CB>>), dim3(grid), dim3(64), 0, s, r.keys, r.desc, r.count,
-                       r.x32, r.half, r.table, r.err);
+    const uint32_t jobs = 2 * r.ntiles;
+    const uint32_t grid = jobs < r.slots_dec ? jobs : r.slots_dec;
+    hipLaunchKernelGGL((halves_kernel<CB, kWin<CB>>), dim3(grid), dim3(64), 0, s, r.keys, r.desc, r.tile_key,
+                       r.ntiles, r.x32, r.half, r.table, r.err);
     return (int)hipGetLastError();
 }
 
 template <int CB>
 int do_garner(const ClassRun &r, hipStream_t s) {
-    const uint32_t tiles = (r.count + kTile - 1) / kTile;
-    hipLaunchKernelGGL(garner_kernel<CB>, dim3(tiles), dim3(64), 0, s, r.keys, r.desc, r.count, r.half, r.y32);
+    hipLaunchKernelGGL(garner_kernel<CB>, dim3(r.ntiles), dim3(64), 0, s, r.keys, r.tile_key, r.half, r.y32);
     return (int)hipGetLastError();
 }
 
@@ -492,23 +462,23 @@ int do_garner(const ClassRun &r, hipStream_t s) {
 }  // namespace
 
 int launch_pack(const ClassRun &r, const uint8_t *src, int decrypt, void *stream) {
-    if (r.count == 0) return 0;
+    if (r.ntiles == 0) return 0;
     PMK_DISPATCH(r.cls, return do_pack<CB>(r, src, decrypt, (hipStream_t)stream));
 }
 int launch_unpack(const ClassRun &r, uint8_t *dst, int decrypt, void *stream) {
-    if (r.count == 0) return 0;
+    if (r.ntiles == 0) return 0;
     PMK_DISPATCH(r.cls, return do_unpack<CB>(r, dst, decrypt, (hipStream_t)stream));
 }
 int launch_encrypt(const ClassRun &r, void *stream) {
-    if (r.count == 0) return 0;
+    if (r.ntiles == 0) return 0;
     PMK_DISPATCH(r.cls, return do_encrypt<CB>(r, (hipStream_t)stream));
 }
 int launch_decrypt_halves(const ClassRun &r, void *stream) {
-    if (r.count == 0) return 0;
+    if (r.ntiles == 0) return 0;
     PMK_DISPATCH(r.cls, return do_halves<CB>(r, (hipStream_t)stream));
 }
 int launch_garner(const ClassRun &r, void *stream) {
-    if (r.count == 0) return 0;
+    if (r.ntiles == 0) return 0;
     PMK_DISPATCH(r.cls, return do_garner<CB>(r, (hipStream_t)stream));
 }
 

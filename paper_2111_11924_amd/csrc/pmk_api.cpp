@@ -266,17 +266,32 @@ int pmk_plan_create(pmk_ctx *ctx, const uint32_t *key_map, uint64_t nchunks, uin
     *out = nullptr;
     std::vector<uint32_t> bits(ctx->keys.size());
     for (size_t i = 0; i < bits.size(); ++i) bits[i] = ctx->keys[i].bits;
-    std::vector<std::vector<ChunkDesc>> per(kNumClasses);
+    // chunks of each key, in message order
+    std::vector<std::vector<ChunkDesc>> per_key(ctx->keys.size());
     std::string why;
     uint64_t total = 0;
     const int rc = walk_chunks(bits.data(), (uint32_t)bits.size(), key_map, nchunks, msg_len, &total, &why,
                                [&](uint64_t, uint32_t k, uint64_t off, uint64_t len, uint64_t ct) {
-                                   const KeySlot &s = ctx->keys[k];
-                                   per[s.cls].push_back(ChunkDesc{off, ct, s.slot, (uint32_t)len});
+                                   per_key[k].push_back(ChunkDesc{off, ct, ctx->keys[k].slot, (uint32_t)len});
                                });
     if (rc != PMK_OK) return set_err(ctx, rc, "%s", why.c_str());
+    // key-uniform tiles of up to 64 chunks, per size class; padding slots keep
+    // the tile's key and have msg_len 0
+    std::vector<std::vector<ChunkDesc>> per(kNumClasses);
+    std::vector<std::vector<uint32_t>> tkeys(kNumClasses);
+    uint32_t counts[kNumClasses] = {};
+    for (size_t k = 0; k < per_key.size(); ++k) {
+        const auto &list = per_key[k];
+        const int c = ctx->keys[k].cls;
+        counts[c] += (uint32_t)list.size();
+        for (size_t i = 0; i < list.size(); i += kTile) {
+            tkeys[c].push_back(ctx->keys[k].slot);
+            for (size_t l = 0; l < (size_t)kTile; ++l)
+                per[c].push_back(i + l < list.size() ? list[i + l] : ChunkDesc{0, 0, ctx->keys[k].slot, 0});
+        }
+    }
     for (int c = 0; c < kNumClasses; ++c)
-        if (per[c].size() > 0x3FFFFFFFull) return set_err(ctx, PMK_ESIZE, "too many chunks in one size class");
+        if (tkeys[c].size() > 0x3FFFFFFull) return set_err(ctx, PMK_ESIZE, "too many chunks in one size class");
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
 
     pmk_plan *pl = new (std::nothrow) pmk_plan();
@@ -290,22 +305,27 @@ int pmk_plan_create(pmk_ctx *ctx, const uint32_t *key_map, uint64_t nchunks, uin
     for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
         ClassRun &r = pl->runs[c];
         r.cls = c;
-        r.count = (uint32_t)per[c].size();
+        r.count = counts[c];
+        r.ntiles = (uint32_t)tkeys[c].size();
         r.err = pl->d_err;
-        if (!r.count) continue;
+        if (!r.ntiles) continue;
         const Geom g = make_geom(kClassBits[c]);
-        const uint64_t tiles = (r.count + kTile - 1) / kTile;
-        const uint64_t htiles = (2ull * r.count + kTile - 1) / kTile;
+        const uint64_t tiles = r.ntiles, htiles = 2ull * r.ntiles;
         r.keys = ctx->d_keys[c];
         r.slots_enc = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 0, ctx->num_cus), tiles));
         r.slots_dec = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 1, ctx->num_cus), htiles));
         const uint64_t tbl_words = std::max(r.slots_enc * table_words_per_slot(c, 0),
                                             r.slots_dec * table_words_per_slot(c, 1));
         ChunkDesc *d = nullptr;
+        uint32_t *tk = nullptr;
         e = dev_alloc(pl, &d, per[c].size() * sizeof(ChunkDesc));
         if (e == hipSuccess)
             e = hipMemcpy(d, per[c].data(), per[c].size() * sizeof(ChunkDesc), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = dev_alloc(pl, &tk, tkeys[c].size() * sizeof(uint32_t));
+        if (e == hipSuccess)
+            e = hipMemcpy(tk, tkeys[c].data(), tkeys[c].size() * sizeof(uint32_t), hipMemcpyHostToDevice);
         r.desc = d;
+        r.tile_key = tk;
         if (e == hipSuccess) e = dev_alloc(pl, &r.x32, tiles * g.S * kTile * sizeof(uint32_t));
         if (e == hipSuccess) e = dev_alloc(pl, &r.y32, tiles * g.S * kTile * sizeof(uint32_t));
         if (e == hipSuccess) e = dev_alloc(pl, &r.half, htiles * g.nlh * kTile * sizeof(uint32_t));
@@ -352,7 +372,7 @@ int pmk_encrypt_plan(pmk_plan *pl, const uint8_t *d_msg, uint8_t *d_ct, void *st
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
     for (int c = 0; c < kNumClasses; ++c) {
         const ClassRun &r = pl->runs[c];
-        if (!r.count) continue;
+        if (!r.ntiles) continue;
         int e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(r, d_msg, 0, stream); });
         if (!e) e = timed_launch(pl, PMK_KERNEL_ENCRYPT, stream, [&] { return launch_encrypt(r, stream); });
         if (!e) e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, d_ct, 0, stream); });
@@ -370,7 +390,7 @@ int pmk_decrypt_plan(pmk_plan *pl, const uint8_t *d_ct, uint8_t *d_msg, void *st
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
     for (int c = 0; c < kNumClasses; ++c) {
         const ClassRun &r = pl->runs[c];
-        if (!r.count) continue;
+        if (!r.ntiles) continue;
         int e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(r, d_ct, 1, stream); });
         if (!e) e = timed_launch(pl, PMK_KERNEL_CRT_HALVES, stream, [&] { return launch_decrypt_halves(r, stream); });
         if (!e) e = timed_launch(pl, PMK_KERNEL_GARNER, stream, [&] { return launch_garner(r, stream); });

@@ -81,12 +81,15 @@ PMK_HD constexpr Geom make_geom(int bits) {
     return g;
 }
 
-// Chunk descriptor, one per chunk, stored per class in rank order.
+// Chunks are grouped into tiles of up to 64 chunks that share one key, so a
+// wavefront's modulus, exponent and window digits are wave-uniform (scalar
+// registers, no divergence).  Slot = tile * 64 + lane; a padding slot has
+// msg_len 0 and is computed but never written back.
 struct ChunkDesc {
     uint64_t msg_off;  // first plaintext byte of the chunk
     uint64_t ct_off;   // first ciphertext byte of the chunk's block
     uint32_t key;      // record index inside the class key table
-    uint32_t msg_len;  // plaintext bytes of this chunk (kb - 4, or the remainder)
+    uint32_t msg_len;  // plaintext bytes of this chunk (kb - 4, or the remainder); 0 = padding
 };
 
 constexpr int kTile = 64;  // bignums per wavefront
@@ -95,11 +98,13 @@ constexpr int kTile = 64;  // bignums per wavefront
 struct ClassRun {
     int cls;                   // index into kClassBits
     uint32_t count;            // chunks of this class
+    uint32_t ntiles;           // key-uniform tiles of this class
     const uint32_t *keys;      // class key table (device), Geom::stride words per key
-    const ChunkDesc *desc;     // count descriptors (device)
-    uint32_t *x32;             // ceil(count/64) * S * 64 words: packed input limbs
+    const ChunkDesc *desc;     // ntiles * 64 slot descriptors (device)
+    const uint32_t *tile_key;  // ntiles key records (device)
+    uint32_t *x32;             // ntiles * S * 64 words: packed input limbs
     uint32_t *y32;             // same shape: result limbs before unpacking
-    uint32_t *half;            // ceil(2 count/64) * nlh * 64 words: CRT half results
+    uint32_t *half;            // 2 ntiles * nlh * 64 words: CRT half results (p then q per tile)
     uint32_t *table;           // per resident wave: window table scratch
     uint32_t slots_enc;        // wave slots in `table` for the encryption kernel
     uint32_t slots_dec;        // wave slots in `table` for the CRT-halves kernel
