@@ -26,7 +26,7 @@ PMK_HD constexpr int lb_full(int bits) { return bits > 3072 ? 27 : 28; }
 PMK_HD constexpr int lb_half(int bits) { return lb_full(bits / 2); }
 
 // Window width of the fixed-window exponentiation of the CRT halves.
-PMK_HD constexpr int window_for(int bits) { return bits <= 256 ? 3 : (bits <= 1024 ? 4 : 5); }
+PMK_HD constexpr int window_for(int bits) { return bits <= 256 ? 3 : (bits <= 512 ? 4 : 5); }
 
 // Offsets (uint32 words) of one key record of a class.
 struct Geom {
