@@ -19,7 +19,8 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(PKG, "libpmk.so")
 
-SOURCES = ["kernels.hip", "pmk_api.cpp", "keyprep.cpp"]
+SOURCES = ["k128.hip", "k256.hip", "k512.hip", "k1024.hip", "k2048.hip", "k3072.hip", "k4096.hip",
+           "dispatch.cpp", "pmk_api.cpp", "keyprep.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -37,7 +38,7 @@ def _compile(src: str) -> str:
     return out
 
 
-def build(jobs: int = 4, verbose: bool = True) -> str:
+def build(jobs: int = 8, verbose: bool = True) -> str:
     os.makedirs(OBJ, exist_ok=True)
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(_compile, SOURCES))
@@ -51,7 +52,7 @@ def build(jobs: int = 4, verbose: bool = True) -> str:
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("--jobs", type=int, default=4)
+    ap.add_argument("--jobs", type=int, default=8)
     a = ap.parse_args()
     build(a.jobs)
     sys.exit(0)

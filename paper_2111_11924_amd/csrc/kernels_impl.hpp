@@ -10,20 +10,24 @@
 //   garner    h = qinv (m_p - m_q) mod p, m = m_q + h q (Sec. 2.1)
 //   unpack    32-bit limbs -> big-endian bytes of each block
 //
-// Every bignum operation is one lane's work (64 bignums per wavefront); the
-// Montgomery products (Sec. 3.2, Algorithm 3) are in mont.hpp.  A tile holds up
-// to 64 chunks under one key, so modulus, exponent and window digits are
-// wave-uniform.  The exponentiation kernels are persistent: each 64-thread block
-// owns a scratch slot for its window table and walks tiles blockIdx.x,
-// +gridDim.x, ...
+// Up to 2048-bit moduli every bignum operation is one lane's work (64 bignums
+// per wavefront, Montgomery products in mont.hpp); 3072- and 4096-bit numbers
+// are spread over 2 or 4 lanes (mont_lanes.hpp).  A tile holds the chunks of
+// one wavefront under one key, so the modulus and exponent are wave-uniform.
+// The exponentiation kernels are persistent: each 64-thread block owns a
+// scratch slot for its window table and walks tiles blockIdx.x, +gridDim.x, ...
+#pragma once
 #include <hip/hip_runtime.h>
 
 #include "mont.hpp"
+#include "mont_lanes.hpp"
 #include "pmk_internal.hpp"
 
 namespace pmk {
 
+#ifndef PMK_DEV
 #define PMK_DEV __device__ __forceinline__
+#endif
 
 PMK_DEV uint32_t bswap32(uint32_t x) { return __builtin_bswap32(x); }
 
@@ -66,48 +70,48 @@ PMK_DEV void be_store(uint8_t *dst, uint64_t base, int64_t len, int k, uint32_t 
 // order (coalesced), the tile is transposed in LDS, writes are whole rows of 64
 // lanes (coalesced).
 
-template <int S>
+template <int S, int CPT>
 __global__ __launch_bounds__(256) void pack_kernel(const uint8_t *__restrict__ src,
                                                    const ChunkDesc *__restrict__ desc,
                                                    const uint32_t *__restrict__ keys,
                                                    const uint32_t *__restrict__ tile_key, int stride,
                                                    int off_kbytes, uint32_t *__restrict__ x32, int decrypt) {
-    __shared__ uint32_t tile[S * (kTile + 1)];
+    __shared__ uint32_t tile[S * (CPT + 1)];
     const uint32_t t = blockIdx.x;
     const int64_t kb = keys[(size_t)tile_key[t] * stride + off_kbytes];
-    for (int i = threadIdx.x; i < S * kTile; i += blockDim.x) {
+    for (int i = threadIdx.x; i < S * CPT; i += blockDim.x) {
         const int c = i / S, k = i % S;
-        const ChunkDesc d = desc[(size_t)t * kTile + c];
+        const ChunkDesc d = desc[(size_t)t * CPT + c];
         uint32_t w = 0;
         if (d.msg_len) w = decrypt ? be_word(src, d.ct_off, kb, k) : be_word(src, d.msg_off, d.msg_len, k);
-        tile[k * (kTile + 1) + c] = w;
+        tile[k * (CPT + 1) + c] = w;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < S * kTile; i += blockDim.x) {
-        const int k = i / kTile, lane = i % kTile;
-        x32[((size_t)t * S + k) * kTile + lane] = tile[k * (kTile + 1) + lane];
+    for (int i = threadIdx.x; i < S * CPT; i += blockDim.x) {
+        const int k = i / CPT, c = i % CPT;
+        x32[((size_t)t * S + k) * CPT + c] = tile[k * (CPT + 1) + c];
     }
 }
 
-template <int S>
+template <int S, int CPT>
 __global__ __launch_bounds__(256) void unpack_kernel(const uint32_t *__restrict__ y32,
                                                      const ChunkDesc *__restrict__ desc,
                                                      const uint32_t *__restrict__ keys,
                                                      const uint32_t *__restrict__ tile_key, int stride,
                                                      int off_kbytes, uint8_t *__restrict__ dst, int decrypt) {
-    __shared__ uint32_t tile[S * (kTile + 1)];
+    __shared__ uint32_t tile[S * (CPT + 1)];
     const uint32_t t = blockIdx.x;
     const int64_t kb = keys[(size_t)tile_key[t] * stride + off_kbytes];
-    for (int i = threadIdx.x; i < S * kTile; i += blockDim.x) {
-        const int k = i / kTile, lane = i % kTile;
-        tile[k * (kTile + 1) + lane] = y32[((size_t)t * S + k) * kTile + lane];
+    for (int i = threadIdx.x; i < S * CPT; i += blockDim.x) {
+        const int k = i / CPT, c = i % CPT;
+        tile[k * (CPT + 1) + c] = y32[((size_t)t * S + k) * CPT + c];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < S * kTile; i += blockDim.x) {
+    for (int i = threadIdx.x; i < S * CPT; i += blockDim.x) {
         const int c = i / S, k = i % S;
-        const ChunkDesc d = desc[(size_t)t * kTile + c];
+        const ChunkDesc d = desc[(size_t)t * CPT + c];
         if (!d.msg_len) continue;
-        const uint32_t w = tile[k * (kTile + 1) + c];
+        const uint32_t w = tile[k * (CPT + 1) + c];
         if (decrypt)
             be_store(dst, d.msg_off, d.msg_len, k, w);
         else
@@ -130,6 +134,16 @@ template <typename T>
 PMK_DEV T *fresh(T *p) {
     asm volatile("" : "+s"(p));
     return p;
+}
+// the same for a per-lane (VGPR) pointer or value
+template <typename T>
+PMK_DEV T *fresh_v(T *p) {
+    asm volatile("" : "+v"(p));
+    return p;
+}
+PMK_DEV int fresh_i(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
 }
 
 // Window-table entries live in global memory as [entry][limb][lane] words, one
@@ -338,36 +352,276 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void ha
     }
 }
 
-// ------------------------------------------------------------------ Garner
-// One lane per chunk: h = MM(m_p + p - m_q, qinv R mod p) = qinv (m_p - m_q) mod p,
-// canonical; m = m_q + h q by schoolbook columns.
+// ------------------------------------------------------------------ lane groups
+// 3072- and 4096-bit classes: a number is spread over a group of L lanes, lane
+// `pos` holding limbs [pos K, pos K + K).  The multiplier of every product is
+// staged in LDS as one column per group (limb i of group g at lds[i * NG + g]),
+// so one call site serves squarings (stage acc), table products (x~ stays
+// staged) and digit products (stage T[digit]).
+
+// stage this lane's K limbs of a number into its group's LDS column (the
+// per-lane base goes through fresh_v so the K addresses are formed at each use
+// as base + immediate, not hoisted into registers for the whole kernel)
+template <int K>
+PMK_DEV void stage_limbs(uint32_t *col, int ng, int pos, const uint32_t (&x)[K]) {
+    uint32_t *d = fresh_v(col + pos * K * ng);
+#pragma unroll
+    for (int j = 0; j < K; ++j) d[j * ng] = x[j];
+}
+// the same from memory: limb pos*K + j at src[j * stride]
+template <int K>
+PMK_DEV void stage_mem(uint32_t *col, int ng, int pos, const uint32_t *src, size_t stride) {
+    uint32_t v[K];
+    src = fresh_v(src);
+#pragma unroll
+    for (int j = 0; j < K; ++j) v[j] = src[j * stride];
+    uint32_t *d = fresh_v(col + pos * K * ng);
+#pragma unroll
+    for (int j = 0; j < K; ++j) d[j * ng] = v[j];
+}
+// the constant 1
+template <int K>
+PMK_DEV void stage_one(uint32_t *col, int ng, int pos) {
+    uint32_t *d = fresh_v(col + pos * K * ng);
+#pragma unroll
+    for (int j = 0; j < K; ++j) d[j * ng] = (pos == 0 && j == 0) ? 1u : 0u;
+}
+// this lane's radix limbs [first, first + K) of the number whose 32-bit words
+// are in the group's LDS column
+template <int K, int LB>
+PMK_DEV void limbs_from_words(uint32_t (&x)[K], const uint32_t *col, int ng, int nwords, int first) {
+    col = fresh_v(col);
+    first = fresh_i(first);  // keep the K word indices and shifts out of the loop-invariant set
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int bit = LB * (first + j);
+        const int k = bit >> 5, sh = bit & 31;
+        const uint32_t lo = k < nwords ? col[k * ng] : 0u;
+        const uint32_t hi = k + 1 < nwords ? col[(k + 1) * ng] : 0u;
+        x[j] = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & Radix<LB>::MASK;
+    }
+}
+
 template <int CB>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void garner_kernel(
-    const uint32_t *__restrict__ keys, const uint32_t *__restrict__ tile_key,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encrypt_lanes_kernel(
+    const uint32_t *__restrict__ keys, const uint32_t *__restrict__ tile_key, uint32_t ntiles,
+    const uint32_t *__restrict__ x32, uint32_t *__restrict__ y32, uint32_t *__restrict__ table) {
+    constexpr Geom G = make_geom(CB);
+    constexpr int L = lanes_full(CB), NLT = G.nlf, K = NLT / L, LB = G.lbf, S = G.S;
+    constexpr int NG = 64 / L;  // groups (chunks) per wavefront
+    constexpr int ROWS = NLT > S ? NLT : S;
+    __shared__ uint32_t lds[ROWS * NG];
+    const int lane = threadIdx.x, pos = lane % L, grp = lane / L;
+    uint32_t *col = lds + grp;
+    uint32_t *tbl = table + (size_t)blockIdx.x * 2 * K * kTile;
+
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t *kr = keys + (size_t)tile_key[tile] * G.stride;  // wave-uniform
+        uint32_t n[K];
+        load_limbs(n, fresh_v(kr + G.off_nf + pos * K));
+        const uint32_t n0 = kr[G.off_n0f];
+        const uint32_t e0 = kr[G.off_e], e1 = kr[G.off_e + 1];
+        const int top = (int)kr[G.off_ebits] - 1;
+
+        uint32_t acc[K];
+        for (int k = pos; k < S; k += L) col[k * NG] = x32[((size_t)tile * S + k) * NG + grp];
+        limbs_from_words<K, LB>(acc, col, NG, S, pos * K);
+        stage_mem<K>(col, NG, pos, kr + G.off_rrf + pos * K, 1);
+
+        // phase 0: to Montgomery, 1: square, 2: multiply by x~, 3: from Montgomery
+        int phase = 0, bit = top - 1;
+        for (;;) {
+            mont_mul_lanes<NLT, LB, L>(acc, acc, col, NG, n, n0, pos);
+            if (phase == 3) break;
+            if (phase == 0) {
+                store_entry(tbl, 1, lane, acc);  // x~
+            } else if (phase == 1) {
+                const uint32_t eb = bit >= 32 ? (e1 >> (bit - 32)) & 1u : (e0 >> bit) & 1u;
+                if (eb) {
+                    phase = 2;
+                    stage_mem<K>(col, NG, pos, fresh(tbl) + K * kTile + lane, kTile);
+                    continue;
+                }
+            }
+            // next bit, or leave
+            if (phase != 0) --bit;
+            if (phase == 0) bit = top - 1;
+            if (bit >= 0) {
+                phase = 1;
+                stage_limbs(col, NG, pos, acc);
+            } else {
+                phase = 3;
+                stage_one<K>(col, NG, pos);
+            }
+        }
+        canonicalize_lanes<K, LB, L>(acc, n, pos);
+        // radix limbs -> 32-bit words through the group's column
+        stage_limbs(col, NG, pos, acc);
+        for (int k = pos; k < S; k += L) {
+            const int bit = 32 * k, j = bit / LB, sh = bit % LB;
+            const uint64_t l0 = j < NLT ? col[j * NG] : 0u;
+            const uint64_t l1 = j + 1 < NLT ? col[(j + 1) * NG] : 0u;
+            const uint64_t l2 = j + 2 < NLT ? col[(j + 2) * NG] : 0u;
+            y32[((size_t)tile * S + k) * NG + grp] = (uint32_t)((l0 >> sh) | (l1 << (LB - sh)) | (l2 << (2 * LB - sh)));
+        }
+    }
+}
+
+// CRT halves with 2 lanes per number: a wavefront holds the 16 chunks of a tile
+// twice, lanes 0-31 modulo p and lanes 32-63 modulo q.
+template <int CB, int WIN>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void halves_lanes_kernel(
+    const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc,
+    const uint32_t *__restrict__ tile_key, uint32_t ntiles, const uint32_t *__restrict__ x32,
+    uint32_t *__restrict__ half, uint32_t *__restrict__ table, uint32_t *__restrict__ err) {
+    constexpr Geom G = make_geom(CB);
+    constexpr int L = lanes_half(CB), NLT = G.nlh, K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
+    constexpr int CPT = chunks_per_tile(CB);
+    constexpr int NG = 64 / L;  // groups per wavefront = 2 * CPT
+    static_assert(NG == 2 * CPT, "one wavefront holds both halves of a tile");
+    constexpr int T = 1 << WIN;
+    constexpr int NW = (32 * SH + WIN - 1) / WIN;
+    constexpr int ROWS = NLT > S ? NLT : S;
+    __shared__ uint32_t lds[ROWS * NG];
+    const int lane = threadIdx.x, pos = lane % L, grp = lane / L;
+    const int c = grp % CPT, h = grp / CPT;
+    uint32_t *col = lds + grp;
+    uint32_t *tbl = table + (size_t)blockIdx.x * T * K * kTile;
+
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t *kr = keys + (size_t)tile_key[tile] * G.stride;
+        const uint32_t *hr = kr + G.off_half[0] + h * G.h_size;  // p for lanes 0-31, q for 32-63
+        uint32_t n[K];
+        load_limbs(n, fresh_v(hr + G.h_m + pos * K));
+        const uint32_t n0 = hr[G.h_m0];
+        const uint32_t *dexp = hr + G.h_d;
+
+        uint32_t acc[K];
+        for (int k = pos; k < S; k += L) col[k * NG] = x32[((size_t)tile * S + k) * CPT + c];
+        if (h == 0 && pos == 0 && desc[(size_t)tile * CPT + c].msg_len) {
+            // C must lie in Z_N
+            const uint32_t *n32 = kr + G.off_n32;
+            int cmp = 0;
+            for (int k = S - 1; k >= 0 && cmp == 0; --k) {
+                const uint32_t w = col[k * NG];
+                cmp = (w > n32[k]) - (w < n32[k]);
+            }
+            if (cmp >= 0) atomicOr(err, 1u);
+        }
+        limbs_from_words<K, LB>(acc, col, NG, S, NLT + pos * K);  // c_hi
+        store_entry(tbl, 0, lane, acc);
+        limbs_from_words<K, LB>(acc, col, NG, S, pos * K);        // c_lo
+        stage_mem<K>(col, NG, pos, hr + G.h_rr + pos * K, 1);
+
+        // phases as in halves_kernel: 0 c_lo R, 1 c_hi R^2 and x~, 2 table,
+        // 3 digits (squarings, then a table product), 4 leave Montgomery form
+        int phase = 0, e = 2, digit = NW - 2, sq = 0;
+        for (;;) {
+            mont_mul_lanes<NLT, LB, L>(acc, acc, col, NG, n, n0, pos);
+            if (phase == 4) break;
+            if (phase == 0) {
+                store_entry(tbl, 1, lane, acc);
+                load_entry(acc, tbl, 0, lane);
+                stage_mem<K>(col, NG, pos, hr + G.h_rrr + pos * K, 1);
+                phase = 1;
+                continue;
+            }
+            if (phase == 1) {
+                // x~ = acc + T[1]: limb-wise, carries across the group's lanes
+                uint32_t lo[K];
+                load_entry(lo, tbl, 1, lane);
+                uint32_t cy = 0;
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const uint32_t v = acc[j] + lo[j] + cy;
+                    acc[j] = v & Radix<LB>::MASK;
+                    cy = v >> LB;
+                }
+#pragma unroll
+                for (int s = 1; s < L; ++s) {
+                    uint32_t cin = grp_prev<L>(cy, pos);
+                    cy = 0;
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        const uint32_t v = acc[j] + cin;
+                        acc[j] = v & Radix<LB>::MASK;
+                        cin = v >> LB;
+                    }
+                    cy = cin;
+                }
+                store_entry(tbl, 1, lane, acc);
+                stage_limbs(col, NG, pos, acc);  // x~ stays staged for the table
+                phase = 2;
+                continue;
+            }
+            if (phase == 2) {
+                store_entry(tbl, e, lane, acc);
+                if (++e < T) continue;
+                const uint32_t dg = digit_of(dexp, SH, NW - 1, WIN);
+                if (dg)
+                    load_entry(acc, tbl, dg, lane);
+                else
+                    load_limbs(acc, fresh_v(hr + G.h_one + pos * K));
+                phase = 3;
+            } else if (sq == WIN + 1) {  // phase 3: a digit's product is done
+                --digit;
+                sq = 0;
+            }
+            // phase 3: next squaring, the digit's product, or the end
+            if (digit < 0) {
+                stage_one<K>(col, NG, pos);
+                phase = 4;
+            } else if (sq < WIN) {
+                stage_limbs(col, NG, pos, acc);
+                ++sq;
+            } else {
+                const uint32_t dg = digit_of(dexp, SH, digit, WIN);
+                if (dg)
+                    stage_mem<K>(col, NG, pos, fresh(tbl) + (size_t)dg * K * kTile + lane, kTile);
+                else
+                    stage_mem<K>(col, NG, pos, hr + G.h_one + pos * K, 1);
+                sq = WIN + 1;
+            }
+        }
+        canonicalize_lanes<K, LB, L>(acc, n, pos);
+        uint32_t *dst = half + ((size_t)(2 * tile + h) * NLT + pos * K) * CPT + c;
+#pragma unroll
+        for (int j = 0; j < K; ++j) dst[(size_t)j * CPT] = acc[j];
+    }
+}
+
+// ------------------------------------------------------------------ Garner
+// One lane per chunk slot (64 consecutive slots per block, keys per lane):
+// h = MM(m_p + p - m_q, qinv R mod p) = qinv (m_p - m_q) mod p, canonical;
+// m = m_q + h q by schoolbook columns.
+template <int CB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(make_geom(CB).nlh > 40 ? 1 : 2))) void garner_kernel(
+    const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc, uint32_t nslots,
     const uint32_t *__restrict__ half, uint32_t *__restrict__ y32) {
     constexpr Geom G = make_geom(CB);
-    constexpr int NL = G.nlh, LB = G.lbh, S = G.S;
+    constexpr int NL = G.nlh, LB = G.lbh, S = G.S, CPT = chunks_per_tile(CB);
     constexpr uint32_t MASK = Radix<LB>::MASK;
-    const uint32_t tile = blockIdx.x;
-    const int lane = threadIdx.x;
-    const uint32_t *kr = keys + (size_t)tile_key[tile] * G.stride;  // wave-uniform
+    const uint32_t slot0 = blockIdx.x * 64 + threadIdx.x;
+    const uint32_t slot = slot0 < nslots ? slot0 : nslots - 1;
+    const uint32_t tile = slot / CPT, c = slot % CPT;
+    const uint32_t *kr = keys + (size_t)desc[slot].key * G.stride;
     const uint32_t *hp = kr + G.off_half[0];
     const uint32_t *hq = kr + G.off_half[1];
-    const uint32_t *mp_src = half + ((size_t)(2 * tile) * NL) * kTile + lane;
-    const uint32_t *mq_src = half + ((size_t)(2 * tile + 1) * NL) * kTile + lane;
+    const uint32_t *mp_src = half + ((size_t)(2 * tile) * NL) * CPT + c;
+    const uint32_t *mq_src = half + ((size_t)(2 * tile + 1) * NL) * CPT + c;
 
     uint32_t p[NL], mq[NL], a[NL], b[NL];
     load_limbs(p, hp + G.h_m);
 #pragma unroll
-    for (int j = 0; j < NL; ++j) mq[j] = mq_src[(size_t)j * kTile];
+    for (int j = 0; j < NL; ++j) mq[j] = mq_src[(size_t)j * CPT];
     {
         // a = m_p + p - m_q, in (0, 2p): limb-wise with signed carries
-        int32_t c = 0;
+        int32_t cy = 0;
 #pragma unroll
         for (int j = 0; j < NL; ++j) {
-            const int32_t v = (int32_t)mp_src[(size_t)j * kTile] + (int32_t)p[j] - (int32_t)mq[j] + c;
+            const int32_t v = (int32_t)mp_src[(size_t)j * CPT] + (int32_t)p[j] - (int32_t)mq[j] + cy;
             a[j] = (uint32_t)v & MASK;
-            c = v >> LB;  // arithmetic shift: -1, 0 or 1
+            cy = v >> LB;  // arithmetic shift: -1, 0 or 1
         }
     }
     load_limbs(b, kr + G.off_qinvr);
@@ -377,119 +631,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ga
     uint32_t q[NL];
     load_limbs(q, hq + G.h_m);
     uint32_t m[2 * NL];
-    uint64_t c = 0;
+    uint64_t cy = 0;
 #pragma unroll
     for (int k = 0; k < 2 * NL; ++k) {  // m = m_q + h q, column by column
-        uint64_t acc = c + (k < NL ? mq[k] : 0u);
+        uint64_t acc = cy + (k < NL ? mq[k] : 0u);
 #pragma unroll
         for (int i = (k - NL + 1 > 0 ? k - NL + 1 : 0); i <= (k < NL ? k : NL - 1); ++i)
             acc += (uint64_t)a[i] * q[k - i];
         m[k] = (uint32_t)acc & MASK;
-        c = acc >> LB;
+        cy = acc >> LB;
     }
+    if (slot0 < nslots) {
 #pragma unroll
-    for (int k = 0; k < S; ++k) y32[((size_t)tile * S + k) * kTile + lane] = radix_word<2 * NL, LB>(m, k);
-}
-
-// ------------------------------------------------------------------ launchers
-namespace {
-
-template <int CB>
-constexpr int kWin = window_for(CB / 2);
-
-template <int CB>
-int occupancy_blocks(const void *fn) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64, 0) != hipSuccess || nb < 1) nb = 1;
-    return nb;
-}
-
-template <int CB>
-uint32_t slots_for(int decrypt, int num_cus) {
-    const void *fn = decrypt ? (const void *)halves_kernel<CB, kWin<CB>> : (const void *)encrypt_kernel<CB>;
-    return (uint32_t)(occupancy_blocks<CB>(fn) * num_cus);
-}
-
-template <int CB>
-int do_pack(const ClassRun &r, const uint8_t *src, int decrypt, hipStream_t s) {
-    constexpr Geom G = make_geom(CB);
-    hipLaunchKernelGGL(pack_kernel<G.S>, dim3(r.ntiles), dim3(256), 0, s, src, r.desc, r.keys, r.tile_key,
-                       G.stride, G.off_kbytes, r.x32, decrypt);
-    return (int)hipGetLastError();
-}
-
-template <int CB>
-int do_unpack(const ClassRun &r, uint8_t *dst, int decrypt, hipStream_t s) {
-    constexpr Geom G = make_geom(CB);
-    hipLaunchKernelGGL(unpack_kernel<G.S>, dim3(r.ntiles), dim3(256), 0, s, r.y32, r.desc, r.keys, r.tile_key,
-                       G.stride, G.off_kbytes, dst, decrypt);
-    return (int)hipGetLastError();
-}
-
-template <int CB>
-int do_encrypt(const ClassRun &r, hipStream_t s) {
-    const uint32_t grid = r.ntiles < r.slots_enc ? r.ntiles : r.slots_enc;
-    hipLaunchKernelGGL(encrypt_kernel<CB>, dim3(grid), dim3(64), 0, s, r.keys, r.tile_key, r.ntiles, r.x32,
-                       r.y32, r.table);
-    return (int)hipGetLastError();
-}
-
-template <int CB>
-int do_halves(const ClassRun &r, hipStream_t s) {
-    const uint32_t jobs = 2 * r.ntiles;
-    const uint32_t grid = jobs < r.slots_dec ? jobs : r.slots_dec;
-    hipLaunchKernelGGL((halves_kernel<CB, kWin<CB>>), dim3(grid), dim3(64), 0, s, r.keys, r.desc, r.tile_key,
-                       r.ntiles, r.x32, r.half, r.table, r.err);
-    return (int)hipGetLastError();
-}
-
-template <int CB>
-int do_garner(const ClassRun &r, hipStream_t s) {
-    hipLaunchKernelGGL(garner_kernel<CB>, dim3(r.ntiles), dim3(64), 0, s, r.keys, r.tile_key, r.half, r.y32);
-    return (int)hipGetLastError();
-}
-
-#define PMK_DISPATCH(cls, CALL)           \
-    switch (cls) {                        \
-        case 0: { constexpr int CB = 128; CALL; } \
-        case 1: { constexpr int CB = 256; CALL; } \
-        case 2: { constexpr int CB = 512; CALL; } \
-        case 3: { constexpr int CB = 1024; CALL; } \
-        case 4: { constexpr int CB = 2048; CALL; } \
-        default: return (int)hipErrorInvalidValue; \
+        for (int k = 0; k < S; ++k) y32[((size_t)tile * S + k) * CPT + c] = radix_word<2 * NL, LB>(m, k);
     }
-
-}  // namespace
-
-int launch_pack(const ClassRun &r, const uint8_t *src, int decrypt, void *stream) {
-    if (r.ntiles == 0) return 0;
-    PMK_DISPATCH(r.cls, return do_pack<CB>(r, src, decrypt, (hipStream_t)stream));
-}
-int launch_unpack(const ClassRun &r, uint8_t *dst, int decrypt, void *stream) {
-    if (r.ntiles == 0) return 0;
-    PMK_DISPATCH(r.cls, return do_unpack<CB>(r, dst, decrypt, (hipStream_t)stream));
-}
-int launch_encrypt(const ClassRun &r, void *stream) {
-    if (r.ntiles == 0) return 0;
-    PMK_DISPATCH(r.cls, return do_encrypt<CB>(r, (hipStream_t)stream));
-}
-int launch_decrypt_halves(const ClassRun &r, void *stream) {
-    if (r.ntiles == 0) return 0;
-    PMK_DISPATCH(r.cls, return do_halves<CB>(r, (hipStream_t)stream));
-}
-int launch_garner(const ClassRun &r, void *stream) {
-    if (r.ntiles == 0) return 0;
-    PMK_DISPATCH(r.cls, return do_garner<CB>(r, (hipStream_t)stream));
-}
-
-uint64_t table_words_per_slot(int cls, int decrypt) {
-    const Geom g = make_geom(kClassBits[cls]);
-    if (!decrypt) return (uint64_t)2 * g.nlf * kTile;
-    return (uint64_t)(1u << window_for(kClassBits[cls] / 2)) * g.nlh * kTile;
-}
-
-uint32_t wave_slots(int cls, int decrypt, int num_cus) {
-    PMK_DISPATCH(cls, return slots_for<CB>(decrypt, num_cus));
 }
 
 }  // namespace pmk

@@ -1,0 +1,142 @@
+// Montgomery multiplication with one bignum spread over a group of L adjacent
+// lanes (L = 2 or 4), for the moduli whose limbs do not fit one lane's
+// registers (3072- and 4096-bit keys).
+//
+// Same arithmetic as mont.hpp (Sec. 3.2, Algorithm 3; LB-bit limbs, 64-bit
+// column accumulators, no carry handling inside the loop), in operand-scanning
+// order (CIOS): lane `pos` of a group owns limbs [pos K, pos K + K) of a, n and
+// of the running accumulator t.  Step i adds a b_i (b_i read from LDS, one
+// address per group: a broadcast), forms the reduction digit m_i from the
+// group's lowest accumulator limb (broadcast from lane 0 by a DPP quad
+// permutation), adds m_i n, and divides t by 2^LB: every lane hands its lowest
+// limb to the lane below (DPP), lane 0 folds the carry of its lowest limb into
+// the next one.  Carries between lanes are settled once, after the last step.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mont.hpp"
+
+namespace pmk {
+
+// quad_perm DPP selectors (four 2-bit lane indices inside each quad)
+constexpr int qperm(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
+
+template <int Ctrl>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, 0xF, 0xF, false);
+}
+
+// value held by lane 0 of the group
+template <int L>
+__device__ __forceinline__ uint32_t grp_first(uint32_t v) {
+    static_assert(L == 2 || L == 4, "groups of 2 or 4 lanes");
+    return L == 2 ? dpp<qperm(0, 0, 2, 2)>(v) : dpp<qperm(0, 0, 0, 0)>(v);
+}
+// value held by the group's last lane
+template <int L>
+__device__ __forceinline__ uint32_t grp_last(uint32_t v) {
+    return L == 2 ? dpp<qperm(1, 1, 3, 3)>(v) : dpp<qperm(3, 3, 3, 3)>(v);
+}
+// value of the next lane of the group (the last lane gets 0)
+template <int L>
+__device__ __forceinline__ uint32_t grp_next(uint32_t v, int pos) {
+    const uint32_t x = L == 2 ? dpp<qperm(1, 1, 3, 3)>(v) : dpp<qperm(1, 2, 3, 3)>(v);
+    return pos == L - 1 ? 0u : x;
+}
+// value of the previous lane of the group (lane 0 gets 0)
+template <int L>
+__device__ __forceinline__ uint32_t grp_prev(uint32_t v, int pos) {
+    const uint32_t x = L == 2 ? dpp<qperm(0, 0, 2, 2)>(v) : dpp<qperm(0, 0, 1, 2)>(v);
+    return pos == 0 ? 0u : x;
+}
+template <int L>
+__device__ __forceinline__ uint64_t grp_next64(uint64_t v, int pos) {
+    return ((uint64_t)grp_next<L>((uint32_t)(v >> 32), pos) << 32) | grp_next<L>((uint32_t)v, pos);
+}
+template <int L>
+__device__ __forceinline__ uint64_t grp_prev64(uint64_t v, int pos) {
+    return ((uint64_t)grp_prev<L>((uint32_t)(v >> 32), pos) << 32) | grp_prev<L>((uint32_t)v, pos);
+}
+
+// r = a b R^-1 mod m (R = 2^(LB NLT)), result below 2m, normalised.  K = NLT/L
+// limbs per lane; b_i at bl[i * bstride] in LDS; r may alias a.
+template <int NLT, int LB, int L>
+__device__ __forceinline__ void mont_mul_lanes(uint32_t (&r)[NLT / L], const uint32_t (&a)[NLT / L],
+                                               const uint32_t *bl, int bstride,
+                                               const uint32_t (&n)[NLT / L], uint32_t n0, int pos) {
+    constexpr int K = NLT / L;
+    static_assert(K * L == NLT, "limbs must split evenly over the lanes");
+    static_assert((2.0 * NLT + 1) * (double)(1ull << LB) * (double)(1ull << LB) < 18446744073709551615.0,
+                  "column sums may overflow 64 bits");
+    constexpr uint32_t MASK = Radix<LB>::MASK;
+    asm volatile("" : "+v"(bl));  // b_i addresses: base + immediate at each use
+    uint64_t t[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) t[j] = 0;
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < NLT; ++i) {
+        const uint32_t bi = bl[i * bstride];
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] += (uint64_t)a[j] * bi;
+        const uint32_t m = (grp_first<L>((uint32_t)t[0]) * n0) & MASK;
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] += (uint64_t)m * n[j];
+        // lane 0's lowest column is now a multiple of 2^LB: its carry moves up;
+        // every other lane's lowest column moves down to the lane below
+        const uint64_t c = pos == 0 ? t[0] >> LB : 0;
+        const uint64_t in = grp_next64<L>(t[0], pos);
+#pragma unroll
+        for (int j = 0; j < K - 1; ++j) t[j] = t[j + 1];
+        t[K - 1] = in;
+        t[0] += c;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // settle carries: within each lane, then L-1 rounds across lane boundaries
+    uint64_t c = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint64_t v = t[j] + c;
+        r[j] = (uint32_t)v & MASK;
+        c = v >> LB;
+    }
+#pragma unroll
+    for (int s = 1; s < L; ++s) {
+        uint64_t cin = grp_prev64<L>(c, pos);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint64_t v = (uint64_t)r[j] + cin;
+            r[j] = (uint32_t)v & MASK;
+            cin = v >> LB;
+        }
+        c = cin;
+    }
+}
+
+// x < 2m -> x mod m for a lane-distributed number: the borrow of x - m crosses
+// the lanes in L rounds; the group keeps x - m when the top lane ends without
+// a borrow.
+template <int K, int LB, int L>
+__device__ __forceinline__ void canonicalize_lanes(uint32_t (&x)[K], const uint32_t (&n)[K], int pos) {
+    constexpr uint32_t MASK = Radix<LB>::MASK;
+    uint32_t d[K];
+    uint32_t bin = 0, bout = 0;
+#pragma unroll
+    for (int s = 0; s < L; ++s) {
+        int32_t borrow = (int32_t)bin;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int32_t v = (int32_t)x[j] - (int32_t)n[j] - borrow;
+            d[j] = (uint32_t)v & MASK;
+            borrow = v < 0 ? 1 : 0;
+        }
+        bout = (uint32_t)borrow;
+        bin = grp_prev<L>(bout, pos);
+    }
+    const bool keep = grp_last<L>(bout) == 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) x[j] = keep ? d[j] : x[j];
+}
+
+}  // namespace pmk

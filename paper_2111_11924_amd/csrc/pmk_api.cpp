@@ -283,10 +283,11 @@ int pmk_plan_create(pmk_ctx *ctx, const uint32_t *key_map, uint64_t nchunks, uin
     for (size_t k = 0; k < per_key.size(); ++k) {
         const auto &list = per_key[k];
         const int c = ctx->keys[k].cls;
+        const size_t cpt = (size_t)chunks_per_tile(kClassBits[c]);
         counts[c] += (uint32_t)list.size();
-        for (size_t i = 0; i < list.size(); i += kTile) {
+        for (size_t i = 0; i < list.size(); i += cpt) {
             tkeys[c].push_back(ctx->keys[k].slot);
-            for (size_t l = 0; l < (size_t)kTile; ++l)
+            for (size_t l = 0; l < cpt; ++l)
                 per[c].push_back(i + l < list.size() ? list[i + l] : ChunkDesc{0, 0, ctx->keys[k].slot, 0});
         }
     }
@@ -310,10 +311,10 @@ int pmk_plan_create(pmk_ctx *ctx, const uint32_t *key_map, uint64_t nchunks, uin
         r.err = pl->d_err;
         if (!r.ntiles) continue;
         const Geom g = make_geom(kClassBits[c]);
-        const uint64_t tiles = r.ntiles, htiles = 2ull * r.ntiles;
+        const uint64_t tiles = r.ntiles, cpt = (uint64_t)chunks_per_tile(kClassBits[c]);
         r.keys = ctx->d_keys[c];
-        r.slots_enc = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 0, ctx->num_cus), tiles));
-        r.slots_dec = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 1, ctx->num_cus), htiles));
+        r.slots_enc = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 0, ctx->num_cus), exp_units(c, 0, r.ntiles)));
+        r.slots_dec = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 1, ctx->num_cus), exp_units(c, 1, r.ntiles)));
         const uint64_t tbl_words = std::max(r.slots_enc * table_words_per_slot(c, 0),
                                             r.slots_dec * table_words_per_slot(c, 1));
         ChunkDesc *d = nullptr;
@@ -326,9 +327,9 @@ int pmk_plan_create(pmk_ctx *ctx, const uint32_t *key_map, uint64_t nchunks, uin
             e = hipMemcpy(tk, tkeys[c].data(), tkeys[c].size() * sizeof(uint32_t), hipMemcpyHostToDevice);
         r.desc = d;
         r.tile_key = tk;
-        if (e == hipSuccess) e = dev_alloc(pl, &r.x32, tiles * g.S * kTile * sizeof(uint32_t));
-        if (e == hipSuccess) e = dev_alloc(pl, &r.y32, tiles * g.S * kTile * sizeof(uint32_t));
-        if (e == hipSuccess) e = dev_alloc(pl, &r.half, htiles * g.nlh * kTile * sizeof(uint32_t));
+        if (e == hipSuccess) e = dev_alloc(pl, &r.x32, tiles * g.S * cpt * sizeof(uint32_t));
+        if (e == hipSuccess) e = dev_alloc(pl, &r.y32, tiles * g.S * cpt * sizeof(uint32_t));
+        if (e == hipSuccess) e = dev_alloc(pl, &r.half, tiles * 2 * g.nlh * cpt * sizeof(uint32_t));
         if (e == hipSuccess) e = dev_alloc(pl, &r.table, tbl_words * sizeof(uint32_t));
     }
     if (e != hipSuccess) {

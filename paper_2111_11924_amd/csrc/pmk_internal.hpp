@@ -16,7 +16,7 @@ namespace pmk {
 // arithmetic only needs R > 4m, so a smaller modulus fits a larger class.
 constexpr int kNumClasses = 7;
 constexpr int kClassBits[kNumClasses] = {128, 256, 512, 1024, 2048, 3072, 4096};
-constexpr int kMaxClass = 4;
+constexpr int kMaxClass = 6;
 
 PMK_HD constexpr int nl_for(int bits, int lb) { return (bits + 2 + lb - 1) / lb; }
 
@@ -24,6 +24,15 @@ PMK_HD constexpr int nl_for(int bits, int lb) { return (bits + 2 + lb - 1) / lb;
 // Montgomery product below 2^64 up to 3072 bits; 4096-bit moduli use 27 bits.
 PMK_HD constexpr int lb_full(int bits) { return bits > 3072 ? 27 : 28; }
 PMK_HD constexpr int lb_half(int bits) { return lb_full(bits / 2); }
+
+// Lanes per bignum: one lane holds a whole number up to 2048-bit moduli; the
+// 3072- and 4096-bit classes spread each number over a group of lanes (4 for
+// the full modulus, 2 for a CRT half) so its limbs fit the registers.
+PMK_HD constexpr int lanes_full(int bits) { return bits >= 3072 ? 4 : 1; }
+PMK_HD constexpr int lanes_half(int bits) { return bits >= 3072 ? 2 : 1; }
+// chunks per tile (one tile = one wavefront of the encryption kernel)
+PMK_HD constexpr int chunks_per_tile(int bits) { return 64 / lanes_full(bits); }
+PMK_HD constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // Window width of the fixed-window exponentiation of the CRT halves.
 PMK_HD constexpr int window_for(int bits) { return bits <= 256 ? 3 : (bits <= 512 ? 4 : 5); }
@@ -52,9 +61,9 @@ PMK_HD constexpr Geom make_geom(int bits) {
     g.S = bits / 32;
     g.SH = bits / 64;
     g.lbf = lb_full(bits);
-    g.nlf = nl_for(bits, g.lbf);
+    g.nlf = round_up(nl_for(bits, g.lbf), lanes_full(bits));
     g.lbh = lb_half(bits);
-    g.nlh = nl_for(bits / 2, g.lbh);
+    g.nlh = round_up(nl_for(bits / 2, g.lbh), lanes_half(bits));
     g.ew = 2;
     const int pf = pad4(g.nlf), ph = pad4(g.nlh);
     int o = 0;
@@ -81,10 +90,10 @@ PMK_HD constexpr Geom make_geom(int bits) {
     return g;
 }
 
-// Chunks are grouped into tiles of up to 64 chunks that share one key, so a
-// wavefront's modulus, exponent and window digits are wave-uniform (scalar
-// registers, no divergence).  Slot = tile * 64 + lane; a padding slot has
-// msg_len 0 and is computed but never written back.
+// Chunks are grouped into tiles of up to chunks_per_tile chunks that share one
+// key, so a wavefront's modulus and exponent are wave-uniform (scalar
+// registers, no divergence).  Slot = tile * chunks_per_tile + chunk; a padding
+// slot has msg_len 0 and is computed but never written back.
 struct ChunkDesc {
     uint64_t msg_off;  // first plaintext byte of the chunk
     uint64_t ct_off;   // first ciphertext byte of the chunk's block
@@ -100,11 +109,11 @@ struct ClassRun {
     uint32_t count;            // chunks of this class
     uint32_t ntiles;           // key-uniform tiles of this class
     const uint32_t *keys;      // class key table (device), Geom::stride words per key
-    const ChunkDesc *desc;     // ntiles * 64 slot descriptors (device)
+    const ChunkDesc *desc;     // ntiles * cpt slot descriptors (device)
     const uint32_t *tile_key;  // ntiles key records (device)
-    uint32_t *x32;             // ntiles * S * 64 words: packed input limbs
-    uint32_t *y32;             // same shape: result limbs before unpacking
-    uint32_t *half;            // 2 ntiles * nlh * 64 words: CRT half results (p then q per tile)
+    uint32_t *x32;             // [tile][word < S][chunk < cpt]: packed input words
+    uint32_t *y32;             // same shape: result words before unpacking
+    uint32_t *half;            // [tile][p, q][limb < nlh][chunk < cpt]: CRT half results
     uint32_t *table;           // per resident wave: window table scratch
     uint32_t slots_enc;        // wave slots in `table` for the encryption kernel
     uint32_t slots_dec;        // wave slots in `table` for the CRT-halves kernel
@@ -121,5 +130,7 @@ int launch_unpack(const ClassRun &r, uint8_t *dst, int decrypt, void *stream);
 uint64_t table_words_per_slot(int cls, int decrypt);
 // resident wave slots the persistent kernels of a class use
 uint32_t wave_slots(int cls, int decrypt, int num_cus);
+// work units (wavefronts' worth of bignums) of the exponentiation kernels
+uint32_t exp_units(int cls, int decrypt, uint32_t ntiles);
 
 }  // namespace pmk

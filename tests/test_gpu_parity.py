@@ -77,11 +77,11 @@ def test_config1_small_512bit(torch, ctx):
     check_against_oracle(torch, ctx, w.keys(), w.message(), w.key_map())
 
 
-@pytest.mark.parametrize("bits", [128, 256, 512, 1024, 2048])
+@pytest.mark.parametrize("bits", [128, 256, 512, 1024, 2048, 3072, 4096])
 def test_each_size_class_several_tiles_ragged(torch, ctx, bits):
     keys = inputs.make_keys([bits] * 5, 700 + bits)
     kb = bits // 8
-    nch = 64 * 3 + 17  # three full tiles and a ragged one
+    nch = 64 * 3 + 17  # several tiles per key and a ragged last tile
     msg_len = (nch - 1) * (kb - 4) + 3  # last chunk: 3 bytes
     msg = inputs.make_message(msg_len, bits)
     km = inputs.round_robin_map(msg_len, [bits] * 5)
@@ -91,7 +91,7 @@ def test_each_size_class_several_tiles_ragged(torch, ctx, bits):
 
 def test_mixed_sizes_random_map(torch, ctx):
     # sizes that are not class sizes run in the next class up
-    bits = [128, 512, 2048, 256, 1024, 768, 192, 1536, 384, 2048]
+    bits = [128, 512, 2048, 256, 1024, 768, 192, 1536, 384, 2048, 3072, 4096, 2560, 3584]
     keys = inputs.make_keys(bits, 801)
     msg = inputs.make_message(150_000 + 7, 801)
     km = inputs.random_map(len(msg), bits, 801)
