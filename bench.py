@@ -86,6 +86,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=1024, help="chunks the oracle baseline times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--config", type=int, default=4,
+                    help="workload recipe (1-4; the JSON line's headline workload is 4)")
+    ap.add_argument("--mode", choices=["plain", "batch"], default="plain",
+                    help="plain: per-class launches, each timed with HIP events during the timed steps; "
+                         "batch: graph-captured batched path (kernel times from one extra profiled step)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -98,8 +103,9 @@ def main() -> int:
 
     from paper_2111_11924_amd import binding, inputs
 
-    w = inputs.config(4)
+    w = inputs.config(args.config)
     keys, msg, km = w.keys(), w.message(), w.key_map()
+    bits_of = np.array([k.bits for k in keys])[km]
     nchunks = len(km)
     ctx = binding.Context(0)
     ctx.load_keys(keys)
@@ -109,35 +115,50 @@ def main() -> int:
     d_pt = torch.empty(len(msg), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
 
+    batch = args.mode == "batch"
     for _ in range(args.warmup):
-        plan.encrypt(d_msg, d_ct, stream)
-        plan.decrypt(d_ct, d_pt, stream)
+        plan.encrypt(d_msg, d_ct, stream, batch=batch)
+        plan.decrypt(d_ct, d_pt, stream, batch=batch)
     torch.cuda.synchronize()
     if args.warmup > 0 and (plan.check(stream) != binding.PMK_OK or not torch.equal(d_pt, d_msg)):
         print("warm-up output wrong: decrypt(encrypt(m)) != m", file=sys.stderr)
         return 1
 
-    plan.profile(True)
+    # plain mode: every launch of the timed steps is bracketed by HIP events on
+    # the launch stream; batch mode replays the captured graphs untouched and
+    # takes kernel times from one more (uncaptured, profiled) step afterwards
+    plan.profile(not batch)
     marks = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         marks[k][0].record(stream)
-        plan.encrypt(d_msg, d_ct, stream)
+        plan.encrypt(d_msg, d_ct, stream, batch=batch)
         marks[k][1].record(stream)
-        plan.decrypt(d_ct, d_pt, stream)
+        plan.decrypt(d_ct, d_pt, stream, batch=batch)
         marks[k][2].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     enc_ms = sum(m[0].elapsed_time(m[1]) for m in marks)
     dec_ms = sum(m[1].elapsed_time(m[2]) for m in marks)
     ok = plan.check(stream) == binding.PMK_OK and torch.equal(d_pt, d_msg)
+    prof_steps = args.steps
+    if batch:
+        plan.profile(True)
+        plan.encrypt(d_msg, d_ct, stream, batch=True)
+        plan.decrypt(d_ct, d_pt, stream, batch=True)
+        torch.cuda.synchronize()
+        prof_steps = 1
 
     halves_ms, halves_n = plan.kernel_time(binding.PMK_KERNEL_CRT_HALVES)
     kern = {binding.KERNEL_NAMES[k]: plan.kernel_time(k) for k in binding.KERNEL_NAMES}
     plan.profile(False)
-    halves_avg_s = halves_ms / max(halves_n, 1) / 1e3
-    halves_work = nchunks * 2 * half_products(2048)  # algorithmic products per launch
+    # algorithmic products of all CRT-halves launches in one step, over their time
+    ub, uc = np.unique(bits_of, return_counts=True)
+    # in batch mode the 3072/4096-bit classes run in the batch kernel instead
+    halves_work = sum(2 * half_products(int(b)) * int(c) for b, c in zip(ub, uc)
+                      if not (batch and int(b) > 2048))
+    halves_avg_s = halves_ms / max(prof_steps, 1) / 1e3
     achieved = halves_work / halves_avg_s
 
     wall_s = t1 - t0
@@ -157,14 +178,16 @@ def main() -> int:
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": w.name, "message_bytes": len(msg), "chunks": nchunks, "keys": len(keys),
-                   "modulus_bits": 2048, "chunk_bytes": 252, "key_map": "round_robin", "public_exponent": 65537},
+                   "modulus_bits": sorted(set(int(k.bits) for k in keys)), "key_map": w.map_kind,
+                   "public_exponent": 65537},
         "dec_modexp_per_s": nchunks * args.steps / (dec_ms / 1e3),
         "enc_modexp_per_s": nchunks * args.steps / (enc_ms / 1e3),
         "dec_MiBps": mib * args.steps / (dec_ms / 1e3),
         "enc_MiBps": mib * args.steps / (enc_ms / 1e3),
         "enc_ms_per_step": enc_ms / args.steps,
         "dec_ms_per_step": dec_ms / args.steps,
-        "kernel_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in kern.items()},
+        "mode": args.mode,
+        "kernel_ms_per_step": {k: v[0] / max(prof_steps, 1) for k, v in kern.items()},
         "roundtrip_ok": bool(ok),
         "p99_request_ms": None,
         "roofline": {
@@ -175,13 +198,17 @@ def main() -> int:
             "unit": "Tmad/s (32x32->64 integer multiply-add)",
             "frac": achieved / PEAK_MAD_PER_S,
             "traffic": None,
-            "work_per_launch": halves_work,
-            "avg_launch_ms": halves_avg_s * 1e3,
+            "work_per_step": halves_work,
+            "avg_launch_ms": halves_ms / max(halves_n, 1),
+            "launches_per_step": halves_n / max(prof_steps, 1),
         },
         "paper_context": {"table3_100MB_dec_s": 0.0622, "table3_100MB_enc_s": 0.0009,
                           "hardware": "NVIDIA P100 + Xeon Silver 4114 (context only)"},
     }
-    if not args.no_cpu_baseline:
+    if args.config != 4:
+        out["metric"] = f"CRT decrypt modexp/s, workload {w.name}"
+        out["unit"] = "CRT decrypt modexp/s (whole encrypt+decrypt steps)"
+    if not args.no_cpu_baseline and args.config == 4:
         out["cpu_baseline"] = cpu_baseline(keys, msg, km, args.cpu_sample)
     plan.close()
     ctx.close()

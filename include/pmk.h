@@ -153,6 +153,33 @@ int pmk_encrypt_plan(pmk_plan *plan, const uint8_t *d_msg, uint8_t *d_ct, void *
 int pmk_decrypt_plan(pmk_plan *plan, const uint8_t *d_ct, uint8_t *d_msg, void *stream);
 
 /*
+ * Batched form (the parallel loops of Algorithm 1 run as a work queue): the
+ * exponentiations of every chunk under 3072- and 4096-bit keys run in ONE
+ * persistent kernel whose waves take work units (tiles of chunks under one
+ * key) from a device counter, 4096-bit units first; at the same time, on a
+ * second stream, the chunks under smaller keys run their own kernels, largest
+ * modulus first.  The whole sequence (packing, exponentiation, CRT
+ * recombination, unpacking) is captured once into a HIP graph per (input,
+ * output) buffer pair and replayed on `stream`; a new buffer pair or window
+ * setting recaptures it.  Results are byte-identical to pmk_encrypt_plan /
+ * pmk_decrypt_plan.  With profiling on (pmk_plan_profile) the sequence runs
+ * uncaptured so that each launch can be timed.  Same buffer rules and errors
+ * as the plan forms; a plan's batch calls must not overlap each other on
+ * different streams (they share the plan's work counter and scratch).
+ */
+int pmk_encrypt_batch(pmk_plan *plan, const uint8_t *d_msg, uint8_t *d_ct, void *stream);
+int pmk_decrypt_batch(pmk_plan *plan, const uint8_t *d_ct, uint8_t *d_msg, void *stream);
+
+/*
+ * Tuning: the window width of the fixed-window CRT exponentiation (2..6) of
+ * the size class holding `bits`-bit moduli.  Changing it never changes
+ * results, only speed; plans already made pick it up (graphs are recaptured).
+ * pmk_get_window returns the width or a negative status.
+ */
+int pmk_set_window(pmk_ctx *ctx, uint32_t bits, int win);
+int pmk_get_window(const pmk_ctx *ctx, uint32_t bits);
+
+/*
  * Wait for `stream`, then return and clear the plan's device-detected error
  * (PMK_OK or PMK_ERANGE).
  */
@@ -172,7 +199,8 @@ enum {
     PMK_KERNEL_CRT_HALVES = 2, /* m_p = c^dp mod p, m_q = c^dq mod q */
     PMK_KERNEL_GARNER = 3,     /* CRT recombination */
     PMK_KERNEL_UNPACK = 4,     /* limbs -> bytes */
-    PMK_KERNEL_KINDS = 5
+    PMK_KERNEL_BATCH = 5,      /* persistent batched exponentiation (1024..4096-bit classes) */
+    PMK_KERNEL_KINDS = 6
 };
 int pmk_plan_profile(pmk_plan *plan, int enable);
 int pmk_plan_kernel_time(pmk_plan *plan, int kind, double *ms_total, uint64_t *launches);

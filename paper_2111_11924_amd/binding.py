@@ -32,7 +32,8 @@ PMK_KERNEL_ENCRYPT = 1
 PMK_KERNEL_CRT_HALVES = 2
 PMK_KERNEL_GARNER = 3
 PMK_KERNEL_UNPACK = 4
-KERNEL_NAMES = {0: "pack", 1: "encrypt", 2: "crt_halves", 3: "garner", 4: "unpack"}
+PMK_KERNEL_BATCH = 5
+KERNEL_NAMES = {0: "pack", 1: "encrypt", 2: "crt_halves", 3: "garner", 4: "unpack", 5: "batch"}
 
 STATUS_NAMES = {0: "PMK_OK", -1: "PMK_EINVAL", -2: "PMK_EKEY", -3: "PMK_ERANGE", -4: "PMK_ESIZE",
                 -5: "PMK_ENOMEM", -6: "PMK_EDEVICE", -7: "PMK_EBUSY", -8: "PMK_EUNSUPPORTED"}
@@ -80,6 +81,10 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "pmk_plan_info": (C.c_int, [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]),
         "pmk_encrypt_plan": (C.c_int, [vp, vp, vp, vp]),
         "pmk_decrypt_plan": (C.c_int, [vp, vp, vp, vp]),
+        "pmk_encrypt_batch": (C.c_int, [vp, vp, vp, vp]),
+        "pmk_decrypt_batch": (C.c_int, [vp, vp, vp, vp]),
+        "pmk_set_window": (C.c_int, [vp, u32, C.c_int]),
+        "pmk_get_window": (C.c_int, [vp, u32]),
         "pmk_plan_check": (C.c_int, [vp, vp]),
         "pmk_plan_profile": (C.c_int, [vp, C.c_int]),
         "pmk_plan_kernel_time": (C.c_int, [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(u64)]),
@@ -231,6 +236,22 @@ def pmk_decrypt_plan(plan: int, d_ct, d_msg, stream=None, ctx: Optional[int] = N
     _check(load_library().pmk_decrypt_plan(plan, _dev_ptr(d_ct), _dev_ptr(d_msg), _stream(stream)), ctx)
 
 
+def pmk_encrypt_batch(plan: int, d_msg, d_ct, stream=None, ctx: Optional[int] = None) -> None:
+    _check(load_library().pmk_encrypt_batch(plan, _dev_ptr(d_msg), _dev_ptr(d_ct), _stream(stream)), ctx)
+
+
+def pmk_decrypt_batch(plan: int, d_ct, d_msg, stream=None, ctx: Optional[int] = None) -> None:
+    _check(load_library().pmk_decrypt_batch(plan, _dev_ptr(d_ct), _dev_ptr(d_msg), _stream(stream)), ctx)
+
+
+def pmk_set_window(ctx: int, bits: int, win: int) -> None:
+    _check(load_library().pmk_set_window(ctx, int(bits), int(win)), ctx)
+
+
+def pmk_get_window(ctx: int, bits: int) -> int:
+    return load_library().pmk_get_window(ctx, int(bits))
+
+
 def pmk_plan_check(plan: int, stream=None) -> int:
     return load_library().pmk_plan_check(plan, _stream(stream))
 
@@ -267,20 +288,25 @@ class Plan:
         self.handle, self.ct_len = pmk_plan_create(ctx.handle, key_map, msg_len)
         self.msg_len = int(msg_len)
 
-    def encrypt(self, msg, ct=None, stream=None):
+    def encrypt(self, msg, ct=None, stream=None, batch: bool = False):
+        """Encrypt `msg` (device tensor) into `ct`; batch=True uses the
+        graph-captured persistent path (pmk_encrypt_batch)."""
         import torch
 
         if ct is None:
             ct = torch.empty(max(self.ct_len, 4), dtype=torch.uint8, device=msg.device)
-        pmk_encrypt_plan(self.handle, msg, ct, stream, self.ctx.handle)
+        fn = pmk_encrypt_batch if batch else pmk_encrypt_plan
+        fn(self.handle, msg, ct, stream, self.ctx.handle)
         return ct
 
-    def decrypt(self, ct, msg=None, stream=None):
+    def decrypt(self, ct, msg=None, stream=None, batch: bool = False):
+        """CRT-decrypt `ct` into `msg`; batch=True uses pmk_decrypt_batch."""
         import torch
 
         if msg is None:
             msg = torch.empty(max(self.msg_len, 4), dtype=torch.uint8, device=ct.device)
-        pmk_decrypt_plan(self.handle, ct, msg, stream, self.ctx.handle)
+        fn = pmk_decrypt_batch if batch else pmk_decrypt_plan
+        fn(self.handle, ct, msg, stream, self.ctx.handle)
         return msg
 
     def check(self, stream=None) -> int:
@@ -317,6 +343,12 @@ class Context:
 
     def load_keys(self, keys: Sequence) -> None:
         pmk_keys_load(self.handle, keys)
+
+    def set_window(self, bits: int, win: int) -> None:
+        pmk_set_window(self.handle, bits, win)
+
+    def window(self, bits: int) -> int:
+        return pmk_get_window(self.handle, bits)
 
     def plan(self, key_map, msg_len: int) -> Plan:
         p = Plan(self, key_map, msg_len)

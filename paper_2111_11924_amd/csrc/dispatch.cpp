@@ -11,7 +11,8 @@ namespace pmk {
     int launch_encrypt_##B(const ClassRun &, hipStream_t);                                 \
     int launch_halves_##B(const ClassRun &, hipStream_t);                                  \
     int launch_garner_##B(const ClassRun &, hipStream_t);                                  \
-    uint32_t wave_slots_##B(int, int);
+    uint32_t wave_slots_##B(int, int);                                                     \
+    uint64_t slot_words_##B(int);
 PMK_DECLARE(128)
 PMK_DECLARE(256)
 PMK_DECLARE(512)
@@ -54,10 +55,16 @@ int launch_garner(const ClassRun &r, void *stream) {
 }
 
 uint64_t table_words_per_slot(int cls, int decrypt) {
-    const int bits = kClassBits[cls];
-    const Geom g = make_geom(bits);
-    if (!decrypt) return (uint64_t)2 * (g.nlf / lanes_full(bits)) * kTile;
-    return (uint64_t)(1u << window_for(bits / 2)) * (g.nlh / lanes_half(bits)) * kTile;
+    switch (cls) {
+        case 0: return slot_words_128(decrypt);
+        case 1: return slot_words_256(decrypt);
+        case 2: return slot_words_512(decrypt);
+        case 3: return slot_words_1024(decrypt);
+        case 4: return slot_words_2048(decrypt);
+        case 5: return slot_words_3072(decrypt);
+        case 6: return slot_words_4096(decrypt);
+        default: return 0;
+    }
 }
 
 uint32_t exp_units(int cls, int decrypt, uint32_t ntiles) {

@@ -125,6 +125,14 @@ PMK_DEV void load_limbs(uint32_t (&x)[NL], const uint32_t *p) {
 #pragma unroll
     for (int j = 0; j < NL; ++j) x[j] = p[j];
 }
+// wave-uniform values (key material of a key-uniform tile): readfirstlane keeps
+// them in scalar registers even where the compiler cannot prove the load uniform
+PMK_DEV uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+template <int NL>
+PMK_DEV void load_uniform(uint32_t (&x)[NL], const uint32_t *p) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) x[j] = uni(p[j]);
+}
 
 // An opaque copy of a wave-uniform pointer.  Table addresses are otherwise
 // loop-invariant, and the compiler hoists all NL per-limb addresses of every
@@ -182,51 +190,44 @@ PMK_DEV uint32_t wave_max(uint32_t v) {
 // ------------------------------------------------------------------ encryption
 // One lane per chunk: x~ = MM(x, R^2), then for the exponent bits below the top
 // one: square, and multiply by x~ where the bit is set; MM(., 1) leaves
-// Montgomery form.
+// Montgomery form.  `tbl` is the calling wave's scratch slot.
 template <int CB>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encrypt_kernel(
-    const uint32_t *__restrict__ keys, const uint32_t *__restrict__ tile_key, uint32_t ntiles,
-    const uint32_t *__restrict__ x32, uint32_t *__restrict__ y32, uint32_t *__restrict__ table) {
+PMK_DEV void encrypt_unit(const ClassRun r, uint32_t tile, uint32_t *tbl) {
     constexpr Geom G = make_geom(CB);
     constexpr int NL = G.nlf, LB = G.lbf, S = G.S;
     const int lane = threadIdx.x;
-    uint32_t *tbl = table + (size_t)blockIdx.x * 2 * NL * kTile;
+    const uint32_t *kr = r.keys + (size_t)uni(r.tile_key[tile]) * G.stride;  // wave-uniform
+    uint32_t n[NL];
+    load_uniform(n, kr + G.off_nf);
+    const uint32_t n0 = uni(kr[G.off_n0f]);
+    const uint32_t e0 = uni(kr[G.off_e]), e1 = uni(kr[G.off_e + 1]);
+    const int top = (int)uni(kr[G.off_ebits]) - 1;
 
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t *kr = keys + (size_t)tile_key[tile] * G.stride;  // wave-uniform
-        uint32_t n[NL];
-        load_limbs(n, kr + G.off_nf);
-        const uint32_t n0 = kr[G.off_n0f];
-        const uint32_t e0 = kr[G.off_e], e1 = kr[G.off_e + 1];
-        const int top = (int)kr[G.off_ebits] - 1;
-
-        uint32_t acc[NL], b[NL];
-        {
-            uint32_t w[S];
+    uint32_t acc[NL], b[NL];
+    {
+        uint32_t w[S];
 #pragma unroll
-            for (int k = 0; k < S; ++k) w[k] = x32[((size_t)tile * S + k) * kTile + lane];
+        for (int k = 0; k < S; ++k) w[k] = r.x32[((size_t)tile * S + k) * kTile + lane];
 #pragma unroll
-            for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j);
-        }
-        load_limbs(b, kr + G.off_rrf);
-        mont_mul<NL, LB>(acc, acc, b, n, n0);  // x~ = x R mod N
-        store_entry(tbl, 1, lane, acc);
-        for (int bit = top - 1; bit >= 0; --bit) {
-            mont_sqr<NL, LB>(acc, acc, n, n0);
-            const uint32_t eb = bit >= 32 ? (e1 >> (bit - 32)) & 1u : (e0 >> bit) & 1u;
-            if (eb) {
-                load_entry(b, tbl, 1, lane);
-                mont_mul<NL, LB>(acc, acc, b, n, n0);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
-        mont_mul<NL, LB>(acc, acc, b, n, n0);  // leave Montgomery form
-        canonicalize<NL, LB>(acc, n);
-#pragma unroll
-        for (int k = 0; k < S; ++k)
-            y32[((size_t)tile * S + k) * kTile + lane] = radix_word<NL, LB>(acc, k);
+        for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j);
     }
+    load_limbs(b, kr + G.off_rrf);
+    mont_mul<NL, LB>(acc, acc, b, n, n0);  // x~ = x R mod N
+    store_entry(tbl, 1, lane, acc);
+    for (int bit = top - 1; bit >= 0; --bit) {
+        mont_sqr<NL, LB>(acc, acc, n, n0);
+        const uint32_t eb = bit >= 32 ? (e1 >> (bit - 32)) & 1u : (e0 >> bit) & 1u;
+        if (eb) {
+            load_entry(b, tbl, 1, lane);
+            mont_mul<NL, LB>(acc, acc, b, n, n0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
+    mont_mul<NL, LB>(acc, acc, b, n, n0);  // leave Montgomery form
+    canonicalize<NL, LB>(acc, n);
+#pragma unroll
+    for (int k = 0; k < S; ++k) r.y32[((size_t)tile * S + k) * kTile + lane] = radix_word<NL, LB>(acc, k);
 }
 
 // ------------------------------------------------------------------ CRT halves
@@ -234,7 +235,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
 // Reduction and entry into Montgomery form at once:
 // x~ = MM(c_lo, R^2) + MM(c_hi, R^3) = c R mod p (below 4p), with
 // c = c_hi 2^(LB NL) + c_lo.  Table T[k] = x~^k (T[0] = R mod p), then
-// fixed windows from the top: WIN squarings and one multiply by T[digit].
+// fixed windows of r.win bits from the top: win squarings and one multiply by
+// T[digit].
 PMK_DEV uint32_t digit_of(const uint32_t *d, int SH, int k, int w) {
     const int pos = k * w;
     const int wd = pos >> 5, sh = pos & 31;
@@ -243,113 +245,105 @@ PMK_DEV uint32_t digit_of(const uint32_t *d, int SH, int k, int w) {
     return (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & ((1u << w) - 1u);
 }
 
-template <int CB, int WIN>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void halves_kernel(
-    const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc,
-    const uint32_t *__restrict__ tile_key, uint32_t ntiles, const uint32_t *__restrict__ x32,
-    uint32_t *__restrict__ half, uint32_t *__restrict__ table, uint32_t *__restrict__ err) {
+template <int CB>
+PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl) {
     constexpr Geom G = make_geom(CB);
     constexpr int NL = G.nlh, LB = G.lbh, S = G.S, SH = G.SH;
-    constexpr int T = 1 << WIN;
-    constexpr int NW = (32 * SH + WIN - 1) / WIN;  // digits of the exponent
+    const int win = r.win, T = 1 << win;
+    const int NW = (32 * SH + win - 1) / win;  // digits of the exponent
     const int lane = threadIdx.x;
-    const uint32_t njobs = 2 * ntiles;
-    uint32_t *tbl = table + (size_t)blockIdx.x * T * NL * kTile;
+    const uint32_t tile = jt >> 1;
+    const int h = jt & 1;
+    const uint32_t *kr = r.keys + (size_t)uni(r.tile_key[tile]) * G.stride;  // wave-uniform
+    const uint32_t *hr = kr + G.off_half[0] + h * G.h_size;
+    uint32_t n[NL];
+    load_uniform(n, hr + G.h_m);
+    const uint32_t n0 = uni(hr[G.h_m0]);
+    const uint32_t *dexp = hr + G.h_d;
+    const uint32_t *one_h = hr + G.h_one;
 
-    for (uint32_t jt = blockIdx.x; jt < njobs; jt += gridDim.x) {
-        const uint32_t tile = jt >> 1;
-        const int h = jt & 1;
-        const uint32_t *kr = keys + (size_t)tile_key[tile] * G.stride;  // wave-uniform
-        const uint32_t *hr = kr + G.off_half[0] + h * G.h_size;
-        uint32_t n[NL];
-        load_limbs(n, hr + G.h_m);
-        const uint32_t n0 = hr[G.h_m0];
-        const uint32_t *dexp = hr + G.h_d;
-        const uint32_t *one_h = hr + G.h_one;
-
-        uint32_t acc[NL], b[NL];
-        {
-            uint32_t w[S];
+    uint32_t acc[NL], b[NL];
+    {
+        uint32_t w[S];
 #pragma unroll
-            for (int k = 0; k < S; ++k) w[k] = x32[((size_t)tile * S + k) * kTile + lane];
-            if (h == 0 && desc[(size_t)tile * kTile + lane].msg_len) {
-                // C must lie in Z_N: compare with N, most significant word first
-                const uint32_t *n32 = kr + G.off_n32;
-                int cmp = 0;
+        for (int k = 0; k < S; ++k) w[k] = r.x32[((size_t)tile * S + k) * kTile + lane];
+        if (h == 0 && r.desc[(size_t)tile * kTile + lane].msg_len) {
+            // C must lie in Z_N: compare with N, most significant word first
+            const uint32_t *n32 = kr + G.off_n32;
+            int cmp = 0;
 #pragma unroll
-                for (int k = S - 1; k >= 0; --k) cmp = cmp ? cmp : (w[k] > n32[k]) - (w[k] < n32[k]);
-                if (cmp >= 0) atomicOr(err, 1u);
-            }
-#pragma unroll
-            for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j + NL);
-            store_entry(tbl, 0, lane, acc);  // c_hi, parked in entry 0 until it is used
-#pragma unroll
-            for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j);
+            for (int k = S - 1; k >= 0; --k) cmp = cmp ? cmp : (w[k] > n32[k]) - (w[k] < n32[k]);
+            if (cmp >= 0) atomicOr(r.err, 1u);
         }
-        load_limbs(b, hr + G.h_rr);
+#pragma unroll
+        for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j + NL);
+        store_entry(tbl, 0, lane, acc);  // c_hi, parked in entry 0 until it is used
+#pragma unroll
+        for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j);
+    }
+    load_limbs(b, hr + G.h_rr);
 
-        // One call site each for the product and the square keeps the loop's
-        // code within the instruction cache.  Phases:
-        //   0  MM(c_lo, R^2) = c_lo R mod p            (parked in T[1])
-        //   1  MM(c_hi, R^3) = c_hi R^2 mod p; x~ = sum (below 4p), T[1] = x~
-        //   2  T[e] = T[e-1] x~ for e = 2 .. T-1
-        //   3  per digit below the top one: WIN squarings, then times T[digit]
-        //   4  MM(., 1): leave Montgomery form
-        int phase = 0, e = 2, digit = NW - 2, sq = 0;
-        for (;;) {
-            if (phase == 3) {
-                if (sq < WIN) {
-                    mont_sqr<NL, LB>(acc, acc, n, n0);
-                    ++sq;
-                    continue;
-                }
-                load_digit(b, tbl, digit_of(dexp, SH, digit, WIN), lane, one_h);
-            }
-            mont_mul<NL, LB>(acc, acc, b, n, n0);
-            if (phase == 4) break;
-            if (phase == 0) {
-                store_entry(tbl, 1, lane, acc);
-                load_entry(acc, tbl, 0, lane);
-                load_limbs(b, hr + G.h_rrr);
-                phase = 1;
+    // One call site each for the product and the square keeps the loop's
+    // code within the instruction cache.  Phases:
+    //   0  MM(c_lo, R^2) = c_lo R mod p            (parked in T[1])
+    //   1  MM(c_hi, R^3) = c_hi R^2 mod p; x~ = sum (below 4p), T[1] = x~
+    //   2  T[e] = T[e-1] x~ for e = 2 .. T-1
+    //   3  per digit below the top one: win squarings, then times T[digit]
+    //   4  MM(., 1): leave Montgomery form
+    int phase = 0, e = 2, digit = NW - 2, sq = 0;
+    for (;;) {
+        if (phase == 3) {
+            if (sq < win) {
+                mont_sqr<NL, LB>(acc, acc, n, n0);
+                ++sq;
                 continue;
             }
-            if (phase == 1) {
-                load_entry(b, tbl, 1, lane);
-                uint32_t c = 0;
-#pragma unroll
-                for (int j = 0; j < NL; ++j) {
-                    const uint32_t v = acc[j] + b[j] + c;
-                    acc[j] = v & Radix<LB>::MASK;
-                    c = v >> LB;
-                }
-                store_entry(tbl, 1, lane, acc);
-#pragma unroll
-                for (int j = 0; j < NL; ++j) b[j] = acc[j];  // x~, the multiplier of phase 2
-                phase = 2;
-            } else if (phase == 2) {
-                store_entry(tbl, e, lane, acc);
-                ++e;
-            } else {  // phase 3: the digit's multiply is done
-                --digit;
-                sq = 0;
-            }
-            if (phase == 2 && e == T) {
-                // table complete: start from the top digit
-                load_digit(acc, tbl, digit_of(dexp, SH, NW - 1, WIN), lane, one_h);
-                phase = 3;
-            }
-            if (phase == 3 && digit < 0) {
-#pragma unroll
-                for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
-                phase = 4;
-            }
+            load_digit(b, tbl, digit_of(dexp, SH, digit, win), lane, one_h);
         }
-        canonicalize<NL, LB>(acc, n);
-        uint32_t *dst = half + ((size_t)jt * NL) * kTile + lane;
+        mont_mul<NL, LB>(acc, acc, b, n, n0);
+        if (phase == 4) break;
+        if (phase == 0) {
+            store_entry(tbl, 1, lane, acc);
+            load_entry(acc, tbl, 0, lane);
+            load_limbs(b, hr + G.h_rrr);
+            phase = 1;
+            continue;
+        }
+        if (phase == 1) {
+            load_entry(b, tbl, 1, lane);
+            uint32_t c = 0;
 #pragma unroll
-        for (int j = 0; j < NL; ++j) dst[(size_t)j * kTile] = acc[j];
+            for (int j = 0; j < NL; ++j) {
+                const uint32_t v = acc[j] + b[j] + c;
+                acc[j] = v & Radix<LB>::MASK;
+                c = v >> LB;
+            }
+            store_entry(tbl, 1, lane, acc);
+#pragma unroll
+            for (int j = 0; j < NL; ++j) b[j] = acc[j];  // x~, the multiplier of phase 2
+            phase = 2;
+        } else if (phase == 2) {
+            store_entry(tbl, e, lane, acc);
+            ++e;
+        } else {  // phase 3: the digit's multiply is done
+            --digit;
+            sq = 0;
+        }
+        if (phase == 2 && e == T) {
+            // table complete: start from the top digit
+            load_digit(acc, tbl, digit_of(dexp, SH, NW - 1, win), lane, one_h);
+            phase = 3;
+        }
+        if (phase == 3 && digit < 0) {
+#pragma unroll
+            for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
+            phase = 4;
+        }
     }
+    canonicalize<NL, LB>(acc, n);
+    uint32_t *dst = r.half + ((size_t)jt * NL) * kTile + lane;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) dst[(size_t)j * kTile] = acc[j];
 }
 
 // ------------------------------------------------------------------ lane groups
@@ -402,191 +396,214 @@ PMK_DEV void limbs_from_words(uint32_t (&x)[K], const uint32_t *col, int ng, int
     }
 }
 
+// LDS words the lane-group units of a class need
 template <int CB>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encrypt_lanes_kernel(
-    const uint32_t *__restrict__ keys, const uint32_t *__restrict__ tile_key, uint32_t ntiles,
-    const uint32_t *__restrict__ x32, uint32_t *__restrict__ y32, uint32_t *__restrict__ table) {
+constexpr int lds_words_enc() {
+    return (make_geom(CB).nlf > make_geom(CB).S ? make_geom(CB).nlf : make_geom(CB).S) * (64 / lanes_full(CB));
+}
+template <int CB>
+constexpr int lds_words_dec() {
+    return (make_geom(CB).nlh > make_geom(CB).S ? make_geom(CB).nlh : make_geom(CB).S) * (64 / lanes_half(CB));
+}
+
+template <int CB>
+PMK_DEV void encrypt_lanes_unit(const ClassRun r, uint32_t tile, uint32_t *tbl, uint32_t *lds) {
     constexpr Geom G = make_geom(CB);
     constexpr int L = lanes_full(CB), NLT = G.nlf, K = NLT / L, LB = G.lbf, S = G.S;
     constexpr int NG = 64 / L;  // groups (chunks) per wavefront
-    constexpr int ROWS = NLT > S ? NLT : S;
-    __shared__ uint32_t lds[ROWS * NG];
     const int lane = threadIdx.x, pos = lane % L, grp = lane / L;
     uint32_t *col = lds + grp;
-    uint32_t *tbl = table + (size_t)blockIdx.x * 2 * K * kTile;
+    const uint32_t *kr = r.keys + (size_t)uni(r.tile_key[tile]) * G.stride;  // wave-uniform
+    uint32_t n[K];
+    load_limbs(n, fresh_v(kr + G.off_nf + pos * K));
+    const uint32_t n0 = uni(kr[G.off_n0f]);
+    const uint32_t e0 = uni(kr[G.off_e]), e1 = uni(kr[G.off_e + 1]);
+    const int top = (int)uni(kr[G.off_ebits]) - 1;
 
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t *kr = keys + (size_t)tile_key[tile] * G.stride;  // wave-uniform
-        uint32_t n[K];
-        load_limbs(n, fresh_v(kr + G.off_nf + pos * K));
-        const uint32_t n0 = kr[G.off_n0f];
-        const uint32_t e0 = kr[G.off_e], e1 = kr[G.off_e + 1];
-        const int top = (int)kr[G.off_ebits] - 1;
+    uint32_t acc[K];
+    for (int k = pos; k < S; k += L) col[k * NG] = r.x32[((size_t)tile * S + k) * NG + grp];
+    limbs_from_words<K, LB>(acc, col, NG, S, pos * K);
+    stage_mem<K>(col, NG, pos, kr + G.off_rrf + pos * K, 1);
 
-        uint32_t acc[K];
-        for (int k = pos; k < S; k += L) col[k * NG] = x32[((size_t)tile * S + k) * NG + grp];
-        limbs_from_words<K, LB>(acc, col, NG, S, pos * K);
-        stage_mem<K>(col, NG, pos, kr + G.off_rrf + pos * K, 1);
-
-        // phase 0: to Montgomery, 1: square, 2: multiply by x~, 3: from Montgomery
-        int phase = 0, bit = top - 1;
-        for (;;) {
-            mont_mul_lanes<NLT, LB, L>(acc, acc, col, NG, n, n0, pos);
-            if (phase == 3) break;
-            if (phase == 0) {
-                store_entry(tbl, 1, lane, acc);  // x~
-            } else if (phase == 1) {
-                const uint32_t eb = bit >= 32 ? (e1 >> (bit - 32)) & 1u : (e0 >> bit) & 1u;
-                if (eb) {
-                    phase = 2;
-                    stage_mem<K>(col, NG, pos, fresh(tbl) + K * kTile + lane, kTile);
-                    continue;
-                }
-            }
-            // next bit, or leave
-            if (phase != 0) --bit;
-            if (phase == 0) bit = top - 1;
-            if (bit >= 0) {
-                phase = 1;
-                stage_limbs(col, NG, pos, acc);
-            } else {
-                phase = 3;
-                stage_one<K>(col, NG, pos);
+    // phase 0: to Montgomery, 1: square, 2: multiply by x~, 3: from Montgomery
+    int phase = 0, bit = top - 1;
+    for (;;) {
+        mont_mul_lanes<NLT, LB, L>(acc, acc, col, NG, n, n0, pos);
+        if (phase == 3) break;
+        if (phase == 0) {
+            store_entry(tbl, 1, lane, acc);  // x~
+        } else if (phase == 1) {
+            const uint32_t eb = bit >= 32 ? (e1 >> (bit - 32)) & 1u : (e0 >> bit) & 1u;
+            if (eb) {
+                phase = 2;
+                stage_mem<K>(col, NG, pos, fresh(tbl) + K * kTile + lane, kTile);
+                continue;
             }
         }
-        canonicalize_lanes<K, LB, L>(acc, n, pos);
-        // radix limbs -> 32-bit words through the group's column
-        stage_limbs(col, NG, pos, acc);
-        for (int k = pos; k < S; k += L) {
-            const int bit = 32 * k, j = bit / LB, sh = bit % LB;
-            const uint64_t l0 = j < NLT ? col[j * NG] : 0u;
-            const uint64_t l1 = j + 1 < NLT ? col[(j + 1) * NG] : 0u;
-            const uint64_t l2 = j + 2 < NLT ? col[(j + 2) * NG] : 0u;
-            y32[((size_t)tile * S + k) * NG + grp] = (uint32_t)((l0 >> sh) | (l1 << (LB - sh)) | (l2 << (2 * LB - sh)));
+        // next bit, or leave
+        if (phase != 0) --bit;
+        if (phase == 0) bit = top - 1;
+        if (bit >= 0) {
+            phase = 1;
+            stage_limbs(col, NG, pos, acc);
+        } else {
+            phase = 3;
+            stage_one<K>(col, NG, pos);
         }
+    }
+    canonicalize_lanes<K, LB, L>(acc, n, pos);
+    // radix limbs -> 32-bit words through the group's column
+    stage_limbs(col, NG, pos, acc);
+    for (int k = pos; k < S; k += L) {
+        const int bit = 32 * k, j = bit / LB, sh = bit % LB;
+        const uint64_t l0 = j < NLT ? col[j * NG] : 0u;
+        const uint64_t l1 = j + 1 < NLT ? col[(j + 1) * NG] : 0u;
+        const uint64_t l2 = j + 2 < NLT ? col[(j + 2) * NG] : 0u;
+        r.y32[((size_t)tile * S + k) * NG + grp] = (uint32_t)((l0 >> sh) | (l1 << (LB - sh)) | (l2 << (2 * LB - sh)));
     }
 }
 
 // CRT halves with 2 lanes per number: a wavefront holds the 16 chunks of a tile
 // twice, lanes 0-31 modulo p and lanes 32-63 modulo q.
-template <int CB, int WIN>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void halves_lanes_kernel(
-    const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc,
-    const uint32_t *__restrict__ tile_key, uint32_t ntiles, const uint32_t *__restrict__ x32,
-    uint32_t *__restrict__ half, uint32_t *__restrict__ table, uint32_t *__restrict__ err) {
+template <int CB>
+PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t tile, uint32_t *tbl, uint32_t *lds) {
     constexpr Geom G = make_geom(CB);
     constexpr int L = lanes_half(CB), NLT = G.nlh, K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
     constexpr int CPT = chunks_per_tile(CB);
     constexpr int NG = 64 / L;  // groups per wavefront = 2 * CPT
     static_assert(NG == 2 * CPT, "one wavefront holds both halves of a tile");
-    constexpr int T = 1 << WIN;
-    constexpr int NW = (32 * SH + WIN - 1) / WIN;
-    constexpr int ROWS = NLT > S ? NLT : S;
-    __shared__ uint32_t lds[ROWS * NG];
+    const int win = r.win, T = 1 << win;
+    const int NW = (32 * SH + win - 1) / win;
     const int lane = threadIdx.x, pos = lane % L, grp = lane / L;
     const int c = grp % CPT, h = grp / CPT;
     uint32_t *col = lds + grp;
-    uint32_t *tbl = table + (size_t)blockIdx.x * T * K * kTile;
+    const uint32_t *kr = r.keys + (size_t)uni(r.tile_key[tile]) * G.stride;
+    const uint32_t *hr = kr + G.off_half[0] + h * G.h_size;  // p for lanes 0-31, q for 32-63
+    uint32_t n[K];
+    load_limbs(n, fresh_v(hr + G.h_m + pos * K));
+    const uint32_t n0 = hr[G.h_m0];
+    const uint32_t *dexp = hr + G.h_d;
 
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t *kr = keys + (size_t)tile_key[tile] * G.stride;
-        const uint32_t *hr = kr + G.off_half[0] + h * G.h_size;  // p for lanes 0-31, q for 32-63
-        uint32_t n[K];
-        load_limbs(n, fresh_v(hr + G.h_m + pos * K));
-        const uint32_t n0 = hr[G.h_m0];
-        const uint32_t *dexp = hr + G.h_d;
-
-        uint32_t acc[K];
-        for (int k = pos; k < S; k += L) col[k * NG] = x32[((size_t)tile * S + k) * CPT + c];
-        if (h == 0 && pos == 0 && desc[(size_t)tile * CPT + c].msg_len) {
-            // C must lie in Z_N
-            const uint32_t *n32 = kr + G.off_n32;
-            int cmp = 0;
-            for (int k = S - 1; k >= 0 && cmp == 0; --k) {
-                const uint32_t w = col[k * NG];
-                cmp = (w > n32[k]) - (w < n32[k]);
-            }
-            if (cmp >= 0) atomicOr(err, 1u);
+    uint32_t acc[K];
+    for (int k = pos; k < S; k += L) col[k * NG] = r.x32[((size_t)tile * S + k) * CPT + c];
+    if (h == 0 && pos == 0 && r.desc[(size_t)tile * CPT + c].msg_len) {
+        // C must lie in Z_N
+        const uint32_t *n32 = kr + G.off_n32;
+        int cmp = 0;
+        for (int k = S - 1; k >= 0 && cmp == 0; --k) {
+            const uint32_t w = col[k * NG];
+            cmp = (w > n32[k]) - (w < n32[k]);
         }
-        limbs_from_words<K, LB>(acc, col, NG, S, NLT + pos * K);  // c_hi
-        store_entry(tbl, 0, lane, acc);
-        limbs_from_words<K, LB>(acc, col, NG, S, pos * K);        // c_lo
-        stage_mem<K>(col, NG, pos, hr + G.h_rr + pos * K, 1);
+        if (cmp >= 0) atomicOr(r.err, 1u);
+    }
+    limbs_from_words<K, LB>(acc, col, NG, S, NLT + pos * K);  // c_hi
+    store_entry(tbl, 0, lane, acc);
+    limbs_from_words<K, LB>(acc, col, NG, S, pos * K);        // c_lo
+    stage_mem<K>(col, NG, pos, hr + G.h_rr + pos * K, 1);
 
-        // phases as in halves_kernel: 0 c_lo R, 1 c_hi R^2 and x~, 2 table,
-        // 3 digits (squarings, then a table product), 4 leave Montgomery form
-        int phase = 0, e = 2, digit = NW - 2, sq = 0;
-        for (;;) {
-            mont_mul_lanes<NLT, LB, L>(acc, acc, col, NG, n, n0, pos);
-            if (phase == 4) break;
-            if (phase == 0) {
-                store_entry(tbl, 1, lane, acc);
-                load_entry(acc, tbl, 0, lane);
-                stage_mem<K>(col, NG, pos, hr + G.h_rrr + pos * K, 1);
-                phase = 1;
-                continue;
+    // phases as in halves_unit: 0 c_lo R, 1 c_hi R^2 and x~, 2 table,
+    // 3 digits (squarings, then a table product), 4 leave Montgomery form
+    int phase = 0, e = 2, digit = NW - 2, sq = 0;
+    for (;;) {
+        mont_mul_lanes<NLT, LB, L>(acc, acc, col, NG, n, n0, pos);
+        if (phase == 4) break;
+        if (phase == 0) {
+            store_entry(tbl, 1, lane, acc);
+            load_entry(acc, tbl, 0, lane);
+            stage_mem<K>(col, NG, pos, hr + G.h_rrr + pos * K, 1);
+            phase = 1;
+            continue;
+        }
+        if (phase == 1) {
+            // x~ = acc + T[1]: limb-wise, carries across the group's lanes
+            uint32_t lo[K];
+            load_entry(lo, tbl, 1, lane);
+            uint32_t cy = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const uint32_t v = acc[j] + lo[j] + cy;
+                acc[j] = v & Radix<LB>::MASK;
+                cy = v >> LB;
             }
-            if (phase == 1) {
-                // x~ = acc + T[1]: limb-wise, carries across the group's lanes
-                uint32_t lo[K];
-                load_entry(lo, tbl, 1, lane);
-                uint32_t cy = 0;
+#pragma unroll
+            for (int s = 1; s < L; ++s) {
+                uint32_t cin = grp_prev<L>(cy, pos);
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
-                    const uint32_t v = acc[j] + lo[j] + cy;
+                    const uint32_t v = acc[j] + cin;
                     acc[j] = v & Radix<LB>::MASK;
-                    cy = v >> LB;
+                    cin = v >> LB;
                 }
-#pragma unroll
-                for (int s = 1; s < L; ++s) {
-                    uint32_t cin = grp_prev<L>(cy, pos);
-                    cy = 0;
-#pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        const uint32_t v = acc[j] + cin;
-                        acc[j] = v & Radix<LB>::MASK;
-                        cin = v >> LB;
-                    }
-                    cy = cin;
-                }
-                store_entry(tbl, 1, lane, acc);
-                stage_limbs(col, NG, pos, acc);  // x~ stays staged for the table
-                phase = 2;
-                continue;
+                cy = cin;
             }
-            if (phase == 2) {
-                store_entry(tbl, e, lane, acc);
-                if (++e < T) continue;
-                const uint32_t dg = digit_of(dexp, SH, NW - 1, WIN);
-                if (dg)
-                    load_entry(acc, tbl, dg, lane);
-                else
-                    load_limbs(acc, fresh_v(hr + G.h_one + pos * K));
-                phase = 3;
-            } else if (sq == WIN + 1) {  // phase 3: a digit's product is done
-                --digit;
-                sq = 0;
-            }
-            // phase 3: next squaring, the digit's product, or the end
-            if (digit < 0) {
-                stage_one<K>(col, NG, pos);
-                phase = 4;
-            } else if (sq < WIN) {
-                stage_limbs(col, NG, pos, acc);
-                ++sq;
-            } else {
-                const uint32_t dg = digit_of(dexp, SH, digit, WIN);
-                if (dg)
-                    stage_mem<K>(col, NG, pos, fresh(tbl) + (size_t)dg * K * kTile + lane, kTile);
-                else
-                    stage_mem<K>(col, NG, pos, hr + G.h_one + pos * K, 1);
-                sq = WIN + 1;
-            }
+            store_entry(tbl, 1, lane, acc);
+            stage_limbs(col, NG, pos, acc);  // x~ stays staged for the table
+            phase = 2;
+            continue;
         }
-        canonicalize_lanes<K, LB, L>(acc, n, pos);
-        uint32_t *dst = half + ((size_t)(2 * tile + h) * NLT + pos * K) * CPT + c;
+        if (phase == 2) {
+            store_entry(tbl, e, lane, acc);
+            if (++e < T) continue;
+            const uint32_t dg = digit_of(dexp, SH, NW - 1, win);
+            if (dg)
+                load_entry(acc, tbl, dg, lane);
+            else
+                load_limbs(acc, fresh_v(hr + G.h_one + pos * K));
+            phase = 3;
+        } else if (sq == win + 1) {  // phase 3: a digit's product is done
+            --digit;
+            sq = 0;
+        }
+        // phase 3: next squaring, the digit's product, or the end
+        if (digit < 0) {
+            stage_one<K>(col, NG, pos);
+            phase = 4;
+        } else if (sq < win) {
+            stage_limbs(col, NG, pos, acc);
+            ++sq;
+        } else {
+            const uint32_t dg = digit_of(dexp, SH, digit, win);
+            if (dg)
+                stage_mem<K>(col, NG, pos, fresh(tbl) + (size_t)dg * K * kTile + lane, kTile);
+            else
+                stage_mem<K>(col, NG, pos, hr + G.h_one + pos * K, 1);
+            sq = win + 1;
+        }
+    }
+    canonicalize_lanes<K, LB, L>(acc, n, pos);
+    uint32_t *dst = r.half + ((size_t)(2 * tile + h) * NLT + pos * K) * CPT + c;
 #pragma unroll
-        for (int j = 0; j < K; ++j) dst[(size_t)j * CPT] = acc[j];
+    for (int j = 0; j < K; ++j) dst[(size_t)j * CPT] = acc[j];
+}
+
+// ------------------------------------------------------------------ per-class kernels
+// Persistent grids: block b owns table slot b and walks units b, b + grid, ...
+template <int CB>
+constexpr int kEncWaves = lanes_full(CB) > 1 ? 2 : 2;
+template <int CB>
+constexpr int kDecWaves = lanes_half(CB) > 1 ? 2 : 3;
+
+template <int CB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kEncWaves<CB>))) void encrypt_kernel(
+    ClassRun r, uint64_t slot_words) {
+    uint32_t *tbl = r.table + (size_t)blockIdx.x * slot_words;
+    if constexpr (lanes_full(CB) > 1) {
+        __shared__ uint32_t lds[lds_words_enc<CB>()];
+        for (uint32_t u = blockIdx.x; u < r.ntiles; u += gridDim.x) encrypt_lanes_unit<CB>(r, u, tbl, lds);
+    } else {
+        for (uint32_t u = blockIdx.x; u < r.ntiles; u += gridDim.x) encrypt_unit<CB>(r, u, tbl);
+    }
+}
+
+template <int CB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kDecWaves<CB>))) void halves_kernel(
+    ClassRun r, uint64_t slot_words) {
+    uint32_t *tbl = r.table + (size_t)blockIdx.x * slot_words;
+    if constexpr (lanes_half(CB) > 1) {
+        __shared__ uint32_t lds[lds_words_dec<CB>()];
+        for (uint32_t u = blockIdx.x; u < r.ntiles; u += gridDim.x) halves_lanes_unit<CB>(r, u, tbl, lds);
+    } else {
+        for (uint32_t u = blockIdx.x; u < 2 * r.ntiles; u += gridDim.x) halves_unit<CB>(r, u, tbl);
     }
 }
 

@@ -32,11 +32,22 @@ struct pmk_ctx {
     uint32_t class_count[kNumClasses] = {};
     int live_plans = 0;
     std::set<pmk_plan *> plans;
+    int win[kNumClasses] = {};  // CRT-halves window width per class
+    uint32_t epoch = 0;         // bumped when a tuning choice changes (captured graphs go stale)
+    std::string device_name;
 };
 
 struct TimedLaunch {
     int kind;
     hipEvent_t start, stop;
+};
+
+// a captured launch sequence and the buffers / tuning it was captured for
+struct CapturedGraph {
+    hipGraphExec_t exec = nullptr;
+    const void *in = nullptr;
+    void *out = nullptr;
+    uint32_t epoch = 0;
 };
 
 struct pmk_plan {
@@ -47,6 +58,14 @@ struct pmk_plan {
     uint32_t *d_err = nullptr;
     bool profile = false;
     std::vector<TimedLaunch> timed;
+    // batched persistent path (allocated on first use)
+    uint32_t *d_counter = nullptr;     // work counter of the wide batch kernel
+    uint32_t *batch_table = nullptr;   // its window-table slots
+    uint32_t batch_slots[2] = {};      // its resident waves, [encrypt, decrypt]
+    uint64_t batch_slot_words = 0;
+    CapturedGraph graph[2];                         // [0] encrypt, [1] decrypt
+    hipStream_t capture_stream = nullptr, side_stream = nullptr;
+    hipEvent_t fork_event = nullptr, join_event = nullptr;
 };
 
 namespace {
@@ -85,8 +104,22 @@ void drop_timings(pmk_plan *pl) {
     pl->timed.clear();
 }
 
+void drop_graphs(pmk_plan *pl) {
+    for (auto &g : pl->graph) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = CapturedGraph{};
+    }
+}
+
 void free_plan_memory(pmk_plan *pl) {
     drop_timings(pl);
+    drop_graphs(pl);
+    if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
+    if (pl->side_stream) (void)hipStreamDestroy(pl->side_stream);
+    if (pl->fork_event) (void)hipEventDestroy(pl->fork_event);
+    if (pl->join_event) (void)hipEventDestroy(pl->join_event);
+    pl->capture_stream = pl->side_stream = nullptr;
+    pl->fork_event = pl->join_event = nullptr;
     for (void *p : pl->allocs) (void)hipFree(p);
     pl->allocs.clear();
 }
@@ -172,6 +205,8 @@ int pmk_create(int device, pmk_ctx **out) {
         return PMK_EDEVICE;
     }
     ctx->num_cus = prop.multiProcessorCount;
+    ctx->device_name = prop.gcnArchName;
+    for (int c = 0; c < kNumClasses; ++c) ctx->win[c] = window_for(kClassBits[c] / 2);
     *out = ctx;
     return PMK_OK;
 }
@@ -309,6 +344,7 @@ int pmk_plan_create(pmk_ctx *ctx, const uint32_t *key_map, uint64_t nchunks, uin
         r.count = counts[c];
         r.ntiles = (uint32_t)tkeys[c].size();
         r.err = pl->d_err;
+        r.win = ctx->win[c];
         if (!r.ntiles) continue;
         const Geom g = make_geom(kClassBits[c]);
         const uint64_t tiles = r.ntiles, cpt = (uint64_t)chunks_per_tile(kClassBits[c]);
@@ -426,6 +462,165 @@ int pmk_plan_kernel_time(pmk_plan *pl, int kind, double *ms_total, uint64_t *lau
     if (ms_total) *ms_total = total;
     if (launches) *launches = n;
     return PMK_OK;
+}
+
+namespace {
+
+// Launches of one pass of the batched path.  Packing runs on `stream`; then
+// the multi-lane classes (4096, 3072 bits) run as one persistent work-queue
+// launch on the plan's side stream while the one-lane classes (2048 bits down)
+// run their own kernels, largest first, on `stream` (forked and joined with
+// events, so the two can share the chip); Garner recombination and unpacking
+// follow on `stream`.
+int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, void *stream) {
+    pmk_ctx *ctx = pl->ctx;
+    BatchArgs a{};
+    uint32_t total = 0;
+    for (int i = 0; i < kWideClasses; ++i) {
+        const int c = wide_class(i);
+        a.runs[i] = pl->runs[c];
+        a.runs[i].win = ctx->win[c];
+        a.start[i] = total;
+        total += pl->runs[c].ntiles ? exp_units(c, decrypt, pl->runs[c].ntiles) : 0u;
+    }
+    a.start[kWideClasses] = total;
+    a.counter = pl->d_counter;
+    a.table = pl->batch_table;
+    a.slot_words = pl->batch_slot_words;
+    int e = total ? launch_counter_reset(pl->d_counter, stream) : 0;
+    bool narrow = false;
+    for (int c = kNumClasses - 1; c >= 0 && !e; --c) {
+        ClassRun r = pl->runs[c];
+        if (!r.ntiles) continue;
+        narrow = narrow || c < kWideFirst;
+        e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(r, in, decrypt, stream); });
+    }
+    const bool fork = !e && total && narrow;
+    if (fork) {
+        e = hipEventRecord(pl->fork_event, (hipStream_t)stream);
+        if (!e) e = hipStreamWaitEvent(pl->side_stream, pl->fork_event, 0);
+    }
+    if (!e && total) {
+        void *s = fork ? (void *)pl->side_stream : stream;
+        const uint32_t grid = std::min(total, pl->batch_slots[decrypt]);
+        e = timed_launch(pl, PMK_KERNEL_BATCH, s, [&] { return launch_batch(a, decrypt, grid, s); });
+    }
+    for (int c = kWideFirst - 1; c >= 0 && !e; --c) {
+        ClassRun r = pl->runs[c];
+        if (!r.ntiles) continue;
+        r.win = ctx->win[c];
+        e = timed_launch(pl, decrypt ? PMK_KERNEL_CRT_HALVES : PMK_KERNEL_ENCRYPT, stream, [&] {
+            return decrypt ? launch_decrypt_halves(r, stream) : launch_encrypt(r, stream);
+        });
+    }
+    if (fork && !e) {
+        e = hipEventRecord(pl->join_event, pl->side_stream);
+        if (!e) e = hipStreamWaitEvent((hipStream_t)stream, pl->join_event, 0);
+    }
+    for (int c = kNumClasses - 1; c >= 0 && !e; --c) {
+        const ClassRun &r = pl->runs[c];
+        if (!r.ntiles) continue;
+        if (decrypt) e = timed_launch(pl, PMK_KERNEL_GARNER, stream, [&] { return launch_garner(r, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, out, decrypt, stream); });
+    }
+    return e;
+}
+
+int batch_prepare(pmk_plan *pl) {
+    if (pl->d_counter) return PMK_OK;
+    pmk_ctx *ctx = pl->ctx;
+    uint32_t units[2] = {0, 0};
+    for (int i = 0; i < kWideClasses; ++i) {
+        const int c = wide_class(i);
+        for (int d = 0; d < 2; ++d) units[d] += pl->runs[c].ntiles ? exp_units(c, d, pl->runs[c].ntiles) : 0u;
+    }
+    uint64_t slots = 0;
+    for (int d = 0; d < 2; ++d) {
+        pl->batch_slots[d] = std::max<uint32_t>(1, std::min(batch_wave_slots(d, ctx->num_cus), units[d]));
+        if (units[d]) slots = std::max<uint64_t>(slots, pl->batch_slots[d]);
+    }
+    pl->batch_slot_words = std::max(batch_slot_words(0), batch_slot_words(1));
+    uint32_t *counter = nullptr;
+    hipError_t e = dev_alloc(pl, &counter, sizeof(uint32_t));
+    if (e == hipSuccess && slots) e = dev_alloc(pl, &pl->batch_table, slots * pl->batch_slot_words * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->side_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->fork_event, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->join_event, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_err(ctx, e, "batch scratch allocation");
+    pl->d_counter = counter;
+    return PMK_OK;
+}
+
+int batch_run(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, void *stream) {
+    pmk_ctx *ctx = pl->ctx;
+    if (pl->msg_len == 0) return PMK_OK;
+    if (!in || !out || ((uintptr_t)in & 3u) || ((uintptr_t)out & 3u))
+        return set_err(ctx, PMK_EINVAL, "buffers must be non-NULL and 4-byte aligned");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
+    int rc = batch_prepare(pl);
+    if (rc != PMK_OK) return rc;
+    if (pl->profile) {
+        // kernel timing needs events around each launch: run the sequence uncaptured
+        const int e = batch_sequence(pl, decrypt, in, out, stream);
+        return e ? hip_err(ctx, (hipError_t)e, "batch launch") : PMK_OK;
+    }
+    CapturedGraph &g = pl->graph[decrypt];
+    if (!g.exec || g.in != in || g.out != out || g.epoch != ctx->epoch) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = CapturedGraph{};
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(pl->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_err(ctx, e, "graph capture");
+        const int le = batch_sequence(pl, decrypt, in, out, pl->capture_stream);
+        e = hipStreamEndCapture(pl->capture_stream, &graph);
+        if (le || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_err(ctx, le ? (hipError_t)le : e, "batch launch (capture)");
+        }
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g = CapturedGraph{};
+            return hip_err(ctx, e, "graph instantiate");
+        }
+        g.in = in;
+        g.out = out;
+        g.epoch = ctx->epoch;
+    }
+    const hipError_t e = hipGraphLaunch(g.exec, (hipStream_t)stream);
+    return e == hipSuccess ? PMK_OK : hip_err(ctx, e, "graph launch");
+}
+
+}  // namespace
+
+int pmk_encrypt_batch(pmk_plan *pl, const uint8_t *d_msg, uint8_t *d_ct, void *stream) {
+    if (!pl) return PMK_EINVAL;
+    return batch_run(pl, 0, d_msg, d_ct, stream);
+}
+
+int pmk_decrypt_batch(pmk_plan *pl, const uint8_t *d_ct, uint8_t *d_msg, void *stream) {
+    if (!pl) return PMK_EINVAL;
+    return batch_run(pl, 1, d_ct, d_msg, stream);
+}
+
+int pmk_set_window(pmk_ctx *ctx, uint32_t bits, int win) {
+    if (!ctx) return PMK_EINVAL;
+    const int c = class_for_bits(bits);
+    if (c < 0) return set_err(ctx, PMK_EUNSUPPORTED, "no size class for %u bits", bits);
+    if (win < 2 || win > kMaxWin) return set_err(ctx, PMK_EINVAL, "window width must be 2..%d", kMaxWin);
+    if (ctx->win[c] != win) {
+        ctx->win[c] = win;
+        ctx->epoch++;
+        for (pmk_plan *pl : ctx->plans) pl->runs[c].win = win;
+    }
+    return PMK_OK;
+}
+
+int pmk_get_window(const pmk_ctx *ctx, uint32_t bits) {
+    if (!ctx) return PMK_EINVAL;
+    const int c = class_for_bits(bits);
+    return c < 0 ? PMK_EUNSUPPORTED : ctx->win[c];
 }
 
 int pmk_plan_check(pmk_plan *pl, void *stream) {

@@ -34,7 +34,8 @@ PMK_HD constexpr int lanes_half(int bits) { return bits >= 3072 ? 2 : 1; }
 PMK_HD constexpr int chunks_per_tile(int bits) { return 64 / lanes_full(bits); }
 PMK_HD constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-// Window width of the fixed-window exponentiation of the CRT halves.
+// Default window width of the fixed-window exponentiation of the CRT halves
+// (the autotuner may pick another one up to kMaxWin).
 PMK_HD constexpr int window_for(int bits) { return bits <= 256 ? 3 : (bits <= 512 ? 4 : 5); }
 
 // Offsets (uint32 words) of one key record of a class.
@@ -118,6 +119,27 @@ struct ClassRun {
     uint32_t slots_enc;        // wave slots in `table` for the encryption kernel
     uint32_t slots_dec;        // wave slots in `table` for the CRT-halves kernel
     uint32_t *err;             // device error word
+    int win;                   // window width of the CRT-halves exponentiation (3..6)
+};
+
+constexpr int kMaxWin = 6;
+
+// One persistent launch over the exponentiation work of the 1024- to 4096-bit
+// classes of a plan: units (tiles, or job tiles of CRT halves) are numbered
+// class by class, largest modulus first, and handed out by an atomic counter.
+// The multi-lane classes (4096 and 3072 bits) share one persistent kernel
+// whose waves take work units (tiles, or CRT jobs of a tile) from a device
+// counter, 4096-bit units first.
+constexpr int kWideClasses = 2;
+constexpr int kWideFirst = kNumClasses - kWideClasses;  // class index of 3072 bits
+// class of entry i of the wide batch: 4096 bits, then 3072 bits
+constexpr int wide_class(int i) { return kNumClasses - 1 - i; }
+struct BatchArgs {
+    ClassRun runs[kWideClasses];       // runs[i] is class wide_class(i)
+    uint32_t start[kWideClasses + 1];  // first unit of runs[i]; start[2] = total
+    uint32_t *counter;                 // next unit to hand out (reset before each launch)
+    uint32_t *table;                   // per-block window-table slots
+    uint64_t slot_words;               // words per slot
 };
 
 // Launchers (kernels.hip).  All asynchronous on `stream`; return hipError_t as int.
@@ -132,5 +154,10 @@ uint64_t table_words_per_slot(int cls, int decrypt);
 uint32_t wave_slots(int cls, int decrypt, int num_cus);
 // work units (wavefronts' worth of bignums) of the exponentiation kernels
 uint32_t exp_units(int cls, int decrypt, uint32_t ntiles);
+// persistent batched exponentiation (kbatch.hip)
+int launch_batch(const BatchArgs &a, int decrypt, uint32_t grid, void *stream);
+int launch_counter_reset(uint32_t *counter, void *stream);
+uint32_t batch_wave_slots(int decrypt, int num_cus);
+uint64_t batch_slot_words(int decrypt);
 
 }  // namespace pmk
