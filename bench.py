@@ -53,38 +53,133 @@ PEAK_MAD_PER_S = 256 * 64 * 2.4e9
 
 
 def cpu_baseline(keys, msg, km, sample_chunks: int):
+    """The C oracle (schoolbook products, Knuth D remainders, CRT) on the host
+    cores: all threads on the first `sample_chunks` chunks, one thread on an
+    eighth of them."""
     import numpy as np
 
     import oracle
 
-    n = min(sample_chunks, len(km))
-    msg_s = msg[: n * 252]
-    km_s = km[:n]
+    def run(n):
+        msg_s = msg[: n * 252]
+        km_s = km[:n]
+        t0 = time.perf_counter()
+        ct = oracle.encrypt(table, msg_s, km_s)
+        t1 = time.perf_counter()
+        pt, rc = oracle.decrypt(table, ct, len(msg_s), km_s, crt=True)
+        t2 = time.perf_counter()
+        assert rc == 0 and np.array_equal(pt, msg_s)
+        return len(msg_s), t1 - t0, t2 - t1
+
     table = oracle.KeyTable(keys)
-    t0 = time.perf_counter()
-    ct = oracle.encrypt(table, msg_s, km_s)
-    t1 = time.perf_counter()
-    pt, rc = oracle.decrypt(table, ct, len(msg_s), km_s, crt=True)
-    t2 = time.perf_counter()
-    assert rc == 0 and np.array_equal(pt, msg_s)
+    n = min(sample_chunks, len(km))
+    threads = oracle.threads()
+    nbytes, te, td = run(n)
+    oracle.set_threads(1)
+    n1 = max(1, n // 8)
+    nbytes1, te1, td1 = run(n1)
+    oracle.set_threads(threads)
     return {
-        "value": n / (t2 - t1),
+        "value": n / td,
         "unit": "2048-bit CRT decrypt modexp/s",
-        "cores": oracle.threads(),
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"first {n} chunks of the workload ({len(msg_s)} bytes, keys 0..{min(n, 256) - 1}): "
-                  f"encrypt {t1 - t0:.2f} s, CRT decrypt {t2 - t1:.2f} s wall",
-        "enc_MiBps": len(msg_s) / (t1 - t0) / 2**20,
-        "dec_MiBps": len(msg_s) / (t2 - t1) / 2**20,
+        "sample": f"first {n} chunks of the workload ({nbytes} bytes, keys 0..{min(n, 256) - 1}) on {threads} "
+                  f"threads: encrypt {te:.2f} s, CRT decrypt {td:.2f} s wall; first {n1} chunks on 1 thread: "
+                  f"encrypt {te1:.2f} s, CRT decrypt {td1:.2f} s",
+        "enc_modexp_per_s": n / te,
+        "enc_MiBps": nbytes / te / 2**20,
+        "dec_MiBps": nbytes / td / 2**20,
+        "single_thread": {"dec_modexp_per_s": n1 / td1, "enc_modexp_per_s": n1 / te1,
+                          "dec_MiBps": nbytes1 / td1 / 2**20, "enc_MiBps": nbytes1 / te1 / 2**20},
     }
+
+
+def serve_measure(nreq: int, loads, seed: int = 5, staging_mib: int = 2048):
+    """Serving workload: a 512-key device table (1024..4096-bit keys), requests
+    of 1 KiB-10 MiB (log-uniform) over 1-64 keys each, half encryptions and
+    half CRT decryptions.  First the closed-loop capacity (all requests queued
+    at once), then Poisson arrivals at each fraction of it in `loads`; latency
+    = completion (result in host memory) - scheduled arrival."""
+    import numpy as np
+
+    from paper_2111_11924_amd import binding, inputs
+
+    w = inputs.config(5)
+    keys = w.keys()
+    bits = [int(k.bits) for k in keys]
+    reqs = inputs.serving_requests(nreq, bits, seed)
+    msgs = [r.message() for r in reqs]
+    ctx = binding.Context(0)
+    ctx.load_keys(keys)
+    srv = ctx.server(staging_bytes=staging_mib << 20)
+    try:
+        # ciphertexts of the decryption requests, made outside any timing
+        pend = [(i, srv.submit(binding.PMK_OP_ENCRYPT, msgs[i], len(msgs[i]), r.key_map))
+                for i, r in enumerate(reqs) if r.op == binding.PMK_OP_DECRYPT]
+        cts = {}
+        for i, (t, out) in pend:
+            assert srv.wait(t)["status"] == binding.PMK_OK
+            cts[i] = out
+        data = [cts[i] if r.op == binding.PMK_OP_DECRYPT else msgs[i] for i, r in enumerate(reqs)]
+
+        def run(offsets):
+            t0 = time.monotonic_ns() + 2_000_000
+            tickets = []
+            for i, r in enumerate(reqs):
+                due = t0 + (int(offsets[i] * 1e9) if offsets is not None else 0)
+                while True:
+                    now = time.monotonic_ns()
+                    if now >= due:
+                        break
+                    time.sleep(min((due - now) / 1e9, 0.002))
+                tickets.append((due, srv.submit(r.op, data[i], len(msgs[i]), r.key_map)))
+            lat, ok = [], True
+            t_end = t0
+            for i, (due, (t, out)) in enumerate(tickets):
+                info = srv.wait(t)
+                ok = ok and info["status"] == binding.PMK_OK
+                if reqs[i].op == binding.PMK_OP_DECRYPT:
+                    ok = ok and np.array_equal(out, msgs[i])
+                lat.append((info["t_done_ns"] - due) / 1e6)
+                t_end = max(t_end, info["t_done_ns"])
+            return np.array(lat), (t_end - t0) / 1e9, ok
+
+        lat, wall, ok = run(None)
+        cap = nreq / wall
+        nbytes = sum(len(m) for m in msgs)
+        out = {"requests": nreq, "mean_request_bytes": nbytes / nreq,
+               "capacity_req_per_s": cap, "capacity_MiBps": nbytes / wall / 2**20, "results_ok": bool(ok),
+               "points": []}
+        for f in loads:
+            arr = inputs.poisson_arrivals(nreq, f * cap, seed)
+            lat, wall, ok2 = run(arr)
+            out["results_ok"] = out["results_ok"] and bool(ok2)
+            out["points"].append({"load": f, "rate_req_per_s": f * cap, "p50_ms": float(np.percentile(lat, 50)),
+                                  "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
+                                  "achieved_req_per_s": nreq / wall})
+        out["server_stats"] = srv.stats()
+    finally:
+        srv.stop()
+        ctx.close()
+    return out
 
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=1024, help="chunks the oracle baseline times")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=2048, help="chunks the oracle baseline times")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick each class's CRT window by timing on this device first (pmk_autotune)")
+    ap.add_argument("--window", type=int, default=0, help="fix the CRT window width of every class")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving workload only: capacity, then Poisson loads 0.5/0.8/1.2 of it")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="requests per serving point (default: 2000 with --serve, 300 for the headline p99)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--config", type=int, default=4,
                     help="workload recipe (1-4; the JSON line's headline workload is 4)")
@@ -103,12 +198,40 @@ def main() -> int:
 
     from paper_2111_11924_amd import binding, inputs
 
+    if args.serve:
+        res = serve_measure(args.serve_requests or 2000, [0.5, 0.8, 1.2])
+        res.update({"metric": "p99 request latency, serving workload (512 keys, 1 KiB-10 MiB requests)",
+                    "unit": "ms", "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
+                    "value": res["points"][1]["p99_ms"], "config": {"workload": "serving-512keys-mixed",
+                                                                    "load_for_value": 0.8}})
+        print(json.dumps(res))
+        return 0 if res["results_ok"] else 1
+
+    if args.copy_probe:
+        # a copy of known size: what FETCH_SIZE / WRITE_SIZE read for it scales
+        # the same counters taken over the path's kernels
+        n = args.copy_probe << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n, "copies": 3}))
+        return 0
+
     w = inputs.config(args.config)
     keys, msg, km = w.keys(), w.message(), w.key_map()
     bits_of = np.array([k.bits for k in keys])[km]
     nchunks = len(km)
     ctx = binding.Context(0)
     ctx.load_keys(keys)
+    if args.window:
+        for b in set(int(k.bits) for k in keys):
+            ctx.set_window(b, args.window)
+    elif args.autotune:
+        ctx.autotune()  # measured on this device (setup, outside the timed region)
+    windows = {int(b): ctx.window(int(b)) for b in sorted(set(int(k.bits) for k in keys))}
     plan = ctx.plan(km, len(msg))
     d_msg = torch.from_numpy(msg).to("cuda")
     d_ct = torch.empty(plan.ct_len, dtype=torch.uint8, device="cuda")
@@ -141,6 +264,7 @@ def main() -> int:
     t1 = time.perf_counter()
     enc_ms = sum(m[0].elapsed_time(m[1]) for m in marks)
     dec_ms = sum(m[1].elapsed_time(m[2]) for m in marks)
+    step_ms = sorted(m[0].elapsed_time(m[2]) for m in marks)
     ok = plan.check(stream) == binding.PMK_OK and torch.equal(d_pt, d_msg)
     prof_steps = args.steps
     if batch:
@@ -187,6 +311,10 @@ def main() -> int:
         "enc_ms_per_step": enc_ms / args.steps,
         "dec_ms_per_step": dec_ms / args.steps,
         "mode": args.mode,
+        "crt_window": windows,
+        "step_ms_median": step_ms[len(step_ms) // 2],
+        "step_ms_min": step_ms[0],
+        "half_modexp_per_s": 2 * nchunks * args.steps / (dec_ms / 1e3),
         "kernel_ms_per_step": {k: v[0] / max(prof_steps, 1) for k, v in kern.items()},
         "roundtrip_ok": bool(ok),
         "p99_request_ms": None,

@@ -180,6 +180,24 @@ int pmk_set_window(pmk_ctx *ctx, uint32_t bits, int win);
 int pmk_get_window(const pmk_ctx *ctx, uint32_t bits);
 
 /*
+ * Autotuner for the launch configuration: for every size class that has keys
+ * in the loaded table, time the CRT decryption of one chip-filling batch of
+ * full-size chunks (zero blocks: the fixed-window exponentiation costs the
+ * same for any input) under the first key of that class, at three window
+ * widths ({4,5,6} for 1024-bit classes and up, {3,4,5} below), and keep the
+ * fastest (pmk_set_window).  The lane count per number is fixed per class by
+ * its kernel.  cache_path (may be NULL): a text file -- a signature line
+ * (GPU architecture, compute units, HIP runtime version), then
+ * "<class bits> <window> <ms>" lines.  When it exists and its signature
+ * matches this device, its windows are applied without measuring, unless
+ * flags has PMK_AUTOTUNE_FORCE; otherwise the measured choice is written
+ * there.  Synchronous; allocates (and frees) its own device buffers; needs a
+ * loaded key table (PMK_EINVAL otherwise).
+ */
+enum { PMK_AUTOTUNE_FORCE = 1 };
+int pmk_autotune(pmk_ctx *ctx, const char *cache_path, int flags);
+
+/*
  * Wait for `stream`, then return and clear the plan's device-detected error
  * (PMK_OK or PMK_ERANGE).
  */
@@ -214,6 +232,78 @@ int pmk_encrypt(pmk_ctx *ctx, const uint8_t *d_msg, uint64_t msg_len, const uint
                 uint64_t nchunks, uint8_t *d_ct, uint64_t ct_cap, void *stream);
 int pmk_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uint32_t *key_map,
                 uint64_t nchunks, uint8_t *d_msg, uint64_t msg_len, void *stream);
+
+/*
+ * Request server (continuous batching).  A scheduler thread on the context
+ * serves encryption and CRT-decryption requests of any size against the
+ * loaded key table: the chunks of every admitted request join batching rounds
+ * (chunks under one key share tiles across requests; each in-flight request
+ * gets a fair share of a round, so small requests are not stuck behind large
+ * ones), in the spirit of the paper's parallel chunk loops and transfer /
+ * compute pipeline (Sec. 3.1, Algorithm 1; Sec. 4).  Requests are admitted in
+ * arrival order while the device staging slab has room for their input and
+ * output; their host buffers are copied in at admission and out at
+ * completion.  Results are byte-identical to pmk_encrypt_plan /
+ * pmk_decrypt_plan on the same input.
+ *
+ * pmk_server_start: staging_bytes (0: 512 MiB) is the admission budget of
+ *   device memory for inputs and outputs in flight; round_chunks (0: two
+ *   chip-filling rounds of 2048-bit CRT halves) bounds the chunks of one
+ *   round.  The key table and window widths may not change while the server
+ *   runs (PMK_EBUSY).  PMK_EBUSY if a server already runs.
+ * pmk_submit (thread-safe): validates like pmk_plan_create (PMK_EKEY,
+ *   PMK_ESIZE, PMK_EINVAL; PMK_ESIZE also when out_cap is too small or the
+ *   request could never fit the staging slab), copies key_map, and returns a
+ *   ticket.  `in` and `out` are HOST memory that must stay valid until the
+ *   ticket is reported done: encryption reads msg_len bytes and writes the
+ *   ciphertext; decryption reads the ciphertext (its length follows from the
+ *   key map) and writes msg_len bytes.
+ * pmk_poll (thread-safe, non-blocking) / pmk_wait (thread-safe, blocking):
+ *   fill *info; once a ticket has been reported done it is forgotten (a later
+ *   call returns PMK_EINVAL).  info->status is the request's result (PMK_OK,
+ *   PMK_ERANGE for a ciphertext block not below its modulus -- that request's
+ *   output is then unspecified -- or PMK_EDEVICE).  Times are CLOCK_MONOTONIC
+ *   nanoseconds.
+ * pmk_server_stop: finishes every submitted request, then stops the thread.
+ *   pmk_destroy stops a running server the same way.
+ */
+typedef struct {
+    uint64_t staging_bytes;
+    uint64_t round_chunks;
+} pmk_server_cfg;
+
+enum { PMK_OP_ENCRYPT = 0, PMK_OP_DECRYPT = 1 };
+enum { PMK_REQ_QUEUED = 0, PMK_REQ_ADMITTED = 1, PMK_REQ_DONE = 2 };
+
+typedef struct {
+    int op;                  /* PMK_OP_ENCRYPT or PMK_OP_DECRYPT */
+    const uint8_t *in;       /* host input */
+    uint8_t *out;            /* host output */
+    uint64_t out_cap;        /* bytes available at out */
+    uint64_t msg_len;        /* plaintext bytes */
+    const uint32_t *key_map; /* host, nchunks key indices (copied at submit) */
+    uint64_t nchunks;
+} pmk_request;
+
+typedef struct {
+    int state;   /* PMK_REQ_* */
+    int status;  /* valid when state == PMK_REQ_DONE */
+    uint64_t t_submit_ns, t_admit_ns, t_done_ns;
+} pmk_ticket_info;
+
+typedef struct {
+    uint64_t requests_submitted, requests_done;
+    uint64_t rounds, chunks;  /* batching rounds run and chunks they processed */
+    uint64_t busy_ns;         /* time the scheduler spent in rounds */
+    uint64_t queued;          /* requests waiting for admission now */
+} pmk_server_stats;
+
+int pmk_server_start(pmk_ctx *ctx, const pmk_server_cfg *cfg);
+int pmk_submit(pmk_ctx *ctx, const pmk_request *req, uint64_t *ticket);
+int pmk_poll(pmk_ctx *ctx, uint64_t ticket, pmk_ticket_info *info);
+int pmk_wait(pmk_ctx *ctx, uint64_t ticket, pmk_ticket_info *info);
+int pmk_server_stats_get(pmk_ctx *ctx, pmk_server_stats *out);
+int pmk_server_stop(pmk_ctx *ctx);
 
 #ifdef __cplusplus
 }

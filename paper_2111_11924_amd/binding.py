@@ -53,6 +53,31 @@ class pmk_key(C.Structure):
                 ("dq", U32P), ("qinv", U32P)]
 
 
+class pmk_server_cfg(C.Structure):
+    _fields_ = [("staging_bytes", C.c_uint64), ("round_chunks", C.c_uint64)]
+
+
+class pmk_request(C.Structure):
+    _fields_ = [("op", C.c_int), ("in_", C.c_void_p), ("out", C.c_void_p), ("out_cap", C.c_uint64),
+                ("msg_len", C.c_uint64), ("key_map", U32P), ("nchunks", C.c_uint64)]
+
+
+class pmk_ticket_info(C.Structure):
+    _fields_ = [("state", C.c_int), ("status", C.c_int), ("t_submit_ns", C.c_uint64),
+                ("t_admit_ns", C.c_uint64), ("t_done_ns", C.c_uint64)]
+
+
+class pmk_server_stats(C.Structure):
+    _fields_ = [("requests_submitted", C.c_uint64), ("requests_done", C.c_uint64), ("rounds", C.c_uint64),
+                ("chunks", C.c_uint64), ("busy_ns", C.c_uint64), ("queued", C.c_uint64)]
+
+
+PMK_OP_ENCRYPT = 0
+PMK_OP_DECRYPT = 1
+PMK_REQ_QUEUED = 0
+PMK_REQ_ADMITTED = 1
+PMK_REQ_DONE = 2
+
 _lib = None
 
 
@@ -85,6 +110,13 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "pmk_decrypt_batch": (C.c_int, [vp, vp, vp, vp]),
         "pmk_set_window": (C.c_int, [vp, u32, C.c_int]),
         "pmk_get_window": (C.c_int, [vp, u32]),
+        "pmk_autotune": (C.c_int, [vp, C.c_char_p, C.c_int]),
+        "pmk_server_start": (C.c_int, [vp, C.POINTER(pmk_server_cfg)]),
+        "pmk_submit": (C.c_int, [vp, C.POINTER(pmk_request), C.POINTER(u64)]),
+        "pmk_poll": (C.c_int, [vp, u64, C.POINTER(pmk_ticket_info)]),
+        "pmk_wait": (C.c_int, [vp, u64, C.POINTER(pmk_ticket_info)]),
+        "pmk_server_stats_get": (C.c_int, [vp, C.POINTER(pmk_server_stats)]),
+        "pmk_server_stop": (C.c_int, [vp]),
         "pmk_plan_check": (C.c_int, [vp, vp]),
         "pmk_plan_profile": (C.c_int, [vp, C.c_int]),
         "pmk_plan_kernel_time": (C.c_int, [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(u64)]),
@@ -252,6 +284,14 @@ def pmk_get_window(ctx: int, bits: int) -> int:
     return load_library().pmk_get_window(ctx, int(bits))
 
 
+PMK_AUTOTUNE_FORCE = 1
+
+
+def pmk_autotune(ctx: int, cache_path: Optional[str] = None, flags: int = 0) -> None:
+    path = os.fsencode(cache_path) if cache_path else None
+    _check(load_library().pmk_autotune(ctx, path, int(flags)), ctx)
+
+
 def pmk_plan_check(plan: int, stream=None) -> int:
     return load_library().pmk_plan_check(plan, _stream(stream))
 
@@ -276,6 +316,49 @@ def pmk_decrypt(ctx: int, d_ct, ct_len: int, key_map, d_msg, msg_len: int, strea
     km = _map_array(key_map)
     return load_library().pmk_decrypt(ctx, _dev_ptr(d_ct), int(ct_len), km.ctypes.data_as(U32P), len(km),
                                       _dev_ptr(d_msg), int(msg_len), _stream(stream))
+
+
+def pmk_server_start(ctx: int, staging_bytes: int = 0, round_chunks: int = 0) -> None:
+    cfg = pmk_server_cfg(int(staging_bytes), int(round_chunks))
+    _check(load_library().pmk_server_start(ctx, C.byref(cfg)), ctx)
+
+
+def pmk_submit(ctx: int, op: int, data: np.ndarray, out: np.ndarray, msg_len: int, key_map) -> Tuple[int, int]:
+    """(status, ticket).  data / out: host uint8 arrays that must stay alive
+    until the ticket is reported done."""
+    km = _map_array(key_map)
+    req = pmk_request(int(op), data.ctypes.data if len(data) else None, out.ctypes.data if len(out) else None,
+                      out.nbytes, int(msg_len), km.ctypes.data_as(U32P), len(km))
+    t = C.c_uint64(0)
+    rc = load_library().pmk_submit(ctx, C.byref(req), C.byref(t))
+    return rc, t.value
+
+
+def _info(i: pmk_ticket_info) -> dict:
+    return {"state": i.state, "status": i.status, "t_submit_ns": i.t_submit_ns, "t_admit_ns": i.t_admit_ns,
+            "t_done_ns": i.t_done_ns}
+
+
+def pmk_poll(ctx: int, ticket: int) -> Tuple[int, dict]:
+    info = pmk_ticket_info()
+    rc = load_library().pmk_poll(ctx, int(ticket), C.byref(info))
+    return rc, _info(info)
+
+
+def pmk_wait(ctx: int, ticket: int) -> Tuple[int, dict]:
+    info = pmk_ticket_info()
+    rc = load_library().pmk_wait(ctx, int(ticket), C.byref(info))
+    return rc, _info(info)
+
+
+def pmk_server_stats_get(ctx: int) -> dict:
+    st = pmk_server_stats()
+    _check(load_library().pmk_server_stats_get(ctx, C.byref(st)), ctx)
+    return {f: getattr(st, f) for f, _ in pmk_server_stats._fields_}
+
+
+def pmk_server_stop(ctx: int) -> None:
+    _check(load_library().pmk_server_stop(ctx), ctx)
 
 
 # ---------- a small object layer over the same calls -------------------------------------
@@ -331,6 +414,60 @@ class Plan:
             pass
 
 
+class Server:
+    """The request server of a context (pmk_server_*).  Keeps each request's
+    host buffers alive until its ticket is reported done."""
+
+    def __init__(self, ctx: "Context", staging_bytes: int = 0, round_chunks: int = 0):
+        self.ctx = ctx
+        pmk_server_start(ctx.handle, staging_bytes, round_chunks)
+        self._held = {}
+        self.running = True
+
+    def submit(self, op: int, data: np.ndarray, msg_len: int, key_map, out: Optional[np.ndarray] = None):
+        """Submit one request; returns (ticket, out array).  Raises PmkError on a
+        validation error."""
+        data = np.ascontiguousarray(data, dtype=np.uint8)
+        if out is None:
+            if op == PMK_OP_ENCRYPT:
+                bits = [pmk_key_bits(self.ctx.handle, int(k)) for k in np.asarray(key_map)]
+                n = int(sum(b // 8 for b in bits))
+            else:
+                n = int(msg_len)
+            out = np.zeros(n, dtype=np.uint8)
+        km = _map_array(key_map)
+        rc, t = pmk_submit(self.ctx.handle, op, data, out, msg_len, km)
+        if rc != PMK_OK:
+            raise PmkError(rc, "submit")
+        self._held[t] = (data, out, km)
+        return t, out
+
+    def poll(self, ticket: int) -> Optional[dict]:
+        rc, info = pmk_poll(self.ctx.handle, ticket)
+        if rc != PMK_OK:
+            raise PmkError(rc, "poll")
+        if info["state"] == PMK_REQ_DONE:
+            self._held.pop(ticket, None)
+            return info
+        return None
+
+    def wait(self, ticket: int) -> dict:
+        rc, info = pmk_wait(self.ctx.handle, ticket)
+        if rc != PMK_OK:
+            raise PmkError(rc, "wait")
+        self._held.pop(ticket, None)
+        return info
+
+    def stats(self) -> dict:
+        return pmk_server_stats_get(self.ctx.handle)
+
+    def stop(self) -> None:
+        if self.running:
+            pmk_server_stop(self.ctx.handle)
+            self.running = False
+            self._held.clear()
+
+
 class Context:
     """pmk_create / pmk_keys_load / plans on one GPU."""
 
@@ -349,6 +486,13 @@ class Context:
 
     def window(self, bits: int) -> int:
         return pmk_get_window(self.handle, bits)
+
+    def autotune(self, cache_path: Optional[str] = None, force: bool = False) -> None:
+        """Pick each loaded size class's CRT window width by timing (pmk_autotune)."""
+        pmk_autotune(self.handle, cache_path, PMK_AUTOTUNE_FORCE if force else 0)
+
+    def server(self, staging_bytes: int = 0, round_chunks: int = 0) -> "Server":
+        return Server(self, staging_bytes, round_chunks)
 
     def plan(self, key_map, msg_len: int) -> Plan:
         p = Plan(self, key_map, msg_len)

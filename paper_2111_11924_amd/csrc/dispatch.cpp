@@ -12,7 +12,7 @@ namespace pmk {
     int launch_halves_##B(const ClassRun &, hipStream_t);                                  \
     int launch_garner_##B(const ClassRun &, hipStream_t);                                  \
     uint32_t wave_slots_##B(int, int);                                                     \
-    uint64_t slot_words_##B(int);
+    uint64_t slot_words_##B(int, int);
 PMK_DECLARE(128)
 PMK_DECLARE(256)
 PMK_DECLARE(512)
@@ -54,15 +54,15 @@ int launch_garner(const ClassRun &r, void *stream) {
     PMK_DISPATCH(r.cls, launch_garner, r, (hipStream_t)stream);
 }
 
-uint64_t table_words_per_slot(int cls, int decrypt) {
+uint64_t table_words_per_slot(int cls, int decrypt, int win) {
     switch (cls) {
-        case 0: return slot_words_128(decrypt);
-        case 1: return slot_words_256(decrypt);
-        case 2: return slot_words_512(decrypt);
-        case 3: return slot_words_1024(decrypt);
-        case 4: return slot_words_2048(decrypt);
-        case 5: return slot_words_3072(decrypt);
-        case 6: return slot_words_4096(decrypt);
+        case 0: return slot_words_128(decrypt, win);
+        case 1: return slot_words_256(decrypt, win);
+        case 2: return slot_words_512(decrypt, win);
+        case 3: return slot_words_1024(decrypt, win);
+        case 4: return slot_words_2048(decrypt, win);
+        case 5: return slot_words_3072(decrypt, win);
+        case 6: return slot_words_4096(decrypt, win);
         default: return 0;
     }
 }

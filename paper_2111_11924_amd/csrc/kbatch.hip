@@ -61,10 +61,10 @@ uint32_t batch_wave_slots(int decrypt, int num_cus) {
     return (uint32_t)nb * (uint32_t)num_cus;
 }
 
-uint64_t batch_slot_words(int decrypt) {
+uint64_t batch_slot_words(int decrypt, const int *win) {
     uint64_t w = 0;
     for (int i = 0; i < kWideClasses; ++i) {
-        const uint64_t x = table_words_per_slot(wide_class(i), decrypt);
+        const uint64_t x = table_words_per_slot(wide_class(i), decrypt, win[i]);
         w = x > w ? x : w;
     }
     return w;

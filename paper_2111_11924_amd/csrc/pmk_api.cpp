@@ -14,61 +14,11 @@
 #include "../../include/pmk.h"
 #include "keyprep.hpp"
 #include "pmk_internal.hpp"
+#include "pmk_state.hpp"
 
 using namespace pmk;
 
-struct KeySlot {
-    int cls;
-    uint32_t slot;  // record index within the class table
-    uint32_t bits;
-};
-
-struct pmk_ctx {
-    int device = 0;
-    int num_cus = 0;
-    std::string err;
-    std::vector<KeySlot> keys;
-    uint32_t *d_keys[kNumClasses] = {};
-    uint32_t class_count[kNumClasses] = {};
-    int live_plans = 0;
-    std::set<pmk_plan *> plans;
-    int win[kNumClasses] = {};  // CRT-halves window width per class
-    uint32_t epoch = 0;         // bumped when a tuning choice changes (captured graphs go stale)
-    std::string device_name;
-};
-
-struct TimedLaunch {
-    int kind;
-    hipEvent_t start, stop;
-};
-
-// a captured launch sequence and the buffers / tuning it was captured for
-struct CapturedGraph {
-    hipGraphExec_t exec = nullptr;
-    const void *in = nullptr;
-    void *out = nullptr;
-    uint32_t epoch = 0;
-};
-
-struct pmk_plan {
-    pmk_ctx *ctx = nullptr;
-    uint64_t msg_len = 0, nchunks = 0, ct_len = 0;
-    ClassRun runs[kNumClasses] = {};
-    std::vector<void *> allocs;
-    uint32_t *d_err = nullptr;
-    bool profile = false;
-    std::vector<TimedLaunch> timed;
-    // batched persistent path (allocated on first use)
-    uint32_t *d_counter = nullptr;     // work counter of the wide batch kernel
-    uint32_t *batch_table = nullptr;   // its window-table slots
-    uint32_t batch_slots[2] = {};      // its resident waves, [encrypt, decrypt]
-    uint64_t batch_slot_words = 0;
-    CapturedGraph graph[2];                         // [0] encrypt, [1] decrypt
-    hipStream_t capture_stream = nullptr, side_stream = nullptr;
-    hipEvent_t fork_event = nullptr, join_event = nullptr;
-};
-
-namespace {
+namespace pmk {
 
 int set_err(pmk_ctx *ctx, int code, const char *fmt, ...) {
     if (ctx) {
@@ -87,14 +37,6 @@ int hip_err(pmk_ctx *ctx, hipError_t e, const char *where) {
                    hipGetErrorString(e));
 }
 
-template <typename T>
-hipError_t dev_alloc(pmk_plan *pl, T **p, size_t bytes) {
-    void *v = nullptr;
-    hipError_t e = hipMalloc(&v, bytes ? bytes : 4);
-    if (e == hipSuccess) pl->allocs.push_back(v);
-    *p = (T *)v;
-    return e;
-}
 
 void drop_timings(pmk_plan *pl) {
     for (auto &t : pl->timed) {
@@ -124,70 +66,45 @@ void free_plan_memory(pmk_plan *pl) {
     pl->allocs.clear();
 }
 
-// Runs one launcher; with profiling on, brackets it with events on `stream`.
-template <typename F>
-int timed_launch(pmk_plan *pl, int kind, void *stream, F launch) {
-    if (!pl->profile) return launch();
-    TimedLaunch t{kind, nullptr, nullptr};
-    if (hipEventCreate(&t.start) != hipSuccess) return (int)hipErrorOutOfMemory;
-    if (hipEventCreate(&t.stop) != hipSuccess) {
-        (void)hipEventDestroy(t.start);
-        return (int)hipErrorOutOfMemory;
+// Grows a per-wave table buffer to at least `need` words.  Tables are sized
+// for the window widths in force; a wider window set later reallocates them
+// here, before any launch that would index past the old size.
+hipError_t regrow(pmk_plan *pl, uint32_t **p, uint64_t &cap, uint64_t need) {
+    if (need <= cap) return hipSuccess;
+    if (*p) {
+        (void)hipDeviceSynchronize();  // launches already queued may still read it
+        for (size_t i = 0; i < pl->allocs.size(); ++i)
+            if (pl->allocs[i] == (void *)*p) {
+                pl->allocs.erase(pl->allocs.begin() + i);
+                break;
+            }
+        (void)hipFree(*p);
+        *p = nullptr;
+        cap = 0;
     }
-    (void)hipEventRecord(t.start, (hipStream_t)stream);
-    const int e = launch();
-    (void)hipEventRecord(t.stop, (hipStream_t)stream);
-    pl->timed.push_back(t);
+    drop_graphs(pl);
+    hipError_t e = dev_alloc(pl, p, need * sizeof(uint32_t));
+    if (e == hipSuccess) cap = need;
     return e;
 }
 
-// Host-side chunk planning shared by pmk_plan_create and pmk_plan_validate.
-// Calls visit(i, key, msg_off, len, ct_off) per chunk; returns status.
-template <typename Visit>
-int walk_chunks(const uint32_t *key_bits, uint32_t nkeys, const uint32_t *key_map, uint64_t nchunks,
-                uint64_t msg_len, uint64_t *ct_len, std::string *why, Visit visit) {
-    if (msg_len == 0) {
-        if (nchunks != 0) {
-            if (why) *why = "empty message needs zero chunks";
-            return PMK_ESIZE;
-        }
-        if (ct_len) *ct_len = 0;
-        return PMK_OK;
+// Window tables of every class of the plan, sized for the context's windows.
+hipError_t ensure_tables(pmk_plan *pl) {
+    for (int c = 0; c < kNumClasses; ++c) {
+        ClassRun &r = pl->runs[c];
+        if (!r.ntiles) continue;
+        r.win = pl->ctx->win[c];
+        const uint64_t need = std::max(r.slots_enc * table_words_per_slot(c, 0, 0),
+                                       r.slots_dec * table_words_per_slot(c, 1, r.win));
+        const hipError_t e = regrow(pl, &r.table, pl->table_cap[c], need);
+        if (e != hipSuccess) return e;
     }
-    if (!key_map) {
-        if (why) *why = "key_map is NULL";
-        return PMK_EINVAL;
-    }
-    uint64_t off = 0, ct = 0;
-    for (uint64_t i = 0; i < nchunks; ++i) {
-        const uint32_t k = key_map[i];
-        if (k >= nkeys) {
-            if (why) *why = "chunk " + std::to_string(i) + " names key " + std::to_string(k);
-            return PMK_EKEY;
-        }
-        const uint64_t cap = key_bits[k] / 8 - 4;
-        if (off >= msg_len) {
-            if (why) *why = "more chunks than the message needs";
-            return PMK_ESIZE;
-        }
-        const uint64_t len = std::min<uint64_t>(cap, msg_len - off);
-        if (i + 1 == nchunks && off + len != msg_len) {
-            if (why) *why = "fewer chunks than the message needs";
-            return PMK_ESIZE;
-        }
-        visit(i, k, off, len, ct);
-        off += len;
-        ct += key_bits[k] / 8;
-    }
-    if (nchunks == 0) {
-        if (why) *why = "non-empty message needs chunks";
-        return PMK_ESIZE;
-    }
-    if (ct_len) *ct_len = ct;
-    return PMK_OK;
+    return hipSuccess;
 }
 
-}  // namespace
+
+
+}  // namespace pmk
 
 extern "C" {
 
@@ -213,6 +130,7 @@ int pmk_create(int device, pmk_ctx **out) {
 
 void pmk_destroy(pmk_ctx *ctx) {
     if (!ctx) return;
+    server_shutdown(ctx);
     (void)hipSetDevice(ctx->device);
     while (!ctx->plans.empty()) pmk_plan_destroy(*ctx->plans.begin());
     for (auto &p : ctx->d_keys)
@@ -248,7 +166,7 @@ int pmk_keys_load(pmk_ctx *ctx, const pmk_key *keys, uint32_t nkeys) {
         const int rc = pmk_key_check(&keys[i], why, sizeof why);
         if (rc != PMK_OK) return set_err(ctx, rc, "key %u: %s", i, why);
         const int c = class_for_bits(keys[i].bits);
-        slots[i] = {c, counts[c]++, keys[i].bits};
+        slots[i] = {c, counts[c]++, keys[i].bits, std::vector<uint32_t>(keys[i].n, keys[i].n + keys[i].bits / 32)};
     }
     std::vector<std::vector<uint32_t>> host(kNumClasses);
     for (int c = 0; c < kNumClasses; ++c)
@@ -351,8 +269,6 @@ int pmk_plan_create(pmk_ctx *ctx, const uint32_t *key_map, uint64_t nchunks, uin
         r.keys = ctx->d_keys[c];
         r.slots_enc = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 0, ctx->num_cus), exp_units(c, 0, r.ntiles)));
         r.slots_dec = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 1, ctx->num_cus), exp_units(c, 1, r.ntiles)));
-        const uint64_t tbl_words = std::max(r.slots_enc * table_words_per_slot(c, 0),
-                                            r.slots_dec * table_words_per_slot(c, 1));
         ChunkDesc *d = nullptr;
         uint32_t *tk = nullptr;
         e = dev_alloc(pl, &d, per[c].size() * sizeof(ChunkDesc));
@@ -366,8 +282,8 @@ int pmk_plan_create(pmk_ctx *ctx, const uint32_t *key_map, uint64_t nchunks, uin
         if (e == hipSuccess) e = dev_alloc(pl, &r.x32, tiles * g.S * cpt * sizeof(uint32_t));
         if (e == hipSuccess) e = dev_alloc(pl, &r.y32, tiles * g.S * cpt * sizeof(uint32_t));
         if (e == hipSuccess) e = dev_alloc(pl, &r.half, tiles * 2 * g.nlh * cpt * sizeof(uint32_t));
-        if (e == hipSuccess) e = dev_alloc(pl, &r.table, tbl_words * sizeof(uint32_t));
     }
+    if (e == hipSuccess) e = ensure_tables(pl);
     if (e != hipSuccess) {
         free_plan_memory(pl);
         delete pl;
@@ -407,6 +323,7 @@ int pmk_encrypt_plan(pmk_plan *pl, const uint8_t *d_msg, uint8_t *d_ct, void *st
     if (!d_msg || !d_ct || !aligned4(d_msg) || !aligned4(d_ct))
         return set_err(ctx, PMK_EINVAL, "buffers must be non-NULL and 4-byte aligned");
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
+    if (const hipError_t te = ensure_tables(pl)) return hip_err(ctx, te, "window table allocation");
     for (int c = 0; c < kNumClasses; ++c) {
         const ClassRun &r = pl->runs[c];
         if (!r.ntiles) continue;
@@ -425,6 +342,7 @@ int pmk_decrypt_plan(pmk_plan *pl, const uint8_t *d_ct, uint8_t *d_msg, void *st
     if (!d_msg || !d_ct || !aligned4(d_msg) || !aligned4(d_ct))
         return set_err(ctx, PMK_EINVAL, "buffers must be non-NULL and 4-byte aligned");
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
+    if (const hipError_t te = ensure_tables(pl)) return hip_err(ctx, te, "window table allocation");
     for (int c = 0; c < kNumClasses; ++c) {
         const ClassRun &r = pl->runs[c];
         if (!r.ntiles) continue;
@@ -464,7 +382,9 @@ int pmk_plan_kernel_time(pmk_plan *pl, int kind, double *ms_total, uint64_t *lau
     return PMK_OK;
 }
 
-namespace {
+}  // extern "C"
+
+namespace pmk {
 
 // Launches of one pass of the batched path.  Packing runs on `stream`; then
 // the multi-lane classes (4096, 3072 bits) run as one persistent work-queue
@@ -486,7 +406,7 @@ int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, v
     a.start[kWideClasses] = total;
     a.counter = pl->d_counter;
     a.table = pl->batch_table;
-    a.slot_words = pl->batch_slot_words;
+    a.slot_words = batch_slot_words(decrypt, pl->batch_win);
     int e = total ? launch_counter_reset(pl->d_counter, stream) : 0;
     bool narrow = false;
     for (int c = kNumClasses - 1; c >= 0 && !e; --c) {
@@ -534,15 +454,10 @@ int batch_prepare(pmk_plan *pl) {
         const int c = wide_class(i);
         for (int d = 0; d < 2; ++d) units[d] += pl->runs[c].ntiles ? exp_units(c, d, pl->runs[c].ntiles) : 0u;
     }
-    uint64_t slots = 0;
-    for (int d = 0; d < 2; ++d) {
+    for (int d = 0; d < 2; ++d)
         pl->batch_slots[d] = std::max<uint32_t>(1, std::min(batch_wave_slots(d, ctx->num_cus), units[d]));
-        if (units[d]) slots = std::max<uint64_t>(slots, pl->batch_slots[d]);
-    }
-    pl->batch_slot_words = std::max(batch_slot_words(0), batch_slot_words(1));
     uint32_t *counter = nullptr;
     hipError_t e = dev_alloc(pl, &counter, sizeof(uint32_t));
-    if (e == hipSuccess && slots) e = dev_alloc(pl, &pl->batch_table, slots * pl->batch_slot_words * sizeof(uint32_t));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->side_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->fork_event, hipEventDisableTiming);
@@ -550,6 +465,18 @@ int batch_prepare(pmk_plan *pl) {
     if (e != hipSuccess) return hip_err(ctx, e, "batch scratch allocation");
     pl->d_counter = counter;
     return PMK_OK;
+}
+
+// The wide batch kernel's table, sized for both directions at the current windows.
+hipError_t ensure_batch_table(pmk_plan *pl) {
+    uint64_t need = 0;
+    for (int i = 0; i < kWideClasses; ++i) pl->batch_win[i] = pl->ctx->win[wide_class(i)];
+    for (int d = 0; d < 2; ++d) {
+        bool any = false;
+        for (int i = 0; i < kWideClasses; ++i) any = any || pl->runs[wide_class(i)].ntiles;
+        if (any) need = std::max<uint64_t>(need, (uint64_t)pl->batch_slots[d] * batch_slot_words(d, pl->batch_win));
+    }
+    return regrow(pl, &pl->batch_table, pl->batch_cap, need);
 }
 
 int batch_run(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, void *stream) {
@@ -560,6 +487,9 @@ int batch_run(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, void *
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
     int rc = batch_prepare(pl);
     if (rc != PMK_OK) return rc;
+    hipError_t te = ensure_tables(pl);
+    if (te == hipSuccess) te = ensure_batch_table(pl);
+    if (te != hipSuccess) return hip_err(ctx, te, "window table allocation");
     if (pl->profile) {
         // kernel timing needs events around each launch: run the sequence uncaptured
         const int e = batch_sequence(pl, decrypt, in, out, stream);
@@ -592,7 +522,9 @@ int batch_run(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, void *
     return e == hipSuccess ? PMK_OK : hip_err(ctx, e, "graph launch");
 }
 
-}  // namespace
+}  // namespace pmk
+
+extern "C" {
 
 int pmk_encrypt_batch(pmk_plan *pl, const uint8_t *d_msg, uint8_t *d_ct, void *stream) {
     if (!pl) return PMK_EINVAL;
@@ -609,6 +541,7 @@ int pmk_set_window(pmk_ctx *ctx, uint32_t bits, int win) {
     const int c = class_for_bits(bits);
     if (c < 0) return set_err(ctx, PMK_EUNSUPPORTED, "no size class for %u bits", bits);
     if (win < 2 || win > kMaxWin) return set_err(ctx, PMK_EINVAL, "window width must be 2..%d", kMaxWin);
+    if (ctx->server) return set_err(ctx, PMK_EBUSY, "window widths are fixed while a server runs");
     if (ctx->win[c] != win) {
         ctx->win[c] = win;
         ctx->epoch++;
@@ -621,6 +554,143 @@ int pmk_get_window(const pmk_ctx *ctx, uint32_t bits) {
     if (!ctx) return PMK_EINVAL;
     const int c = class_for_bits(bits);
     return c < 0 ? PMK_EUNSUPPORTED : ctx->win[c];
+}
+
+}  // extern "C"
+
+namespace {
+
+// identity of the device and runtime an autotuning result belongs to
+std::string tune_signature(const pmk_ctx *ctx) {
+    int rt = 0;
+    (void)hipRuntimeGetVersion(&rt);
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "pmk-autotune 1 %s cus=%d hip=%d", ctx->device_name.c_str(), ctx->num_cus, rt);
+    return buf;
+}
+
+// Applies a cache file written for this device; false if absent or foreign.
+bool tune_load(pmk_ctx *ctx, const char *path) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool ok = std::fgets(line, sizeof line, f) != nullptr;
+    if (ok) {
+        line[strcspn(line, "\r\n")] = 0;
+        ok = tune_signature(ctx) == line;
+    }
+    int got[kNumClasses];
+    for (int c = 0; c < kNumClasses; ++c) got[c] = ctx->win[c];
+    unsigned bits = 0;
+    int win = 0;
+    while (ok && std::fgets(line, sizeof line, f)) {
+        if (std::sscanf(line, "%u %d", &bits, &win) != 2) continue;
+        const int c = class_for_bits(bits);
+        if (c < 0 || kClassBits[c] != (int)bits || win < 2 || win > kMaxWin) {
+            ok = false;
+            break;
+        }
+        got[c] = win;
+    }
+    std::fclose(f);
+    if (!ok) return false;
+    for (int c = 0; c < kNumClasses; ++c) (void)pmk_set_window(ctx, (uint32_t)kClassBits[c], got[c]);
+    return true;
+}
+
+// Time of one CRT decryption of `pl` (device-resident buffers), best of `reps`.
+int tune_time(pmk_plan *pl, const uint8_t *ct, uint8_t *out, hipStream_t st, int reps, float *best) {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    int rc = e == hipSuccess ? pmk_decrypt_plan(pl, ct, out, st) : PMK_EDEVICE;  // warm-up, sizes tables
+    *best = 1e30f;
+    for (int i = 0; i < reps && rc == PMK_OK; ++i) {
+        (void)hipEventRecord(a, st);
+        rc = pmk_decrypt_plan(pl, ct, out, st);
+        (void)hipEventRecord(b, st);
+        float ms = 0.f;
+        if (rc == PMK_OK && hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess)
+            *best = std::min(*best, ms);
+        else if (rc == PMK_OK)
+            rc = PMK_EDEVICE;
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pmk_autotune(pmk_ctx *ctx, const char *cache_path, int flags) {
+    if (!ctx) return PMK_EINVAL;
+    if (ctx->keys.empty()) return set_err(ctx, PMK_EINVAL, "autotuning needs a loaded key table");
+    if (ctx->server) return set_err(ctx, PMK_EBUSY, "autotuning is not possible while a server runs");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
+    if (cache_path && !(flags & PMK_AUTOTUNE_FORCE) && tune_load(ctx, cache_path)) return PMK_OK;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+        return set_err(ctx, PMK_EDEVICE, "stream creation failed");
+    std::string report = tune_signature(ctx) + "\n";
+    int rc = PMK_OK;
+    for (int c = 0; c < kNumClasses && rc == PMK_OK; ++c) {
+        uint32_t k0 = UINT32_MAX;
+        for (uint32_t k = 0; k < ctx->keys.size(); ++k)
+            if (ctx->keys[k].cls == c) {
+                k0 = k;
+                break;
+            }
+        if (k0 == UINT32_MAX) continue;
+        const int cb = kClassBits[c];
+        const uint32_t per_tile = exp_units(c, 1, 1);
+        // four chip-filling rounds of work units (steady state, not one wave of launches)
+        const uint64_t tiles = std::max<uint32_t>(1, 4 * wave_slots(c, 1, ctx->num_cus) / per_tile);
+        const uint64_t nch = tiles * (uint64_t)chunks_per_tile(cb);
+        const uint64_t kb = ctx->keys[k0].bits / 8;
+        std::vector<uint32_t> km(nch, k0);
+        pmk_plan *pl = nullptr;
+        uint64_t ct_len = 0;
+        rc = pmk_plan_create(ctx, km.data(), nch, nch * (kb - 4), &pl, &ct_len);
+        if (rc != PMK_OK) break;
+        uint8_t *ct = nullptr, *out = nullptr;
+        hipError_t e = hipMalloc(&ct, ct_len);
+        if (e == hipSuccess) e = hipMalloc(&out, nch * (kb - 4));
+        if (e == hipSuccess) e = hipMemset(ct, 0, ct_len);  // zero blocks: valid input, data-independent timing
+        if (e != hipSuccess) rc = hip_err(ctx, e, "autotune buffers");
+        const int w0 = window_for(cb / 2) > 4 ? 4 : 3;
+        int best_w = ctx->win[c];
+        float best_ms = 1e30f;
+        char line[128];
+        for (int w = w0; w < w0 + 3 && w <= kMaxWin && rc == PMK_OK; ++w) {
+            (void)pmk_set_window(ctx, (uint32_t)cb, w);
+            float ms = 0.f;
+            rc = tune_time(pl, ct, out, st, 3, &ms);
+            // a wider window must win by 1% to be taken: its table costs memory
+            if (rc == PMK_OK && ms < 0.99f * best_ms) {
+                best_ms = ms;
+                best_w = w;
+            }
+        }
+        if (rc == PMK_OK) {
+            std::snprintf(line, sizeof line, "%d %d %.4f\n", cb, best_w, best_ms);
+            report += line;
+        }
+        (void)pmk_set_window(ctx, (uint32_t)cb, best_w);
+        if (ct) (void)hipFree(ct);
+        if (out) (void)hipFree(out);
+        pmk_plan_destroy(pl);
+    }
+    (void)hipStreamDestroy(st);
+    if (rc != PMK_OK) return rc;
+    if (cache_path) {
+        FILE *f = std::fopen(cache_path, "w");
+        if (!f) return set_err(ctx, PMK_EINVAL, "cannot write autotune cache %s", cache_path);
+        std::fputs(report.c_str(), f);
+        std::fclose(f);
+    }
+    return PMK_OK;
 }
 
 int pmk_plan_check(pmk_plan *pl, void *stream) {

@@ -148,8 +148,8 @@ int launch_encrypt(const ClassRun &r, void *stream);
 int launch_decrypt_halves(const ClassRun &r, void *stream);
 int launch_garner(const ClassRun &r, void *stream);
 int launch_unpack(const ClassRun &r, uint8_t *dst, int decrypt, void *stream);
-// table words needed per wave slot for a class
-uint64_t table_words_per_slot(int cls, int decrypt);
+// table words needed per wave slot for a class (decryption: at window width win)
+uint64_t table_words_per_slot(int cls, int decrypt, int win);
 // resident wave slots the persistent kernels of a class use
 uint32_t wave_slots(int cls, int decrypt, int num_cus);
 // work units (wavefronts' worth of bignums) of the exponentiation kernels
@@ -158,6 +158,7 @@ uint32_t exp_units(int cls, int decrypt, uint32_t ntiles);
 int launch_batch(const BatchArgs &a, int decrypt, uint32_t grid, void *stream);
 int launch_counter_reset(uint32_t *counter, void *stream);
 uint32_t batch_wave_slots(int decrypt, int num_cus);
-uint64_t batch_slot_words(int decrypt);
+// table words per wave slot of the wide batch kernel; win[i] is the window of wide_class(i)
+uint64_t batch_slot_words(int decrypt, const int *win);
 
 }  // namespace pmk

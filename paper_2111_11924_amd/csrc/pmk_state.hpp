@@ -1,0 +1,171 @@
+// Host-side state of the library (context and plan) and the helpers the
+// API and the request server share.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/pmk.h"
+#include "pmk_internal.hpp"
+
+namespace pmk {
+struct Server;
+}
+using pmk::ClassRun;
+using pmk::kNumClasses;
+using pmk::kWideClasses;
+
+struct KeySlot {
+    int cls;
+    uint32_t slot;  // record index within the class table
+    uint32_t bits;
+    std::vector<uint32_t> n;  // modulus, little-endian limbs (host copy)
+};
+
+struct pmk_ctx {
+    int device = 0;
+    int num_cus = 0;
+    std::string err;
+    std::vector<KeySlot> keys;
+    uint32_t *d_keys[kNumClasses] = {};
+    uint32_t class_count[kNumClasses] = {};
+    int live_plans = 0;
+    std::set<pmk_plan *> plans;
+    int win[kNumClasses] = {};  // CRT-halves window width per class
+    uint32_t epoch = 0;         // bumped when a tuning choice changes (captured graphs go stale)
+    std::string device_name;
+    pmk::Server *server = nullptr;  // request server (pmk_server_start), if running
+};
+
+struct TimedLaunch {
+    int kind;
+    hipEvent_t start, stop;
+};
+
+// a captured launch sequence and the buffers / tuning it was captured for
+struct CapturedGraph {
+    hipGraphExec_t exec = nullptr;
+    const void *in = nullptr;
+    void *out = nullptr;
+    uint32_t epoch = 0;
+};
+
+struct pmk_plan {
+    pmk_ctx *ctx = nullptr;
+    uint64_t msg_len = 0, nchunks = 0, ct_len = 0;
+    ClassRun runs[kNumClasses] = {};
+    std::vector<void *> allocs;
+    uint32_t *d_err = nullptr;
+    bool profile = false;
+    std::vector<TimedLaunch> timed;
+    // batched persistent path (allocated on first use)
+    uint32_t *d_counter = nullptr;     // work counter of the wide batch kernel
+    uint32_t *batch_table = nullptr;   // its window-table slots
+    uint64_t batch_cap = 0;            // words allocated at batch_table
+    uint64_t table_cap[kNumClasses] = {};  // words allocated at runs[c].table
+    uint32_t batch_slots[2] = {};      // its resident waves, [encrypt, decrypt]
+    int batch_win[kWideClasses] = {};  // windows the wide batch kernel runs at
+    CapturedGraph graph[2];                         // [0] encrypt, [1] decrypt
+    hipStream_t capture_stream = nullptr, side_stream = nullptr;
+    hipEvent_t fork_event = nullptr, join_event = nullptr;
+};
+
+namespace pmk {
+
+// Records a message on the context and returns `code`.
+int set_err(pmk_ctx *ctx, int code, const char *fmt, ...);
+// Maps a HIP error to a status (PMK_ENOMEM or PMK_EDEVICE) with a message.
+int hip_err(pmk_ctx *ctx, hipError_t e, const char *where);
+
+template <typename T>
+hipError_t dev_alloc(pmk_plan *pl, T **p, size_t bytes) {
+    void *v = nullptr;
+    hipError_t e = hipMalloc(&v, bytes ? bytes : 4);
+    if (e == hipSuccess) pl->allocs.push_back(v);
+    *p = (T *)v;
+    return e;
+}
+
+void drop_timings(pmk_plan *pl);
+void drop_graphs(pmk_plan *pl);
+void free_plan_memory(pmk_plan *pl);
+// Grows a plan-owned device buffer to at least `need` words (device-synchronous
+// when it reallocates; captured graphs are dropped).
+hipError_t regrow(pmk_plan *pl, uint32_t **p, uint64_t &cap, uint64_t need);
+// Window tables of every class of the plan, sized for the context's windows.
+hipError_t ensure_tables(pmk_plan *pl);
+// Scratch of the batched path (counter, streams, events) and its table.
+int batch_prepare(pmk_plan *pl);
+hipError_t ensure_batch_table(pmk_plan *pl);
+// One uncaptured pass of the batched launch sequence; returns a hipError_t.
+int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, void *stream);
+// Stops and frees the request server of a context (server.cpp).
+void server_shutdown(pmk_ctx *ctx);
+
+// Runs one launcher; with profiling on, brackets it with events on `stream`.
+template <typename F>
+int timed_launch(pmk_plan *pl, int kind, void *stream, F launch) {
+    if (!pl->profile) return launch();
+    TimedLaunch t{kind, nullptr, nullptr};
+    if (hipEventCreate(&t.start) != hipSuccess) return (int)hipErrorOutOfMemory;
+    if (hipEventCreate(&t.stop) != hipSuccess) {
+        (void)hipEventDestroy(t.start);
+        return (int)hipErrorOutOfMemory;
+    }
+    (void)hipEventRecord(t.start, (hipStream_t)stream);
+    const int e = launch();
+    (void)hipEventRecord(t.stop, (hipStream_t)stream);
+    pl->timed.push_back(t);
+    return e;
+}
+
+// Host-side chunk planning shared by pmk_plan_create and pmk_plan_validate.
+// Calls visit(i, key, msg_off, len, ct_off) per chunk; returns status.
+template <typename Visit>
+int walk_chunks(const uint32_t *key_bits, uint32_t nkeys, const uint32_t *key_map, uint64_t nchunks,
+                uint64_t msg_len, uint64_t *ct_len, std::string *why, Visit visit) {
+    if (msg_len == 0) {
+        if (nchunks != 0) {
+            if (why) *why = "empty message needs zero chunks";
+            return PMK_ESIZE;
+        }
+        if (ct_len) *ct_len = 0;
+        return PMK_OK;
+    }
+    if (!key_map) {
+        if (why) *why = "key_map is NULL";
+        return PMK_EINVAL;
+    }
+    uint64_t off = 0, ct = 0;
+    for (uint64_t i = 0; i < nchunks; ++i) {
+        const uint32_t k = key_map[i];
+        if (k >= nkeys) {
+            if (why) *why = "chunk " + std::to_string(i) + " names key " + std::to_string(k);
+            return PMK_EKEY;
+        }
+        const uint64_t cap = key_bits[k] / 8 - 4;
+        if (off >= msg_len) {
+            if (why) *why = "more chunks than the message needs";
+            return PMK_ESIZE;
+        }
+        const uint64_t len = std::min<uint64_t>(cap, msg_len - off);
+        if (i + 1 == nchunks && off + len != msg_len) {
+            if (why) *why = "fewer chunks than the message needs";
+            return PMK_ESIZE;
+        }
+        visit(i, k, off, len, ct);
+        off += len;
+        ct += key_bits[k] / 8;
+    }
+    if (nchunks == 0) {
+        if (why) *why = "non-empty message needs chunks";
+        return PMK_ESIZE;
+    }
+    if (ct_len) *ct_len = ct;
+    return PMK_OK;
+}
+
+}  // namespace pmk

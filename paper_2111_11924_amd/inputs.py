@@ -330,3 +330,52 @@ def config(idx: int) -> Workload:
 
 
 CONFIGS: Dict[int, str] = {i: config(i).name for i in range(1, 6)}
+
+
+@dataclass
+class ServingRequest:
+    """One request of the serving workload: op 0 = encrypt, 1 = decrypt."""
+    op: int
+    msg_len: int
+    keys: List[int]           # the request's key subset (indices into the table)
+    key_map: np.ndarray       # chunk j under keys[j mod len(keys)]
+    msg_seed: int             # seed of its message bytes (make_message)
+
+    def message(self) -> np.ndarray:
+        return make_message(self.msg_len, self.msg_seed)
+
+
+def map_over_subset(msg_len: int, subset: Sequence[int], key_bits: Sequence[int]) -> np.ndarray:
+    """Chunk j of a msg_len-byte message under subset[j mod len(subset)]."""
+    out: List[int] = []
+    off, j = 0, 0
+    while off < msg_len:
+        k = subset[j % len(subset)]
+        out.append(k)
+        off += key_bits[k] // 8 - 4
+        j += 1
+    return np.asarray(out, dtype=np.uint32)
+
+
+def serving_requests(count: int, key_bits: Sequence[int], seed: int = 5, lo: int = 1024,
+                     hi: int = 10 * 1024 * 1024, max_keys: int = 64, decrypt_share: float = 0.5
+                     ) -> List[ServingRequest]:
+    """Requests of the serving workload: sizes log-uniform in [lo, hi] bytes,
+    1..max_keys distinct keys each (uniform count, drawn without replacement),
+    encrypt or decrypt with probability 1 - decrypt_share / decrypt_share."""
+    rng = np.random.Generator(np.random.PCG64(seed * 1000 + 4))
+    reqs = []
+    for i in range(count):
+        size = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        k = int(rng.integers(1, max_keys + 1))
+        subset = [int(x) for x in rng.choice(len(key_bits), size=min(k, len(key_bits)), replace=False)]
+        op = int(rng.random() < decrypt_share)
+        reqs.append(ServingRequest(op, size, subset, map_over_subset(size, subset, key_bits),
+                                   seed * 100000 + i))
+    return reqs
+
+
+def poisson_arrivals(count: int, rate_per_s: float, seed: int = 5) -> np.ndarray:
+    """Arrival offsets in seconds of a Poisson process of the given rate."""
+    rng = np.random.Generator(np.random.PCG64(seed * 1000 + 4 + 7919))
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=count))

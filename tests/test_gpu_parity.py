@@ -329,3 +329,31 @@ def test_window_width_never_changes_results(torch, ctx, win):
             ctx.set_window(b, default[b])
     with pytest.raises(binding.PmkError):
         ctx.set_window(2048, 7)
+
+
+def test_autotune_cache_and_results(torch, ctx, tmp_path):
+    bits = [2048, 1024, 512]
+    keys = inputs.make_keys(bits, 840)
+    ctx.load_keys(keys)
+    default = {b: ctx.window(b) for b in bits}
+    cache = str(tmp_path / "tune.txt")
+    try:
+        ctx.autotune(cache)
+        lines = open(cache).read().splitlines()
+        assert lines[0].startswith("pmk-autotune 1 ")
+        chosen = {int(l.split()[0]): int(l.split()[1]) for l in lines[1:]}
+        assert set(chosen) == set(bits)
+        for b in bits:
+            assert ctx.window(b) == chosen[b]
+            assert chosen[b] in ((4, 5, 6) if b >= 1024 else (3, 4, 5))
+        # the cache is applied without measuring
+        for b in bits:
+            ctx.set_window(b, 2)
+        ctx.autotune(cache)
+        assert all(ctx.window(b) == chosen[b] for b in bits)
+        msg = inputs.make_message(30_000 + 3, 840)
+        km = inputs.random_map(len(msg), bits, 840)
+        check_against_oracle(torch, ctx, keys, msg, km)
+    finally:
+        for b in bits:
+            ctx.set_window(b, default[b])
