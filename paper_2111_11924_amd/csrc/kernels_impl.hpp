@@ -178,6 +178,63 @@ PMK_DEV void load_digit(uint32_t (&x)[NL], const uint32_t *tbl, uint32_t e, int 
     }
 }
 
+// The CRT-halves table of the one-lane classes uses 16-byte rows instead:
+// [entry][group of 4 limbs][lane] uint4 values, so one digit's entry can be
+// copied into LDS by global_load_lds_dwordx4 (lane i's 16 bytes land at
+// dst + 16 i) while the digit's squarings run, without holding registers.
+template <int NL>
+PMK_DEV void store_row4(uint32_t *tbl, uint32_t e, int lane, const uint32_t (&x)[NL]) {
+    constexpr int G4 = (NL + 3) / 4;
+    uint4 *t = reinterpret_cast<uint4 *>(fresh(tbl)) + (size_t)e * G4 * kTile + lane;
+#pragma unroll
+    for (int g = 0; g < G4; ++g) {
+        uint4 v;
+        v.x = x[4 * g];
+        v.y = 4 * g + 1 < NL ? x[4 * g + 1] : 0u;
+        v.z = 4 * g + 2 < NL ? x[4 * g + 2] : 0u;
+        v.w = 4 * g + 3 < NL ? x[4 * g + 3] : 0u;
+        t[(size_t)g * kTile] = v;
+    }
+}
+template <int NL>
+PMK_DEV void load_row4(uint32_t (&x)[NL], const uint32_t *tbl, uint32_t e, int lane) {
+    constexpr int G4 = (NL + 3) / 4;
+    const uint4 *t = reinterpret_cast<const uint4 *>(fresh(tbl)) + (size_t)e * G4 * kTile + lane;
+#pragma unroll
+    for (int g = 0; g < G4; ++g) {
+        const uint4 v = t[(size_t)g * kTile];
+        x[4 * g] = v.x;
+        if (4 * g + 1 < NL) x[4 * g + 1] = v.y;
+        if (4 * g + 2 < NL) x[4 * g + 2] = v.z;
+        if (4 * g + 3 < NL) x[4 * g + 3] = v.w;
+    }
+}
+// start copying entry e of this wave's table into lds[G4 * 64 * 4] (asynchronous)
+template <int NL>
+PMK_DEV void prefetch_row4(uint32_t *lds, const uint32_t *tbl, uint32_t e, int lane) {
+    constexpr int G4 = (NL + 3) / 4;
+    const uint4 *t = reinterpret_cast<const uint4 *>(fresh(tbl)) + (size_t)e * G4 * kTile + lane;
+#pragma unroll
+    for (int g = 0; g < G4; ++g)
+        __builtin_amdgcn_global_load_lds((const void *)(t + (size_t)g * kTile),
+                                         (__attribute__((address_space(3))) void *)(lds + g * kTile * 4), 16, 0, 0);
+}
+// wait for the copy, then read this lane's limbs out of LDS
+template <int NL>
+PMK_DEV void take_row4(uint32_t (&x)[NL], const uint32_t *lds, int lane) {
+    constexpr int G4 = (NL + 3) / 4;
+    __builtin_amdgcn_s_waitcnt(0);
+    const uint4 *t = reinterpret_cast<const uint4 *>(lds) + lane;
+#pragma unroll
+    for (int g = 0; g < G4; ++g) {
+        const uint4 v = t[g * kTile];
+        x[4 * g] = v.x;
+        if (4 * g + 1 < NL) x[4 * g + 1] = v.y;
+        if (4 * g + 2 < NL) x[4 * g + 2] = v.z;
+        if (4 * g + 3 < NL) x[4 * g + 3] = v.w;
+    }
+}
+
 PMK_DEV uint32_t wave_max(uint32_t v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -246,7 +303,7 @@ PMK_DEV uint32_t digit_of(const uint32_t *d, int SH, int k, int w) {
 }
 
 template <int CB>
-PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl) {
+PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t *lds) {
     constexpr Geom G = make_geom(CB);
     constexpr int NL = G.nlh, LB = G.lbh, S = G.S, SH = G.SH;
     const int win = r.win, T = 1 << win;
@@ -277,7 +334,7 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl) {
         }
 #pragma unroll
         for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j + NL);
-        store_entry(tbl, 0, lane, acc);  // c_hi, parked in entry 0 until it is used
+        store_row4(tbl, 0, lane, acc);  // c_hi, parked in entry 0 until it is used
 #pragma unroll
         for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j);
     }
@@ -288,29 +345,35 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl) {
     //   0  MM(c_lo, R^2) = c_lo R mod p            (parked in T[1])
     //   1  MM(c_hi, R^3) = c_hi R^2 mod p; x~ = sum (below 4p), T[1] = x~
     //   2  T[e] = T[e-1] x~ for e = 2 .. T-1
-    //   3  per digit below the top one: win squarings, then times T[digit]
+    //   3  per digit below the top one: win squarings (while T[digit] is
+    //      copied into LDS), then times T[digit]
     //   4  MM(., 1): leave Montgomery form
     int phase = 0, e = 2, digit = NW - 2, sq = 0;
     for (;;) {
         if (phase == 3) {
             if (sq < win) {
+                if (sq == 0) prefetch_row4<NL>(lds, tbl, digit_of(dexp, SH, digit, win), lane);
                 mont_sqr<NL, LB>(acc, acc, n, n0);
                 ++sq;
                 continue;
             }
-            load_digit(b, tbl, digit_of(dexp, SH, digit, win), lane, one_h);
+            take_row4(b, lds, lane);
         }
         mont_mul<NL, LB>(acc, acc, b, n, n0);
         if (phase == 4) break;
         if (phase == 0) {
-            store_entry(tbl, 1, lane, acc);
-            load_entry(acc, tbl, 0, lane);
+            store_row4(tbl, 1, lane, acc);
+            load_row4(acc, tbl, 0, lane);
             load_limbs(b, hr + G.h_rrr);
             phase = 1;
+            // table-building steps leave nothing in flight: the wait the
+            // compiler puts where the digit loop joins them would otherwise
+            // also wait for the digit prefetch
+            __builtin_amdgcn_s_waitcnt(0);
             continue;
         }
         if (phase == 1) {
-            load_entry(b, tbl, 1, lane);
+            load_row4(b, tbl, 1, lane);
             uint32_t c = 0;
 #pragma unroll
             for (int j = 0; j < NL; ++j) {
@@ -318,20 +381,25 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl) {
                 acc[j] = v & Radix<LB>::MASK;
                 c = v >> LB;
             }
-            store_entry(tbl, 1, lane, acc);
+            store_row4(tbl, 1, lane, acc);
 #pragma unroll
             for (int j = 0; j < NL; ++j) b[j] = acc[j];  // x~, the multiplier of phase 2
             phase = 2;
+            __builtin_amdgcn_s_waitcnt(0);
         } else if (phase == 2) {
-            store_entry(tbl, e, lane, acc);
+            store_row4(tbl, e, lane, acc);
             ++e;
+            __builtin_amdgcn_s_waitcnt(0);
         } else {  // phase 3: the digit's multiply is done
             --digit;
             sq = 0;
         }
         if (phase == 2 && e == T) {
-            // table complete: start from the top digit
-            load_digit(acc, tbl, digit_of(dexp, SH, NW - 1, win), lane, one_h);
+            // table complete: T[0] = R mod p (the Montgomery one), start from the top digit
+            load_limbs(b, one_h);
+            store_row4(tbl, 0, lane, b);
+            load_row4(acc, tbl, digit_of(dexp, SH, NW - 1, win), lane);
+            __builtin_amdgcn_s_waitcnt(0);
             phase = 3;
         }
         if (phase == 3 && digit < 0) {
@@ -603,7 +671,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kDecWaves<CB
         __shared__ uint32_t lds[lds_words_dec<CB>()];
         for (uint32_t u = blockIdx.x; u < r.ntiles; u += gridDim.x) halves_lanes_unit<CB>(r, u, tbl, lds);
     } else {
-        for (uint32_t u = blockIdx.x; u < 2 * r.ntiles; u += gridDim.x) halves_unit<CB>(r, u, tbl);
+        __shared__ uint32_t lds[pad4(make_geom(CB).nlh) * kTile];  // one prefetched table entry
+        for (uint32_t u = blockIdx.x; u < 2 * r.ntiles; u += gridDim.x) halves_unit<CB>(r, u, tbl, lds);
     }
 }
 
