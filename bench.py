@@ -51,6 +51,29 @@ def enc_products(bits: int, e: int = 65537) -> int:
 # clock, 64 lanes per compute unit, 256 compute units, 2.4 GHz.
 PEAK_MAD_PER_S = 256 * 64 * 2.4e9
 
+# HBM traffic of one CRT-halves launch on the 100 MiB workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) of
+# `bench.py --no-serve --steps 2 --warmup 1 --no-cpu-baseline`, each scaled by
+# what the counter reads for a plain 256 MiB device copy (bench.py
+# --copy-probe 256: FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of
+# them).  Valid only for the kernel sources it was measured on (hash below);
+# reported as null otherwise.
+HALVES_TRAFFIC = {"sources_sha256": "5c1fb9984b871653e24b7308b5f439b2cf96364d1ee2fbb69d474bcadaafad8d",
+                  "fetch_bytes": 26_227_546_870, "write_bytes": 4_805_691_392}
+KERNEL_SOURCES = ["paper_2111_11924_amd/csrc/kernels_impl.hpp", "paper_2111_11924_amd/csrc/mont.hpp",
+                  "paper_2111_11924_amd/csrc/mont_lanes.hpp", "paper_2111_11924_amd/csrc/pmk_internal.hpp",
+                  "paper_2111_11924_amd/csrc/kernels_class.inc", "paper_2111_11924_amd/csrc/k2048.hip"]
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def cpu_baseline(keys, msg, km, sample_chunks: int):
     """The C oracle (schoolbook products, Knuth D remainders, CRT) on the host
@@ -174,6 +197,8 @@ def main() -> int:
     ap.add_argument("--autotune", action="store_true",
                     help="pick each class's CRT window by timing on this device first (pmk_autotune)")
     ap.add_argument("--window", type=int, default=0, help="fix the CRT window width of every class")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the short serving pass that fills p99_request_ms")
     ap.add_argument("--serve", action="store_true",
                     help="serving workload only: capacity, then Poisson loads 0.5/0.8/1.2 of it")
     ap.add_argument("--serve-requests", type=int, default=0,
@@ -285,6 +310,10 @@ def main() -> int:
     halves_avg_s = halves_ms / max(prof_steps, 1) / 1e3
     achieved = halves_work / halves_avg_s
 
+    traffic = None
+    if (args.config == 4 and args.window in (0, 5) and not args.autotune and HALVES_TRAFFIC["fetch_bytes"]
+            and HALVES_TRAFFIC["sources_sha256"] == kernel_sources_sha256()):
+        traffic = HALVES_TRAFFIC["fetch_bytes"] + HALVES_TRAFFIC["write_bytes"]
     wall_s = t1 - t0
     ms_per_step = wall_s * 1e3 / args.steps
     mib = len(msg) / 2**20
@@ -325,7 +354,7 @@ def main() -> int:
             "peak": PEAK_MAD_PER_S / 1e12,
             "unit": "Tmad/s (32x32->64 integer multiply-add)",
             "frac": achieved / PEAK_MAD_PER_S,
-            "traffic": None,
+            "traffic": traffic,
             "work_per_step": halves_work,
             "avg_launch_ms": halves_ms / max(halves_n, 1),
             "launches_per_step": halves_n / max(prof_steps, 1),
@@ -336,10 +365,19 @@ def main() -> int:
     if args.config != 4:
         out["metric"] = f"CRT decrypt modexp/s, workload {w.name}"
         out["unit"] = "CRT decrypt modexp/s (whole encrypt+decrypt steps)"
-    if not args.no_cpu_baseline and args.config == 4:
-        out["cpu_baseline"] = cpu_baseline(keys, msg, km, args.cpu_sample)
     plan.close()
     ctx.close()
+    if not args.no_serve and args.config == 4:
+        # serving workload after the timed region: p99 at 0.8 of capacity
+        sv = serve_measure(args.serve_requests or 300, [0.8])
+        out["p99_request_ms"] = sv["points"][0]["p99_ms"]
+        out["serving"] = {"workload": "serving-512keys-mixed", "requests": sv["requests"],
+                          "capacity_req_per_s": sv["capacity_req_per_s"], "capacity_MiBps": sv["capacity_MiBps"],
+                          "load": 0.8, "p50_ms": sv["points"][0]["p50_ms"], "p99_ms": sv["points"][0]["p99_ms"],
+                          "results_ok": sv["results_ok"]}
+        ok = ok and sv["results_ok"]
+    if not args.no_cpu_baseline and args.config == 4:
+        out["cpu_baseline"] = cpu_baseline(keys, msg, km, args.cpu_sample)
     print(json.dumps(out))
     return 0 if ok else 1
 

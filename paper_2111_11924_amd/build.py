@@ -18,6 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(PKG, "libpmk.so")
+PROBE = os.path.join(ROOT, "_build", "mad_rate")  # VALU issue-rate probe (python -m paper_2111_11924_amd.peak)
 
 SOURCES = ["kbatch.hip", "k4096.hip", "k3072.hip", "k2048.hip", "k1024.hip", "k512.hip", "k256.hip", "k128.hip",
            "dispatch.cpp", "pmk_api.cpp", "keyprep.cpp", "server.cpp"]
@@ -38,10 +39,19 @@ def _compile(src: str) -> str:
     return out
 
 
+def build_probe() -> str:
+    tmp = PROBE + f".{os.getpid()}.tmp"
+    subprocess.check_call([HIPCC, "-O3", "-std=c++17"] + DEVICE + [os.path.join(CSRC, "mad_rate.hip"), "-o", tmp])
+    os.replace(tmp, PROBE)
+    return PROBE
+
+
 def build(jobs: int = 8, verbose: bool = True) -> str:
     os.makedirs(OBJ, exist_ok=True)
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        probe = ex.submit(build_probe)
         objs = list(ex.map(_compile, SOURCES))
+        probe.result()
     tmp = LIB + f".{os.getpid()}.tmp"
     subprocess.check_call([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs)
     os.replace(tmp, LIB)
