@@ -118,7 +118,7 @@ def cpu_baseline(keys, msg, km, sample_chunks: int):
     }
 
 
-def serve_measure(nreq: int, loads, seed: int = 5, staging_mib: int = 2048):
+def serve_measure(nreq: int, loads, seed: int = 5, staging_mib: int = 2048, round_chunks: int = 0):
     """Serving workload: a 512-key device table (1024..4096-bit keys), requests
     of 1 KiB-10 MiB (log-uniform) over 1-64 keys each, half encryptions and
     half CRT decryptions.  First the closed-loop capacity (all requests queued
@@ -135,7 +135,7 @@ def serve_measure(nreq: int, loads, seed: int = 5, staging_mib: int = 2048):
     msgs = [r.message() for r in reqs]
     ctx = binding.Context(0)
     ctx.load_keys(keys)
-    srv = ctx.server(staging_bytes=staging_mib << 20)
+    srv = ctx.server(staging_bytes=staging_mib << 20, round_chunks=round_chunks)
     try:
         # ciphertexts of the decryption requests, made outside any timing
         pend = [(i, srv.submit(binding.PMK_OP_ENCRYPT, msgs[i], len(msgs[i]), r.key_map))
@@ -203,6 +203,8 @@ def main() -> int:
                     help="serving workload only: capacity, then Poisson loads 0.5/0.8/1.2 of it")
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests per serving point (default: 2000 with --serve, 300 for the headline p99)")
+    ap.add_argument("--round-chunks", type=int, default=0,
+                    help="server: most chunks per batching round (0: the library default)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -224,7 +226,8 @@ def main() -> int:
     from paper_2111_11924_amd import binding, inputs
 
     if args.serve:
-        res = serve_measure(args.serve_requests or 2000, [0.5, 0.8, 1.2])
+        res = serve_measure(args.serve_requests or 2000, [0.5, 0.8, 1.2], round_chunks=args.round_chunks)
+        res["round_chunks"] = args.round_chunks
         res.update({"metric": "p99 request latency, serving workload (512 keys, 1 KiB-10 MiB requests)",
                     "unit": "ms", "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
                     "value": res["points"][1]["p99_ms"], "config": {"workload": "serving-512keys-mixed",
@@ -369,7 +372,7 @@ def main() -> int:
     ctx.close()
     if not args.no_serve and args.config == 4:
         # serving workload after the timed region: p99 at 0.8 of capacity
-        sv = serve_measure(args.serve_requests or 300, [0.8])
+        sv = serve_measure(args.serve_requests or 300, [0.8], round_chunks=args.round_chunks)
         out["p99_request_ms"] = sv["points"][0]["p99_ms"]
         out["serving"] = {"workload": "serving-512keys-mixed", "requests": sv["requests"],
                           "capacity_req_per_s": sv["capacity_req_per_s"], "capacity_MiBps": sv["capacity_MiBps"],

@@ -45,7 +45,8 @@ enum {
     PMK_ENOMEM = -5,      /* device or host allocation failed */
     PMK_EDEVICE = -6,     /* HIP runtime error */
     PMK_EBUSY = -7,       /* keys replaced while plans made from them still exist */
-    PMK_EUNSUPPORTED = -8 /* modulus size or exponent the library has no kernel for */
+    PMK_EUNSUPPORTED = -8, /* modulus size or exponent the library has no kernel for */
+    PMK_EBLIND = -9        /* a blinding ciphertext block c_R is not invertible modulo N */
 };
 
 typedef struct pmk_ctx pmk_ctx;
@@ -153,6 +154,24 @@ int pmk_encrypt_plan(pmk_plan *plan, const uint8_t *d_msg, uint8_t *d_ct, void *
 int pmk_decrypt_plan(pmk_plan *plan, const uint8_t *d_ct, uint8_t *d_msg, void *stream);
 
 /*
+ * Blinded PMKRSA (Sec. 3.1, Eqs. 3-10, Algorithm 1 with its blinding factor R).
+ * Encryption takes one blinding factor r_i per chunk in d_r -- laid out like
+ * ciphertext blocks: kb_i bytes big-endian per chunk, ct_len bytes in all, each
+ * 1 <= r_i < N with gcd(r_i, N) = 1 (the caller draws them) -- and writes
+ * c*_i = (r_i m_i)^e mod N to d_ct_star and c_R,i = r_i^e mod N to d_ct_r (ct_len
+ * bytes each, same block layout).  Decryption computes
+ * m_i = (c*_i)^d (c_R,i^d)^-1 mod N, i.e. r'_i = c_R,i^d = r_i is divided out,
+ * through CRT: per prime, (c*)^(d_p) times c_R^(p-1-d_p) (Fermat's inverse),
+ * then Garner.  A c* or c_R block not below N sets PMK_ERANGE, a c_R divisible
+ * by p or q sets PMK_EBLIND (both from pmk_plan_check).  Asynchronous on
+ * `stream`; every buffer device memory, 4-byte aligned.
+ */
+int pmk_encrypt_blinded_plan(pmk_plan *plan, const uint8_t *d_msg, const uint8_t *d_r, uint8_t *d_ct_star,
+                             uint8_t *d_ct_r, void *stream);
+int pmk_decrypt_blinded_plan(pmk_plan *plan, const uint8_t *d_ct_star, const uint8_t *d_ct_r, uint8_t *d_msg,
+                             void *stream);
+
+/*
  * Batched form (the parallel loops of Algorithm 1 run as a work queue): the
  * exponentiations of every chunk under 3072- and 4096-bit keys run in ONE
  * persistent kernel whose waves take work units (tiles of chunks under one
@@ -199,7 +218,7 @@ int pmk_autotune(pmk_ctx *ctx, const char *cache_path, int flags);
 
 /*
  * Wait for `stream`, then return and clear the plan's device-detected error
- * (PMK_OK or PMK_ERANGE).
+ * (PMK_OK, PMK_ERANGE or PMK_EBLIND).
  */
 int pmk_plan_check(pmk_plan *plan, void *stream);
 
@@ -217,8 +236,9 @@ enum {
     PMK_KERNEL_CRT_HALVES = 2, /* m_p = c^dp mod p, m_q = c^dq mod q */
     PMK_KERNEL_GARNER = 3,     /* CRT recombination */
     PMK_KERNEL_UNPACK = 4,     /* limbs -> bytes */
-    PMK_KERNEL_BATCH = 5,      /* persistent batched exponentiation (1024..4096-bit classes) */
-    PMK_KERNEL_KINDS = 6
+    PMK_KERNEL_BATCH = 5,      /* persistent batched exponentiation (3072/4096-bit classes) */
+    PMK_KERNEL_BLIND = 6,      /* blinded decryption: product of the two CRT half results */
+    PMK_KERNEL_KINDS = 7
 };
 int pmk_plan_profile(pmk_plan *plan, int enable);
 int pmk_plan_kernel_time(pmk_plan *plan, int kind, double *ms_total, uint64_t *launches);

@@ -26,6 +26,7 @@ PMK_ENOMEM = -5
 PMK_EDEVICE = -6
 PMK_EBUSY = -7
 PMK_EUNSUPPORTED = -8
+PMK_EBLIND = -9
 
 PMK_KERNEL_PACK = 0
 PMK_KERNEL_ENCRYPT = 1
@@ -33,10 +34,12 @@ PMK_KERNEL_CRT_HALVES = 2
 PMK_KERNEL_GARNER = 3
 PMK_KERNEL_UNPACK = 4
 PMK_KERNEL_BATCH = 5
-KERNEL_NAMES = {0: "pack", 1: "encrypt", 2: "crt_halves", 3: "garner", 4: "unpack", 5: "batch"}
+PMK_KERNEL_BLIND = 6
+KERNEL_NAMES = {0: "pack", 1: "encrypt", 2: "crt_halves", 3: "garner", 4: "unpack", 5: "batch", 6: "blind"}
 
 STATUS_NAMES = {0: "PMK_OK", -1: "PMK_EINVAL", -2: "PMK_EKEY", -3: "PMK_ERANGE", -4: "PMK_ESIZE",
-                -5: "PMK_ENOMEM", -6: "PMK_EDEVICE", -7: "PMK_EBUSY", -8: "PMK_EUNSUPPORTED"}
+                -5: "PMK_ENOMEM", -6: "PMK_EDEVICE", -7: "PMK_EBUSY", -8: "PMK_EUNSUPPORTED",
+                -9: "PMK_EBLIND"}
 
 U32P = C.POINTER(C.c_uint32)
 
@@ -106,6 +109,8 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "pmk_plan_info": (C.c_int, [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]),
         "pmk_encrypt_plan": (C.c_int, [vp, vp, vp, vp]),
         "pmk_decrypt_plan": (C.c_int, [vp, vp, vp, vp]),
+        "pmk_encrypt_blinded_plan": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "pmk_decrypt_blinded_plan": (C.c_int, [vp, vp, vp, vp, vp]),
         "pmk_encrypt_batch": (C.c_int, [vp, vp, vp, vp]),
         "pmk_decrypt_batch": (C.c_int, [vp, vp, vp, vp]),
         "pmk_set_window": (C.c_int, [vp, u32, C.c_int]),
@@ -268,6 +273,16 @@ def pmk_decrypt_plan(plan: int, d_ct, d_msg, stream=None, ctx: Optional[int] = N
     _check(load_library().pmk_decrypt_plan(plan, _dev_ptr(d_ct), _dev_ptr(d_msg), _stream(stream)), ctx)
 
 
+def pmk_encrypt_blinded_plan(plan: int, d_msg, d_r, d_ct_star, d_ct_r, stream=None, ctx: Optional[int] = None) -> None:
+    _check(load_library().pmk_encrypt_blinded_plan(plan, _dev_ptr(d_msg), _dev_ptr(d_r), _dev_ptr(d_ct_star),
+                                                   _dev_ptr(d_ct_r), _stream(stream)), ctx)
+
+
+def pmk_decrypt_blinded_plan(plan: int, d_ct_star, d_ct_r, d_msg, stream=None, ctx: Optional[int] = None) -> None:
+    _check(load_library().pmk_decrypt_blinded_plan(plan, _dev_ptr(d_ct_star), _dev_ptr(d_ct_r), _dev_ptr(d_msg),
+                                                   _stream(stream)), ctx)
+
+
 def pmk_encrypt_batch(plan: int, d_msg, d_ct, stream=None, ctx: Optional[int] = None) -> None:
     _check(load_library().pmk_encrypt_batch(plan, _dev_ptr(d_msg), _dev_ptr(d_ct), _stream(stream)), ctx)
 
@@ -390,6 +405,24 @@ class Plan:
             msg = torch.empty(max(self.msg_len, 4), dtype=torch.uint8, device=ct.device)
         fn = pmk_decrypt_batch if batch else pmk_decrypt_plan
         fn(self.handle, ct, msg, stream, self.ctx.handle)
+        return msg
+
+    def encrypt_blinded(self, msg, r, stream=None):
+        """(c*, c_R) device tensors for message `msg` and blinding blocks `r`."""
+        import torch
+
+        n = max(self.ct_len, 4)
+        cs = torch.empty(n, dtype=torch.uint8, device=msg.device)
+        cr = torch.empty(n, dtype=torch.uint8, device=msg.device)
+        pmk_encrypt_blinded_plan(self.handle, msg, r, cs, cr, stream, self.ctx.handle)
+        return cs, cr
+
+    def decrypt_blinded(self, ct_star, ct_r, msg=None, stream=None):
+        import torch
+
+        if msg is None:
+            msg = torch.empty(max(self.msg_len, 4), dtype=torch.uint8, device=ct_star.device)
+        pmk_decrypt_blinded_plan(self.handle, ct_star, ct_r, msg, stream, self.ctx.handle)
         return msg
 
     def check(self, stream=None) -> int:

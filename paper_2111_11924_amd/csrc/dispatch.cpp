@@ -11,6 +11,7 @@ namespace pmk {
     int launch_encrypt_##B(const ClassRun &, hipStream_t);                                 \
     int launch_halves_##B(const ClassRun &, hipStream_t);                                  \
     int launch_garner_##B(const ClassRun &, hipStream_t);                                  \
+    int launch_blind_combine_##B(const ClassRun &, const uint32_t *, hipStream_t);         \
     uint32_t wave_slots_##B(int, int);                                                     \
     uint64_t slot_words_##B(int, int);
 PMK_DECLARE(128)
@@ -52,6 +53,10 @@ int launch_decrypt_halves(const ClassRun &r, void *stream) {
 int launch_garner(const ClassRun &r, void *stream) {
     if (r.ntiles == 0) return 0;
     PMK_DISPATCH(r.cls, launch_garner, r, (hipStream_t)stream);
+}
+int launch_blind_combine(const ClassRun &r, const uint32_t *half2, void *stream) {
+    if (r.ntiles == 0) return 0;
+    PMK_DISPATCH(r.cls, launch_blind_combine, r, half2, (hipStream_t)stream);
 }
 
 uint64_t table_words_per_slot(int cls, int decrypt, int win) {

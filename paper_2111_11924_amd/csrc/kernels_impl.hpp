@@ -279,9 +279,17 @@ PMK_DEV void encrypt_unit(const ClassRun r, uint32_t tile, uint32_t *tbl) {
             mont_mul<NL, LB>(acc, acc, b, n, n0);
         }
     }
+    // leave Montgomery form: MM(x~^e, 1) = x^e; with a final factor v,
+    // MM(x~^e, v) = x^e v mod N (blinded encryption: m^e r^e = (m r)^e)
+    if (r.fin32) {
+        const uint32_t *v = r.fin32 + (size_t)tile * S * kTile + lane;
 #pragma unroll
-    for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
-    mont_mul<NL, LB>(acc, acc, b, n, n0);  // leave Montgomery form
+        for (int j = 0; j < NL; ++j) b[j] = radix_limb_mem<S, LB>(v, kTile, j);
+    } else {
+#pragma unroll
+        for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
+    }
+    mont_mul<NL, LB>(acc, acc, b, n, n0);
     canonicalize<NL, LB>(acc, n);
 #pragma unroll
     for (int k = 0; k < S; ++k) r.y32[((size_t)tile * S + k) * kTile + lane] = radix_word<NL, LB>(acc, k);
@@ -316,7 +324,7 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t 
     uint32_t n[NL];
     load_uniform(n, hr + G.h_m);
     const uint32_t n0 = uni(hr[G.h_m0]);
-    const uint32_t *dexp = hr + G.h_d;
+    const uint32_t *dexp = hr + (r.exp_sel ? G.h_d2 : G.h_d);
     const uint32_t *one_h = hr + G.h_one;
 
     uint32_t acc[NL], b[NL];
@@ -516,7 +524,14 @@ PMK_DEV void encrypt_lanes_unit(const ClassRun r, uint32_t tile, uint32_t *tbl, 
             stage_limbs(col, NG, pos, acc);
         } else {
             phase = 3;
-            stage_one<K>(col, NG, pos);
+            if (r.fin32) {
+                // final factor v (blinded encryption): this lane's K limbs of v into the column
+                const uint32_t *v = fresh_v(r.fin32 + (size_t)tile * S * NG + grp);
+#pragma unroll 1
+                for (int j = 0; j < K; ++j) col[(pos * K + j) * NG] = radix_limb_mem<S, LB>(v, NG, pos * K + j);
+            } else {
+                stage_one<K>(col, NG, pos);
+            }
         }
     }
     canonicalize_lanes<K, LB, L>(acc, n, pos);
@@ -550,7 +565,7 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t tile, uint32_t *tbl, u
     uint32_t n[K];
     load_limbs(n, fresh_v(hr + G.h_m + pos * K));
     const uint32_t n0 = hr[G.h_m0];
-    const uint32_t *dexp = hr + G.h_d;
+    const uint32_t *dexp = hr + (r.exp_sel ? G.h_d2 : G.h_d);
 
     uint32_t acc[K];
     for (int k = pos; k < S; k += L) col[k * NG] = r.x32[((size_t)tile * S + k) * CPT + c];
@@ -730,6 +745,46 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(make_geom(CB
     if (slot0 < nslots) {
 #pragma unroll
         for (int k = 0; k < S; ++k) y32[((size_t)tile * S + k) * CPT + c] = radix_word<2 * NL, LB>(m, k);
+    }
+}
+
+// ------------------------------------------------------------------ blinding
+// Blinded decryption (Sec. 3.1, Algorithm 1): with a = c* mod p_h and
+// b = c_R mod p_h, m mod p_h = a^d * (b^d)^-1 = a^d * b^(p_h - 1 - d).  The two
+// exponentiations land in half (a^d) and half2 (b^(p_h-1-d)); this kernel
+// multiplies them: half[h] = MM(MM(x, y), R^2) mod p_h, canonical.  y = 0 means
+// b is divisible by p_h (the blinding factor shares a prime with N): flagged.
+// Grid: (slots / 64, 2), one lane per slot of prime h = blockIdx.y.
+template <int CB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(make_geom(CB).nlh > 40 ? 1 : 2))) void blind_combine_kernel(
+    const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc, uint32_t nslots,
+    uint32_t *__restrict__ half, const uint32_t *__restrict__ half2, uint32_t *err) {
+    constexpr Geom G = make_geom(CB);
+    constexpr int NL = G.nlh, LB = G.lbh, CPT = chunks_per_tile(CB);
+    const uint32_t slot0 = blockIdx.x * 64 + threadIdx.x;
+    const uint32_t slot = slot0 < nslots ? slot0 : nslots - 1;
+    const int h = blockIdx.y;
+    const uint32_t tile = slot / CPT, c = slot % CPT;
+    const uint32_t *hr = keys + (size_t)desc[slot].key * G.stride + G.off_half[h];
+    const size_t base = ((size_t)(2 * tile + h) * NL) * CPT + c;
+    uint32_t m[NL], x[NL], y[NL];
+    load_limbs(m, hr + G.h_m);
+    uint32_t any = 0;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+        x[j] = half[base + (size_t)j * CPT];
+        y[j] = half2[base + (size_t)j * CPT];
+        any |= y[j];
+    }
+    const uint32_t n0 = hr[G.h_m0];
+    mont_mul<NL, LB>(x, x, y, m, n0);
+    load_limbs(y, hr + G.h_rr);
+    mont_mul<NL, LB>(x, x, y, m, n0);
+    canonicalize<NL, LB>(x, m);
+    if (slot0 < nslots && desc[slot].msg_len) {
+        if (!any) atomicOr(err, 2u);
+#pragma unroll
+        for (int j = 0; j < NL; ++j) half[base + (size_t)j * CPT] = x[j];
     }
 }
 

@@ -179,7 +179,7 @@ void build_record(const pmk_key &k, int cls, uint32_t *rec) {
     for (int i = 0; i < g.S; ++i) rec[g.off_n32 + i] = n[i];
     to_radix(n, g.lbf, g.nlf, rec + g.off_nf);
     rec[g.off_n0f] = (0u - inv32(n[0])) & ((1u << g.lbf) - 1u);
-    mont_consts(n, g.lbf, g.nlf, rec + g.off_onef, rec + g.off_rrf, nullptr);
+    mont_consts(n, g.lbf, g.nlf, rec + g.off_onef, rec + g.off_rrf, rec + g.off_rrrf);
     const Words e = from(k.e, k.e_limbs, 2);
     rec[g.off_e] = e[0];
     rec[g.off_e + 1] = e[1];
@@ -194,6 +194,11 @@ void build_record(const pmk_key &k, int cls, uint32_t *rec) {
         mont_consts(m, g.lbh, g.nlh, hr + g.h_one, hr + g.h_rr, hr + g.h_rrr);
         const Words d = from(exps[h], SH, g.SH);
         for (int i = 0; i < g.SH; ++i) hr[g.h_d + i] = d[i];
+        // d2 = m - 1 - d: (c^d)^-1 = c^d2 mod m for c not divisible by m (Fermat)
+        Words d2 = m;
+        d2[0] -= 1;  // m is odd, so no borrow
+        sub_in(d2, d);
+        for (int i = 0; i < g.SH; ++i) hr[g.h_d2 + i] = d2[i];
     }
     {
         const Words p = from(k.p, SH, g.SH);

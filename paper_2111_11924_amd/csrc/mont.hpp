@@ -161,6 +161,17 @@ __device__ __forceinline__ void canonicalize(uint32_t (&x)[NL], const uint32_t (
     for (int j = 0; j < NL; ++j) x[j] = keep ? d[j] : x[j];
 }
 
+// The same, reading word k from src[k * stride] (memory instead of registers).
+template <int S, int LB>
+__device__ __forceinline__ uint32_t radix_limb_mem(const uint32_t *src, size_t stride, int j) {
+    const int bit = LB * j;
+    const int k = bit >> 5, sh = bit & 31;
+    const uint32_t lo = k < S ? src[(size_t)k * stride] : 0u;
+    const uint32_t hi = (k + 1) < S ? src[(size_t)(k + 1) * stride] : 0u;
+    const uint64_t v = ((uint64_t)hi << 32) | lo;
+    return (uint32_t)(v >> sh) & Radix<LB>::MASK;
+}
+
 // Limb j of an LB-bit-radix number read out of little-endian 32-bit words w[0..S)
 // (bits [LB*j, LB*j+LB)); words past S read as zero.
 template <int S, int LB>

@@ -355,6 +355,83 @@ int pmk_decrypt_plan(pmk_plan *pl, const uint8_t *d_ct, uint8_t *d_msg, void *st
     return PMK_OK;
 }
 
+static int blind_prepare(pmk_plan *pl) {
+    if (pl->blind_ready) return PMK_OK;
+    for (int c = 0; c < kNumClasses; ++c) {
+        const ClassRun &r = pl->runs[c];
+        if (!r.ntiles) continue;
+        const Geom g = make_geom(kClassBits[c]);
+        const uint64_t tiles = r.ntiles, cpt = (uint64_t)chunks_per_tile(kClassBits[c]);
+        hipError_t e = dev_alloc(pl, &pl->x32b[c], tiles * g.S * cpt * sizeof(uint32_t));
+        if (e == hipSuccess) e = dev_alloc(pl, &pl->half2[c], tiles * 2 * g.nlh * cpt * sizeof(uint32_t));
+        if (e != hipSuccess) return hip_err(pl->ctx, e, "blinding buffers");
+    }
+    pl->blind_ready = true;
+    return PMK_OK;
+}
+
+int pmk_encrypt_blinded_plan(pmk_plan *pl, const uint8_t *d_msg, const uint8_t *d_r, uint8_t *d_ct_star,
+                             uint8_t *d_ct_r, void *stream) {
+    if (!pl) return PMK_EINVAL;
+    pmk_ctx *ctx = pl->ctx;
+    if (pl->msg_len == 0) return PMK_OK;
+    if (!d_msg || !d_r || !d_ct_star || !d_ct_r || !aligned4(d_msg) || !aligned4(d_r) || !aligned4(d_ct_star) ||
+        !aligned4(d_ct_r))
+        return set_err(ctx, PMK_EINVAL, "buffers must be non-NULL and 4-byte aligned");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
+    if (const hipError_t te = ensure_tables(pl)) return hip_err(ctx, te, "window table allocation");
+    int rc = blind_prepare(pl);
+    if (rc != PMK_OK) return rc;
+    for (int c = 0; c < kNumClasses; ++c) {
+        const ClassRun &r = pl->runs[c];
+        if (!r.ntiles) continue;
+        ClassRun rb = r;  // c_R = r^e, from the blinding blocks (packed like ciphertext blocks)
+        rb.x32 = pl->x32b[c];
+        ClassRun star = r;  // c* = m^e c_R = (m r)^e: the last product takes c_R instead of 1
+        star.fin32 = r.y32;
+        int e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(rb, d_r, 1, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_ENCRYPT, stream, [&] { return launch_encrypt(rb, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, d_ct_r, 0, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(r, d_msg, 0, stream); });
+        // each unit reads its tile's c_R words before writing that tile's result over them
+        if (!e) e = timed_launch(pl, PMK_KERNEL_ENCRYPT, stream, [&] { return launch_encrypt(star, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, d_ct_star, 0, stream); });
+        if (e) return hip_err(ctx, (hipError_t)e, "blinded encrypt launch");
+    }
+    return PMK_OK;
+}
+
+int pmk_decrypt_blinded_plan(pmk_plan *pl, const uint8_t *d_ct_star, const uint8_t *d_ct_r, uint8_t *d_msg,
+                             void *stream) {
+    if (!pl) return PMK_EINVAL;
+    pmk_ctx *ctx = pl->ctx;
+    if (pl->msg_len == 0) return PMK_OK;
+    if (!d_msg || !d_ct_star || !d_ct_r || !aligned4(d_msg) || !aligned4(d_ct_star) || !aligned4(d_ct_r))
+        return set_err(ctx, PMK_EINVAL, "buffers must be non-NULL and 4-byte aligned");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
+    if (const hipError_t te = ensure_tables(pl)) return hip_err(ctx, te, "window table allocation");
+    int rc = blind_prepare(pl);
+    if (rc != PMK_OK) return rc;
+    for (int c = 0; c < kNumClasses; ++c) {
+        const ClassRun &r = pl->runs[c];
+        if (!r.ntiles) continue;
+        ClassRun rr = r;  // c_R^(p-1-d_p), c_R^(q-1-d_q) into half2
+        rr.x32 = pl->x32b[c];
+        rr.half = pl->half2[c];
+        rr.exp_sel = 1;
+        int e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(r, d_ct_star, 1, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(rr, d_ct_r, 1, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_CRT_HALVES, stream, [&] { return launch_decrypt_halves(r, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_CRT_HALVES, stream, [&] { return launch_decrypt_halves(rr, stream); });
+        if (!e)
+            e = timed_launch(pl, PMK_KERNEL_BLIND, stream, [&] { return launch_blind_combine(r, pl->half2[c], stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_GARNER, stream, [&] { return launch_garner(r, stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, d_msg, 1, stream); });
+        if (e) return hip_err(ctx, (hipError_t)e, "blinded decrypt launch");
+    }
+    return PMK_OK;
+}
+
 int pmk_plan_profile(pmk_plan *pl, int enable) {
     if (!pl) return PMK_EINVAL;
     (void)hipSetDevice(pl->ctx->device);
@@ -706,7 +783,8 @@ int pmk_plan_check(pmk_plan *pl, void *stream) {
         e = hipMemcpy(pl->d_err, &zero, sizeof zero, hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) return hip_err(ctx, e, "error flag read");
-    if (flag) return set_err(ctx, PMK_ERANGE, "a ciphertext block is not below its modulus");
+    if (flag & 1u) return set_err(ctx, PMK_ERANGE, "a ciphertext block is not below its modulus");
+    if (flag & 2u) return set_err(ctx, PMK_EBLIND, "a blinding block is not invertible modulo N");
     return PMK_OK;
 }
 

@@ -44,10 +44,11 @@ struct Geom {
     int lbf, nlf, lbh, nlh;
     int ew;  // words of the public exponent
     // full-modulus part
-    int off_n32, off_nf, off_n0f, off_rrf, off_onef, off_e, off_ebits, off_kbytes;
-    // half records (p then q): m, m0, rr, rrr, one, d
+    int off_n32, off_nf, off_n0f, off_rrf, off_rrrf, off_onef, off_e, off_ebits, off_kbytes;
+    // half records (p then q): m, m0, rr, rrr, one, d, and d2 = m - 1 - d (the
+    // exponent of the Fermat inverse of c^d, for blinded decryption)
     int off_half[2];
-    int h_m, h_m0, h_rr, h_rrr, h_one, h_d, h_size;
+    int h_m, h_m0, h_rr, h_rrr, h_one, h_d, h_d2, h_size;
     int off_qinvr;
     int stride;
 };
@@ -70,6 +71,7 @@ PMK_HD constexpr Geom make_geom(int bits) {
     int o = 0;
     g.off_nf = o; o += pf;
     g.off_rrf = o; o += pf;
+    g.off_rrrf = o; o += pf;
     g.off_onef = o; o += pf;
     g.off_n32 = o; o += pad4(g.S);
     g.off_n0f = o; o += 1;
@@ -83,7 +85,8 @@ PMK_HD constexpr Geom make_geom(int bits) {
     g.h_one = 3 * ph;
     g.h_m0 = 4 * ph;
     g.h_d = 4 * ph + 4;
-    g.h_size = pad4(4 * ph + 4 + g.SH);
+    g.h_d2 = g.h_d + pad4(g.SH);
+    g.h_size = pad4(g.h_d2 + g.SH);
     g.off_half[0] = o; o += g.h_size;
     g.off_half[1] = o; o += g.h_size;
     g.off_qinvr = o; o += ph;
@@ -118,8 +121,12 @@ struct ClassRun {
     uint32_t *table;           // per resident wave: window table scratch
     uint32_t slots_enc;        // wave slots in `table` for the encryption kernel
     uint32_t slots_dec;        // wave slots in `table` for the CRT-halves kernel
-    uint32_t *err;             // device error word
+    uint32_t *err;             // device error word: bit 0 block >= N, bit 1 blinding factor not invertible
     int win;                   // window width of the CRT-halves exponentiation (3..6)
+    // blinded PMKRSA (Sec. 3.1, Algorithm 1)
+    const uint32_t *fin32;     // encryption: words of a factor v < N the result is multiplied by
+                               // (x^e v mod N; tile layout of y32), nullptr = 1
+    int exp_sel;               // CRT halves: 0 exponents d_p, d_q; 1 exponents p-1-d_p, q-1-d_q
 };
 
 constexpr int kMaxWin = 6;
@@ -147,6 +154,8 @@ int launch_pack(const ClassRun &r, const uint8_t *src, int decrypt, void *stream
 int launch_encrypt(const ClassRun &r, void *stream);
 int launch_decrypt_halves(const ClassRun &r, void *stream);
 int launch_garner(const ClassRun &r, void *stream);
+// blinded decryption: half[h] = half[h] * half2[h] mod p_h for both primes
+int launch_blind_combine(const ClassRun &r, const uint32_t *half2, void *stream);
 int launch_unpack(const ClassRun &r, uint8_t *dst, int decrypt, void *stream);
 // table words needed per wave slot for a class (decryption: at window width win)
 uint64_t table_words_per_slot(int cls, int decrypt, int win);

@@ -71,6 +71,10 @@ struct pmk_plan {
     CapturedGraph graph[2];                         // [0] encrypt, [1] decrypt
     hipStream_t capture_stream = nullptr, side_stream = nullptr;
     hipEvent_t fork_event = nullptr, join_event = nullptr;
+    // blinded PMKRSA: second input tiles and second CRT halves (allocated on first use)
+    uint32_t *x32b[kNumClasses] = {};
+    uint32_t *half2[kNumClasses] = {};
+    bool blind_ready = false;
 };
 
 namespace pmk {

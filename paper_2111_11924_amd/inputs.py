@@ -332,6 +332,23 @@ def config(idx: int) -> Workload:
 CONFIGS: Dict[int, str] = {i: config(i).name for i in range(1, 6)}
 
 
+def make_blinding(keys: Sequence["RsaKey"], key_map: np.ndarray, seed: int) -> np.ndarray:
+    """Blinding factors of the PMKRSA scheme (Sec. 3.1): per chunk an r uniform
+    in [2, N-1] with gcd(r, N) = 1 under the chunk's key, as kb-byte big-endian
+    blocks laid out like the ciphertext (the scheme draws them; here they are
+    seeded inputs)."""
+    rng = np.random.Generator(np.random.PCG64(seed * 1000 + 5))
+    out = []
+    for k in np.asarray(key_map).tolist():
+        key = keys[k]
+        while True:
+            r = 2 + rand_int(rng, key.bits + 64) % (key.n - 2)
+            if math.gcd(r, key.n) == 1:
+                break
+        out.append(np.frombuffer(r.to_bytes(key.bits // 8, "big"), dtype=np.uint8))
+    return np.concatenate(out) if out else np.zeros(0, np.uint8)
+
+
 @dataclass
 class ServingRequest:
     """One request of the serving workload: op 0 = encrypt, 1 = decrypt."""
