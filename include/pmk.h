@@ -172,19 +172,22 @@ int pmk_decrypt_blinded_plan(pmk_plan *plan, const uint8_t *d_ct_star, const uin
                              void *stream);
 
 /*
- * Batched form (the parallel loops of Algorithm 1 run as a work queue): the
- * exponentiations of every chunk under 3072- and 4096-bit keys run in ONE
- * persistent kernel whose waves take work units (tiles of chunks under one
- * key) from a device counter, 4096-bit units first; at the same time, on a
- * second stream, the chunks under smaller keys run their own kernels, largest
- * modulus first.  The whole sequence (packing, exponentiation, CRT
- * recombination, unpacking) is captured once into a HIP graph per (input,
- * output) buffer pair and replayed on `stream`; a new buffer pair or window
- * setting recaptures it.  Results are byte-identical to pmk_encrypt_plan /
- * pmk_decrypt_plan.  With profiling on (pmk_plan_profile) the sequence runs
- * uncaptured so that each launch can be timed.  Same buffer rules and errors
- * as the plan forms; a plan's batch calls must not overlap each other on
- * different streams (they share the plan's work counter and scratch).
+ * Batched form (the parallel loops of Algorithm 1, all size classes at once):
+ * after packing, the exponentiation kernels of the plan's size classes run
+ * side by side on `stream` and internal side streams (default priority),
+ * forked and joined with events, so classes too small to fill the GPU share
+ * it.  Encryption of the 3072- and 4096-bit classes is ONE persistent
+ * work-queue launch whose waves take units (a quarter tile each) from a
+ * device counter, 4096-bit units first; every other exponentiation is its
+ * class's persistent kernel, CRT halves dealt over the streams largest work
+ * first.  The whole sequence (packing, exponentiation, CRT recombination,
+ * unpacking) is captured once into a HIP graph per (input, output) buffer pair
+ * and replayed on `stream`; a new buffer pair or window setting recaptures it.
+ * Results are byte-identical to pmk_encrypt_plan / pmk_decrypt_plan.  With
+ * profiling on (pmk_plan_profile) the sequence runs uncaptured so that each
+ * launch can be timed (concurrent launches then overlap in the sums).  Same
+ * buffer rules and errors as the plan forms; a plan's batch calls must not
+ * overlap each other on different streams (they share its scratch).
  */
 int pmk_encrypt_batch(pmk_plan *plan, const uint8_t *d_msg, uint8_t *d_ct, void *stream);
 int pmk_decrypt_batch(pmk_plan *plan, const uint8_t *d_ct, uint8_t *d_msg, void *stream);
@@ -236,7 +239,7 @@ enum {
     PMK_KERNEL_CRT_HALVES = 2, /* m_p = c^dp mod p, m_q = c^dq mod q */
     PMK_KERNEL_GARNER = 3,     /* CRT recombination */
     PMK_KERNEL_UNPACK = 4,     /* limbs -> bytes */
-    PMK_KERNEL_BATCH = 5,      /* persistent batched exponentiation (3072/4096-bit classes) */
+    PMK_KERNEL_BATCH = 5,      /* persistent work-queue encryption (3072/4096-bit classes) */
     PMK_KERNEL_BLIND = 6,      /* blinded decryption: product of the two CRT half results */
     PMK_KERNEL_KINDS = 7
 };

@@ -73,8 +73,8 @@ uint64_t table_words_per_slot(int cls, int decrypt, int win) {
 }
 
 uint32_t exp_units(int cls, int decrypt, uint32_t ntiles) {
-    if (!decrypt) return ntiles;
-    return lanes_half(kClassBits[cls]) > 1 ? ntiles : 2 * ntiles;
+    // encryption: one wavefront per 64 / lanes_full chunks; CRT halves: one per tile and prime
+    return decrypt ? 2 * ntiles : ntiles * (uint32_t)lanes_full(kClassBits[cls]);
 }
 
 uint32_t wave_slots(int cls, int decrypt, int num_cus) {

@@ -10,10 +10,11 @@
 //   garner    h = qinv (m_p - m_q) mod p, m = m_q + h q (Sec. 2.1)
 //   unpack    32-bit limbs -> big-endian bytes of each block
 //
-// Up to 2048-bit moduli every bignum operation is one lane's work (64 bignums
-// per wavefront, Montgomery products in mont.hpp); 3072- and 4096-bit numbers
-// are spread over 2 or 4 lanes (mont_lanes.hpp).  A tile holds the chunks of
-// one wavefront under one key, so the modulus and exponent are wave-uniform.
+// Every CRT half (up to 2048 bits) and every full-size number up to 2048 bits
+// is one lane's work (64 bignums per wavefront, Montgomery products in
+// mont.hpp); full-size 3072- and 4096-bit numbers (encryption) are spread over
+// 4 lanes (mont_lanes.hpp).  A tile holds 64 chunks under one key, so the
+// modulus and exponent are wave-uniform.
 // The exponentiation kernels are persistent: each 64-thread block owns a
 // scratch slot for its window table and walks tiles blockIdx.x, +gridDim.x, ...
 #pragma once
@@ -329,22 +330,25 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t 
 
     uint32_t acc[NL], b[NL];
     {
-        uint32_t w[S];
-#pragma unroll
-        for (int k = 0; k < S; ++k) w[k] = r.x32[((size_t)tile * S + k) * kTile + lane];
+        // the ciphertext words are read from the tile in memory (not staged in
+        // registers: S is up to 128 words)
+        const uint32_t *w = fresh_v(r.x32 + (size_t)tile * S * kTile + lane);
         if (h == 0 && r.desc[(size_t)tile * kTile + lane].msg_len) {
             // C must lie in Z_N: compare with N, most significant word first
             const uint32_t *n32 = kr + G.off_n32;
             int cmp = 0;
-#pragma unroll
-            for (int k = S - 1; k >= 0; --k) cmp = cmp ? cmp : (w[k] > n32[k]) - (w[k] < n32[k]);
+#pragma unroll 1
+            for (int k = S - 1; k >= 0 && cmp == 0; --k) {
+                const uint32_t x = w[(size_t)k * kTile], y = n32[k];
+                cmp = (x > y) - (x < y);
+            }
             if (cmp >= 0) atomicOr(r.err, 1u);
         }
 #pragma unroll
-        for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j + NL);
+        for (int j = 0; j < NL; ++j) acc[j] = radix_limb_mem<S, LB>(w, kTile, j + NL);
         store_row4(tbl, 0, lane, acc);  // c_hi, parked in entry 0 until it is used
 #pragma unroll
-        for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j);
+        for (int j = 0; j < NL; ++j) acc[j] = radix_limb_mem<S, LB>(w, kTile, j);
     }
     load_limbs(b, hr + G.h_rr);
 
@@ -477,17 +481,23 @@ template <int CB>
 constexpr int lds_words_enc() {
     return (make_geom(CB).nlf > make_geom(CB).S ? make_geom(CB).nlf : make_geom(CB).S) * (64 / lanes_full(CB));
 }
+// LDS words of the CRT-halves units (one prefetched table entry per wavefront)
 template <int CB>
 constexpr int lds_words_dec() {
-    return (make_geom(CB).nlh > make_geom(CB).S ? make_geom(CB).nlh : make_geom(CB).S) * (64 / lanes_half(CB));
+    return pad4(make_geom(CB).nlh) * kTile;
 }
 
+// Unit u encrypts chunks [part NG, part NG + NG) of tile u / L (part = u % L):
+// a tile of 64 chunks takes L wavefronts of NG = 64 / L groups.
 template <int CB>
-PMK_DEV void encrypt_lanes_unit(const ClassRun r, uint32_t tile, uint32_t *tbl, uint32_t *lds) {
+PMK_DEV void encrypt_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint32_t *lds) {
     constexpr Geom G = make_geom(CB);
     constexpr int L = lanes_full(CB), NLT = G.nlf, K = NLT / L, LB = G.lbf, S = G.S;
     constexpr int NG = 64 / L;  // groups (chunks) per wavefront
+    const uint32_t tile = u / L;
+    const int part = (int)(u % L);
     const int lane = threadIdx.x, pos = lane % L, grp = lane / L;
+    const int c = part * NG + grp;  // chunk within the tile
     uint32_t *col = lds + grp;
     const uint32_t *kr = r.keys + (size_t)uni(r.tile_key[tile]) * G.stride;  // wave-uniform
     uint32_t n[K];
@@ -497,7 +507,7 @@ PMK_DEV void encrypt_lanes_unit(const ClassRun r, uint32_t tile, uint32_t *tbl, 
     const int top = (int)uni(kr[G.off_ebits]) - 1;
 
     uint32_t acc[K];
-    for (int k = pos; k < S; k += L) col[k * NG] = r.x32[((size_t)tile * S + k) * NG + grp];
+    for (int k = pos; k < S; k += L) col[k * NG] = r.x32[((size_t)tile * S + k) * kTile + c];
     limbs_from_words<K, LB>(acc, col, NG, S, pos * K);
     stage_mem<K>(col, NG, pos, kr + G.off_rrf + pos * K, 1);
 
@@ -526,9 +536,9 @@ PMK_DEV void encrypt_lanes_unit(const ClassRun r, uint32_t tile, uint32_t *tbl, 
             phase = 3;
             if (r.fin32) {
                 // final factor v (blinded encryption): this lane's K limbs of v into the column
-                const uint32_t *v = fresh_v(r.fin32 + (size_t)tile * S * NG + grp);
+                const uint32_t *v = fresh_v(r.fin32 + (size_t)tile * S * kTile + c);
 #pragma unroll 1
-                for (int j = 0; j < K; ++j) col[(pos * K + j) * NG] = radix_limb_mem<S, LB>(v, NG, pos * K + j);
+                for (int j = 0; j < K; ++j) col[(pos * K + j) * NG] = radix_limb_mem<S, LB>(v, kTile, pos * K + j);
             } else {
                 stage_one<K>(col, NG, pos);
             }
@@ -542,129 +552,16 @@ PMK_DEV void encrypt_lanes_unit(const ClassRun r, uint32_t tile, uint32_t *tbl, 
         const uint64_t l0 = j < NLT ? col[j * NG] : 0u;
         const uint64_t l1 = j + 1 < NLT ? col[(j + 1) * NG] : 0u;
         const uint64_t l2 = j + 2 < NLT ? col[(j + 2) * NG] : 0u;
-        r.y32[((size_t)tile * S + k) * NG + grp] = (uint32_t)((l0 >> sh) | (l1 << (LB - sh)) | (l2 << (2 * LB - sh)));
+        r.y32[((size_t)tile * S + k) * kTile + c] = (uint32_t)((l0 >> sh) | (l1 << (LB - sh)) | (l2 << (2 * LB - sh)));
     }
-}
-
-// CRT halves with 2 lanes per number: a wavefront holds the 16 chunks of a tile
-// twice, lanes 0-31 modulo p and lanes 32-63 modulo q.
-template <int CB>
-PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t tile, uint32_t *tbl, uint32_t *lds) {
-    constexpr Geom G = make_geom(CB);
-    constexpr int L = lanes_half(CB), NLT = G.nlh, K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
-    constexpr int CPT = chunks_per_tile(CB);
-    constexpr int NG = 64 / L;  // groups per wavefront = 2 * CPT
-    static_assert(NG == 2 * CPT, "one wavefront holds both halves of a tile");
-    const int win = r.win, T = 1 << win;
-    const int NW = (32 * SH + win - 1) / win;
-    const int lane = threadIdx.x, pos = lane % L, grp = lane / L;
-    const int c = grp % CPT, h = grp / CPT;
-    uint32_t *col = lds + grp;
-    const uint32_t *kr = r.keys + (size_t)uni(r.tile_key[tile]) * G.stride;
-    const uint32_t *hr = kr + G.off_half[0] + h * G.h_size;  // p for lanes 0-31, q for 32-63
-    uint32_t n[K];
-    load_limbs(n, fresh_v(hr + G.h_m + pos * K));
-    const uint32_t n0 = hr[G.h_m0];
-    const uint32_t *dexp = hr + (r.exp_sel ? G.h_d2 : G.h_d);
-
-    uint32_t acc[K];
-    for (int k = pos; k < S; k += L) col[k * NG] = r.x32[((size_t)tile * S + k) * CPT + c];
-    if (h == 0 && pos == 0 && r.desc[(size_t)tile * CPT + c].msg_len) {
-        // C must lie in Z_N
-        const uint32_t *n32 = kr + G.off_n32;
-        int cmp = 0;
-        for (int k = S - 1; k >= 0 && cmp == 0; --k) {
-            const uint32_t w = col[k * NG];
-            cmp = (w > n32[k]) - (w < n32[k]);
-        }
-        if (cmp >= 0) atomicOr(r.err, 1u);
-    }
-    limbs_from_words<K, LB>(acc, col, NG, S, NLT + pos * K);  // c_hi
-    store_entry(tbl, 0, lane, acc);
-    limbs_from_words<K, LB>(acc, col, NG, S, pos * K);        // c_lo
-    stage_mem<K>(col, NG, pos, hr + G.h_rr + pos * K, 1);
-
-    // phases as in halves_unit: 0 c_lo R, 1 c_hi R^2 and x~, 2 table,
-    // 3 digits (squarings, then a table product), 4 leave Montgomery form
-    int phase = 0, e = 2, digit = NW - 2, sq = 0;
-    for (;;) {
-        mont_mul_lanes<NLT, LB, L>(acc, acc, col, NG, n, n0, pos);
-        if (phase == 4) break;
-        if (phase == 0) {
-            store_entry(tbl, 1, lane, acc);
-            load_entry(acc, tbl, 0, lane);
-            stage_mem<K>(col, NG, pos, hr + G.h_rrr + pos * K, 1);
-            phase = 1;
-            continue;
-        }
-        if (phase == 1) {
-            // x~ = acc + T[1]: limb-wise, carries across the group's lanes
-            uint32_t lo[K];
-            load_entry(lo, tbl, 1, lane);
-            uint32_t cy = 0;
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const uint32_t v = acc[j] + lo[j] + cy;
-                acc[j] = v & Radix<LB>::MASK;
-                cy = v >> LB;
-            }
-#pragma unroll
-            for (int s = 1; s < L; ++s) {
-                uint32_t cin = grp_prev<L>(cy, pos);
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    const uint32_t v = acc[j] + cin;
-                    acc[j] = v & Radix<LB>::MASK;
-                    cin = v >> LB;
-                }
-                cy = cin;
-            }
-            store_entry(tbl, 1, lane, acc);
-            stage_limbs(col, NG, pos, acc);  // x~ stays staged for the table
-            phase = 2;
-            continue;
-        }
-        if (phase == 2) {
-            store_entry(tbl, e, lane, acc);
-            if (++e < T) continue;
-            const uint32_t dg = digit_of(dexp, SH, NW - 1, win);
-            if (dg)
-                load_entry(acc, tbl, dg, lane);
-            else
-                load_limbs(acc, fresh_v(hr + G.h_one + pos * K));
-            phase = 3;
-        } else if (sq == win + 1) {  // phase 3: a digit's product is done
-            --digit;
-            sq = 0;
-        }
-        // phase 3: next squaring, the digit's product, or the end
-        if (digit < 0) {
-            stage_one<K>(col, NG, pos);
-            phase = 4;
-        } else if (sq < win) {
-            stage_limbs(col, NG, pos, acc);
-            ++sq;
-        } else {
-            const uint32_t dg = digit_of(dexp, SH, digit, win);
-            if (dg)
-                stage_mem<K>(col, NG, pos, fresh(tbl) + (size_t)dg * K * kTile + lane, kTile);
-            else
-                stage_mem<K>(col, NG, pos, hr + G.h_one + pos * K, 1);
-            sq = win + 1;
-        }
-    }
-    canonicalize_lanes<K, LB, L>(acc, n, pos);
-    uint32_t *dst = r.half + ((size_t)(2 * tile + h) * NLT + pos * K) * CPT + c;
-#pragma unroll
-    for (int j = 0; j < K; ++j) dst[(size_t)j * CPT] = acc[j];
 }
 
 // ------------------------------------------------------------------ per-class kernels
 // Persistent grids: block b owns table slot b and walks units b, b + grid, ...
 template <int CB>
-constexpr int kEncWaves = lanes_full(CB) > 1 ? 2 : 2;
+constexpr int kEncWaves = 2;
 template <int CB>
-constexpr int kDecWaves = lanes_half(CB) > 1 ? 2 : 3;
+constexpr int kDecWaves = make_geom(CB).nlh > 40 ? 2 : 3;
 
 template <int CB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kEncWaves<CB>))) void encrypt_kernel(
@@ -672,7 +569,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kEncWaves<CB
     uint32_t *tbl = r.table + (size_t)blockIdx.x * slot_words;
     if constexpr (lanes_full(CB) > 1) {
         __shared__ uint32_t lds[lds_words_enc<CB>()];
-        for (uint32_t u = blockIdx.x; u < r.ntiles; u += gridDim.x) encrypt_lanes_unit<CB>(r, u, tbl, lds);
+        const uint32_t units = r.ntiles * lanes_full(CB);
+        for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) encrypt_lanes_unit<CB>(r, u, tbl, lds);
     } else {
         for (uint32_t u = blockIdx.x; u < r.ntiles; u += gridDim.x) encrypt_unit<CB>(r, u, tbl);
     }
@@ -682,13 +580,8 @@ template <int CB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kDecWaves<CB>))) void halves_kernel(
     ClassRun r, uint64_t slot_words) {
     uint32_t *tbl = r.table + (size_t)blockIdx.x * slot_words;
-    if constexpr (lanes_half(CB) > 1) {
-        __shared__ uint32_t lds[lds_words_dec<CB>()];
-        for (uint32_t u = blockIdx.x; u < r.ntiles; u += gridDim.x) halves_lanes_unit<CB>(r, u, tbl, lds);
-    } else {
-        __shared__ uint32_t lds[pad4(make_geom(CB).nlh) * kTile];  // one prefetched table entry
-        for (uint32_t u = blockIdx.x; u < 2 * r.ntiles; u += gridDim.x) halves_unit<CB>(r, u, tbl, lds);
-    }
+    __shared__ uint32_t lds[lds_words_dec<CB>()];  // one prefetched table entry
+    for (uint32_t u = blockIdx.x; u < 2 * r.ntiles; u += gridDim.x) halves_unit<CB>(r, u, tbl, lds);
 }
 
 // ------------------------------------------------------------------ Garner

@@ -57,11 +57,15 @@ void free_plan_memory(pmk_plan *pl) {
     drop_timings(pl);
     drop_graphs(pl);
     if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
-    if (pl->side_stream) (void)hipStreamDestroy(pl->side_stream);
+    for (int i = 0; i < pmk_plan::kSide; ++i) {
+        if (pl->side_stream[i]) (void)hipStreamDestroy(pl->side_stream[i]);
+        if (pl->join_event[i]) (void)hipEventDestroy(pl->join_event[i]);
+        pl->side_stream[i] = nullptr;
+        pl->join_event[i] = nullptr;
+    }
     if (pl->fork_event) (void)hipEventDestroy(pl->fork_event);
-    if (pl->join_event) (void)hipEventDestroy(pl->join_event);
-    pl->capture_stream = pl->side_stream = nullptr;
-    pl->fork_event = pl->join_event = nullptr;
+    pl->capture_stream = nullptr;
+    pl->fork_event = nullptr;
     for (void *p : pl->allocs) (void)hipFree(p);
     pl->allocs.clear();
 }
@@ -464,11 +468,14 @@ int pmk_plan_kernel_time(pmk_plan *pl, int kind, double *ms_total, uint64_t *lau
 namespace pmk {
 
 // Launches of one pass of the batched path.  Packing runs on `stream`; then
-// the multi-lane classes (4096, 3072 bits) run as one persistent work-queue
-// launch on the plan's side stream while the one-lane classes (2048 bits down)
-// run their own kernels, largest first, on `stream` (forked and joined with
-// events, so the two can share the chip); Garner recombination and unpacking
-// follow on `stream`.
+// the exponentiation kernels of the size classes run side by side on `stream`
+// and the plan's side streams (forked and joined with events), so that
+// classes too small to fill the chip share it:
+//   encryption: the 4096- and 3072-bit classes as one persistent work-queue
+//     launch on a side stream, the one-lane classes on `stream`, largest first;
+//   decryption: each class's CRT-halves kernel, classes ordered by their work
+//     and dealt round-robin over the streams (largest first on each).
+// Garner recombination and unpacking follow on `stream`.
 int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, void *stream) {
     pmk_ctx *ctx = pl->ctx;
     BatchArgs a{};
@@ -478,41 +485,51 @@ int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, v
         a.runs[i] = pl->runs[c];
         a.runs[i].win = ctx->win[c];
         a.start[i] = total;
-        total += pl->runs[c].ntiles ? exp_units(c, decrypt, pl->runs[c].ntiles) : 0u;
+        total += pl->runs[c].ntiles ? exp_units(c, 0, pl->runs[c].ntiles) : 0u;
     }
     a.start[kWideClasses] = total;
     a.counter = pl->d_counter;
     a.table = pl->batch_table;
-    a.slot_words = batch_slot_words(decrypt, pl->batch_win);
-    int e = total ? launch_counter_reset(pl->d_counter, stream) : 0;
-    bool narrow = false;
+    a.slot_words = batch_slot_words();
+    int e = 0;
+    if (!decrypt && total) e = launch_counter_reset(pl->d_counter, stream);
+    // launches of the exponentiation stage: (class, stream index)
+    int order[kNumClasses], nl = 0;
     for (int c = kNumClasses - 1; c >= 0 && !e; --c) {
         ClassRun r = pl->runs[c];
         if (!r.ntiles) continue;
-        narrow = narrow || c < kWideFirst;
         e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(r, in, decrypt, stream); });
+        if (decrypt || c < kWideFirst) order[nl++] = c;
     }
-    const bool fork = !e && total && narrow;
-    if (fork) {
+    if (decrypt) {  // classes by canonical work, largest first
+        auto work = [&](int c) {
+            const double s = kClassBits[c] / 64.0;
+            return (double)pl->runs[c].ntiles * kClassBits[c] * (2 * s * s + s);
+        };
+        std::sort(order, order + nl, [&](int x, int y) { return work(x) > work(y); });
+    }
+    const int lanes = decrypt ? std::min(nl, 1 + pmk_plan::kSide) : (total && nl ? 2 : 1);
+    if (!e && lanes > 1) {
         e = hipEventRecord(pl->fork_event, (hipStream_t)stream);
-        if (!e) e = hipStreamWaitEvent(pl->side_stream, pl->fork_event, 0);
+        for (int i = 0; i < lanes - 1 && !e; ++i) e = hipStreamWaitEvent(pl->side_stream[i], pl->fork_event, 0);
     }
-    if (!e && total) {
-        void *s = fork ? (void *)pl->side_stream : stream;
-        const uint32_t grid = std::min(total, pl->batch_slots[decrypt]);
-        e = timed_launch(pl, PMK_KERNEL_BATCH, s, [&] { return launch_batch(a, decrypt, grid, s); });
+    auto stream_of = [&](int lane) { return lane == 0 ? stream : (void *)pl->side_stream[lane - 1]; };
+    if (!e && !decrypt && total) {
+        void *s = stream_of(lanes - 1);
+        const uint32_t grid = std::min(total, pl->batch_slots);
+        e = timed_launch(pl, PMK_KERNEL_BATCH, s, [&] { return launch_batch(a, grid, s); });
     }
-    for (int c = kWideFirst - 1; c >= 0 && !e; --c) {
-        ClassRun r = pl->runs[c];
-        if (!r.ntiles) continue;
-        r.win = ctx->win[c];
-        e = timed_launch(pl, decrypt ? PMK_KERNEL_CRT_HALVES : PMK_KERNEL_ENCRYPT, stream, [&] {
-            return decrypt ? launch_decrypt_halves(r, stream) : launch_encrypt(r, stream);
+    for (int i = 0; i < nl && !e; ++i) {
+        ClassRun r = pl->runs[order[i]];
+        r.win = ctx->win[order[i]];
+        void *s = decrypt ? stream_of(i % lanes) : stream;
+        e = timed_launch(pl, decrypt ? PMK_KERNEL_CRT_HALVES : PMK_KERNEL_ENCRYPT, s, [&] {
+            return decrypt ? launch_decrypt_halves(r, s) : launch_encrypt(r, s);
         });
     }
-    if (fork && !e) {
-        e = hipEventRecord(pl->join_event, pl->side_stream);
-        if (!e) e = hipStreamWaitEvent((hipStream_t)stream, pl->join_event, 0);
+    for (int i = 0; i < lanes - 1 && !e; ++i) {
+        e = hipEventRecord(pl->join_event[i], pl->side_stream[i]);
+        if (!e) e = hipStreamWaitEvent((hipStream_t)stream, pl->join_event[i], 0);
     }
     for (int c = kNumClasses - 1; c >= 0 && !e; --c) {
         const ClassRun &r = pl->runs[c];
@@ -526,33 +543,30 @@ int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, v
 int batch_prepare(pmk_plan *pl) {
     if (pl->d_counter) return PMK_OK;
     pmk_ctx *ctx = pl->ctx;
-    uint32_t units[2] = {0, 0};
+    uint32_t units = 0;
     for (int i = 0; i < kWideClasses; ++i) {
         const int c = wide_class(i);
-        for (int d = 0; d < 2; ++d) units[d] += pl->runs[c].ntiles ? exp_units(c, d, pl->runs[c].ntiles) : 0u;
+        units += pl->runs[c].ntiles ? exp_units(c, 0, pl->runs[c].ntiles) : 0u;
     }
-    for (int d = 0; d < 2; ++d)
-        pl->batch_slots[d] = std::max<uint32_t>(1, std::min(batch_wave_slots(d, ctx->num_cus), units[d]));
+    pl->batch_slots = std::max<uint32_t>(1, std::min(batch_wave_slots(ctx->num_cus), units));
     uint32_t *counter = nullptr;
     hipError_t e = dev_alloc(pl, &counter, sizeof(uint32_t));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->capture_stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->side_stream, hipStreamNonBlocking);
+    for (int i = 0; i < pmk_plan::kSide && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&pl->side_stream[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->join_event[i], hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->fork_event, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->join_event, hipEventDisableTiming);
     if (e != hipSuccess) return hip_err(ctx, e, "batch scratch allocation");
     pl->d_counter = counter;
     return PMK_OK;
 }
 
-// The wide batch kernel's table, sized for both directions at the current windows.
+// The wide batch kernel's table (encryption keeps two numbers per wave).
 hipError_t ensure_batch_table(pmk_plan *pl) {
-    uint64_t need = 0;
-    for (int i = 0; i < kWideClasses; ++i) pl->batch_win[i] = pl->ctx->win[wide_class(i)];
-    for (int d = 0; d < 2; ++d) {
-        bool any = false;
-        for (int i = 0; i < kWideClasses; ++i) any = any || pl->runs[wide_class(i)].ntiles;
-        if (any) need = std::max<uint64_t>(need, (uint64_t)pl->batch_slots[d] * batch_slot_words(d, pl->batch_win));
-    }
+    bool any = false;
+    for (int i = 0; i < kWideClasses; ++i) any = any || pl->runs[wide_class(i)].ntiles;
+    const uint64_t need = any ? (uint64_t)pl->batch_slots * batch_slot_words() : 0;
     return regrow(pl, &pl->batch_table, pl->batch_cap, need);
 }
 

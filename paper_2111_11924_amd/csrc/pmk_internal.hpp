@@ -25,13 +25,14 @@ PMK_HD constexpr int nl_for(int bits, int lb) { return (bits + 2 + lb - 1) / lb;
 PMK_HD constexpr int lb_full(int bits) { return bits > 3072 ? 27 : 28; }
 PMK_HD constexpr int lb_half(int bits) { return lb_full(bits / 2); }
 
-// Lanes per bignum: one lane holds a whole number up to 2048-bit moduli; the
-// 3072- and 4096-bit classes spread each number over a group of lanes (4 for
-// the full modulus, 2 for a CRT half) so its limbs fit the registers.
+// Lanes per full-size bignum: one lane holds a whole number up to 2048-bit
+// moduli; the 3072- and 4096-bit classes spread each full-size number over a
+// group of 4 lanes so its limbs fit the registers.  CRT halves (at most 2048
+// bits) always fit one lane.
 PMK_HD constexpr int lanes_full(int bits) { return bits >= 3072 ? 4 : 1; }
-PMK_HD constexpr int lanes_half(int bits) { return bits >= 3072 ? 2 : 1; }
-// chunks per tile (one tile = one wavefront of the encryption kernel)
-PMK_HD constexpr int chunks_per_tile(int bits) { return 64 / lanes_full(bits); }
+// chunks per tile: a tile is one wavefront of CRT halves (64 numbers); the
+// encryption of a 3072/4096-bit tile takes lanes_full wavefronts of 64/L chunks
+PMK_HD constexpr int chunks_per_tile(int) { return 64; }
 PMK_HD constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // Default window width of the fixed-window exponentiation of the CRT halves
@@ -65,7 +66,7 @@ PMK_HD constexpr Geom make_geom(int bits) {
     g.lbf = lb_full(bits);
     g.nlf = round_up(nl_for(bits, g.lbf), lanes_full(bits));
     g.lbh = lb_half(bits);
-    g.nlh = round_up(nl_for(bits / 2, g.lbh), lanes_half(bits));
+    g.nlh = nl_for(bits / 2, g.lbh);
     g.ew = 2;
     const int pf = pad4(g.nlf), ph = pad4(g.nlh);
     int o = 0;
@@ -134,9 +135,9 @@ constexpr int kMaxWin = 6;
 // One persistent launch over the exponentiation work of the 1024- to 4096-bit
 // classes of a plan: units (tiles, or job tiles of CRT halves) are numbered
 // class by class, largest modulus first, and handed out by an atomic counter.
-// The multi-lane classes (4096 and 3072 bits) share one persistent kernel
-// whose waves take work units (tiles, or CRT jobs of a tile) from a device
-// counter, 4096-bit units first.
+// The encryption of the 4096- and 3072-bit classes (4 lanes per number) runs
+// as one persistent kernel whose waves take work units from a device counter,
+// 4096-bit units first.
 constexpr int kWideClasses = 2;
 constexpr int kWideFirst = kNumClasses - kWideClasses;  // class index of 3072 bits
 // class of entry i of the wide batch: 4096 bits, then 3072 bits
@@ -164,10 +165,10 @@ uint32_t wave_slots(int cls, int decrypt, int num_cus);
 // work units (wavefronts' worth of bignums) of the exponentiation kernels
 uint32_t exp_units(int cls, int decrypt, uint32_t ntiles);
 // persistent batched exponentiation (kbatch.hip)
-int launch_batch(const BatchArgs &a, int decrypt, uint32_t grid, void *stream);
+int launch_batch(const BatchArgs &a, uint32_t grid, void *stream);
 int launch_counter_reset(uint32_t *counter, void *stream);
-uint32_t batch_wave_slots(int decrypt, int num_cus);
-// table words per wave slot of the wide batch kernel; win[i] is the window of wide_class(i)
-uint64_t batch_slot_words(int decrypt, const int *win);
+uint32_t batch_wave_slots(int num_cus);
+// table words per wave slot of the wide batch kernel
+uint64_t batch_slot_words();
 
 }  // namespace pmk

@@ -66,11 +66,11 @@ struct pmk_plan {
     uint32_t *batch_table = nullptr;   // its window-table slots
     uint64_t batch_cap = 0;            // words allocated at batch_table
     uint64_t table_cap[kNumClasses] = {};  // words allocated at runs[c].table
-    uint32_t batch_slots[2] = {};      // its resident waves, [encrypt, decrypt]
-    int batch_win[kWideClasses] = {};  // windows the wide batch kernel runs at
+    uint32_t batch_slots = 0;          // its resident waves
     CapturedGraph graph[2];                         // [0] encrypt, [1] decrypt
-    hipStream_t capture_stream = nullptr, side_stream = nullptr;
-    hipEvent_t fork_event = nullptr, join_event = nullptr;
+    static constexpr int kSide = 3;  // side streams of the batched sequence
+    hipStream_t capture_stream = nullptr, side_stream[kSide] = {};
+    hipEvent_t fork_event = nullptr, join_event[kSide] = {};
     // blinded PMKRSA: second input tiles and second CRT halves (allocated on first use)
     uint32_t *x32b[kNumClasses] = {};
     uint32_t *half2[kNumClasses] = {};

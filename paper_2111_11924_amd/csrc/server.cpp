@@ -227,7 +227,7 @@ int launch_round(Server *sv, RoundPlan &R, int decrypt, const std::vector<Taken>
                 R.h_desc[c].push_back(i + l < list.size() ? list[i + l] : ChunkDesc{0, 0, slot, 0});
         }
     }
-    uint32_t units[2] = {0, 0};
+    uint32_t units = 0;  // work units of the wide encryption kernel
     for (int c = 0; c < kNumClasses; ++c) {
         ClassRun &r = R.pl.runs[c];
         const uint64_t tiles = R.h_tkey[c].size();
@@ -239,8 +239,7 @@ int launch_round(Server *sv, RoundPlan &R, int decrypt, const std::vector<Taken>
         r.err = R.pl.d_err;
         r.slots_enc = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 0, ctx->num_cus), exp_units(c, 0, r.ntiles)));
         r.slots_dec = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 1, ctx->num_cus), exp_units(c, 1, r.ntiles)));
-        if (c >= kWideFirst)
-            for (int d = 0; d < 2; ++d) units[d] += exp_units(c, d, r.ntiles);
+        if (c >= kWideFirst) units += exp_units(c, 0, r.ntiles);
         e = hipMemcpyAsync(R.desc[c], R.h_desc[c].data(), R.h_desc[c].size() * sizeof(ChunkDesc),
                            hipMemcpyHostToDevice, sv->stream);
         if (e == hipSuccess)
@@ -250,8 +249,7 @@ int launch_round(Server *sv, RoundPlan &R, int decrypt, const std::vector<Taken>
     }
     int rc = batch_prepare(&R.pl);
     if (rc != PMK_OK) return (int)hipErrorOutOfMemory;
-    for (int d = 0; d < 2; ++d)
-        R.pl.batch_slots[d] = std::max<uint32_t>(1, std::min(batch_wave_slots(d, ctx->num_cus), units[d]));
+    R.pl.batch_slots = std::max<uint32_t>(1, std::min(batch_wave_slots(ctx->num_cus), units));
     hipError_t e = ensure_tables(&R.pl);
     if (e == hipSuccess) e = ensure_batch_table(&R.pl);
     if (e != hipSuccess) return (int)e;
