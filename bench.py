@@ -118,7 +118,8 @@ def cpu_baseline(keys, msg, km, sample_chunks: int):
     }
 
 
-def serve_measure(nreq: int, loads, seed: int = 5, staging_mib: int = 2048, round_chunks: int = 0):
+def serve_measure(nreq: int, loads, seed: int = 5, staging_mib: int = 2048, round_chunks: int = 0,
+                  pipeline_depth: int = 0):
     """Serving workload: a 512-key device table (1024..4096-bit keys), requests
     of 1 KiB-10 MiB (log-uniform) over 1-64 keys each, half encryptions and
     half CRT decryptions.  First the closed-loop capacity (all requests queued
@@ -135,7 +136,7 @@ def serve_measure(nreq: int, loads, seed: int = 5, staging_mib: int = 2048, roun
     msgs = [r.message() for r in reqs]
     ctx = binding.Context(0)
     ctx.load_keys(keys)
-    srv = ctx.server(staging_bytes=staging_mib << 20, round_chunks=round_chunks)
+    srv = ctx.server(staging_bytes=staging_mib << 20, round_chunks=round_chunks, pipeline_depth=pipeline_depth)
     try:
         # ciphertexts of the decryption requests, made outside any timing
         pend = [(i, srv.submit(binding.PMK_OP_ENCRYPT, msgs[i], len(msgs[i]), r.key_map))
@@ -205,6 +206,7 @@ def main() -> int:
                     help="requests per serving point (default: 2000 with --serve, 300 for the headline p99)")
     ap.add_argument("--round-chunks", type=int, default=0,
                     help="server: most chunks per batching round (0: the library default)")
+    ap.add_argument("--pipeline-depth", type=int, default=0, help="server: rounds in flight (1 or 2)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -226,8 +228,10 @@ def main() -> int:
     from paper_2111_11924_amd import binding, inputs
 
     if args.serve:
-        res = serve_measure(args.serve_requests or 2000, [0.5, 0.8, 1.2], round_chunks=args.round_chunks)
+        res = serve_measure(args.serve_requests or 2000, [0.5, 0.8, 1.2], round_chunks=args.round_chunks,
+                            pipeline_depth=args.pipeline_depth)
         res["round_chunks"] = args.round_chunks
+        res["pipeline_depth"] = args.pipeline_depth
         res.update({"metric": "p99 request latency, serving workload (512 keys, 1 KiB-10 MiB requests)",
                     "unit": "ms", "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
                     "value": res["points"][1]["p99_ms"], "config": {"workload": "serving-512keys-mixed",

@@ -272,7 +272,7 @@ int pmk_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uint32
  * pmk_server_start: staging_bytes (0: 512 MiB) is the admission budget of
  *   device memory for inputs and outputs in flight; round_chunks (0: two
  *   chip-filling rounds of 2048-bit CRT halves) bounds the chunks of one
- *   round.  The key table and window widths may not change while the server
+ *   round; pipeline_depth as in the struct.  The key table and window widths may not change while the server
  *   runs (PMK_EBUSY).  PMK_EBUSY if a server already runs.
  * pmk_submit (thread-safe): validates like pmk_plan_create (PMK_EKEY,
  *   PMK_ESIZE, PMK_EINVAL; PMK_ESIZE also when out_cap is too small or the
@@ -293,6 +293,8 @@ int pmk_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uint32
 typedef struct {
     uint64_t staging_bytes;
     uint64_t round_chunks;
+    uint32_t pipeline_depth; /* rounds in flight: 0 or 1 = one at a time (lower latency),
+                                2 = the next round is built and queued while one runs */
 } pmk_server_cfg;
 
 enum { PMK_OP_ENCRYPT = 0, PMK_OP_DECRYPT = 1 };

@@ -57,7 +57,7 @@ class pmk_key(C.Structure):
 
 
 class pmk_server_cfg(C.Structure):
-    _fields_ = [("staging_bytes", C.c_uint64), ("round_chunks", C.c_uint64)]
+    _fields_ = [("staging_bytes", C.c_uint64), ("round_chunks", C.c_uint64), ("pipeline_depth", C.c_uint32)]
 
 
 class pmk_request(C.Structure):
@@ -333,8 +333,8 @@ def pmk_decrypt(ctx: int, d_ct, ct_len: int, key_map, d_msg, msg_len: int, strea
                                       _dev_ptr(d_msg), int(msg_len), _stream(stream))
 
 
-def pmk_server_start(ctx: int, staging_bytes: int = 0, round_chunks: int = 0) -> None:
-    cfg = pmk_server_cfg(int(staging_bytes), int(round_chunks))
+def pmk_server_start(ctx: int, staging_bytes: int = 0, round_chunks: int = 0, pipeline_depth: int = 0) -> None:
+    cfg = pmk_server_cfg(int(staging_bytes), int(round_chunks), int(pipeline_depth))
     _check(load_library().pmk_server_start(ctx, C.byref(cfg)), ctx)
 
 
@@ -451,9 +451,9 @@ class Server:
     """The request server of a context (pmk_server_*).  Keeps each request's
     host buffers alive until its ticket is reported done."""
 
-    def __init__(self, ctx: "Context", staging_bytes: int = 0, round_chunks: int = 0):
+    def __init__(self, ctx: "Context", staging_bytes: int = 0, round_chunks: int = 0, pipeline_depth: int = 0):
         self.ctx = ctx
-        pmk_server_start(ctx.handle, staging_bytes, round_chunks)
+        pmk_server_start(ctx.handle, staging_bytes, round_chunks, pipeline_depth)
         self._held = {}
         self.running = True
 
@@ -524,8 +524,8 @@ class Context:
         """Pick each loaded size class's CRT window width by timing (pmk_autotune)."""
         pmk_autotune(self.handle, cache_path, PMK_AUTOTUNE_FORCE if force else 0)
 
-    def server(self, staging_bytes: int = 0, round_chunks: int = 0) -> "Server":
-        return Server(self, staging_bytes, round_chunks)
+    def server(self, staging_bytes: int = 0, round_chunks: int = 0, pipeline_depth: int = 0) -> "Server":
+        return Server(self, staging_bytes, round_chunks, pipeline_depth)
 
     def plan(self, key_map, msg_len: int) -> Plan:
         p = Plan(self, key_map, msg_len)

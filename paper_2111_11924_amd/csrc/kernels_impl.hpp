@@ -329,9 +329,26 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t 
     const uint32_t *one_h = hr + G.h_one;
 
     uint32_t acc[NL], b[NL];
-    {
-        // the ciphertext words are read from the tile in memory (not staged in
-        // registers: S is up to 128 words)
+    if constexpr (S <= 64) {
+        uint32_t w[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) w[k] = r.x32[((size_t)tile * S + k) * kTile + lane];
+        if (h == 0 && r.desc[(size_t)tile * kTile + lane].msg_len) {
+            // C must lie in Z_N: compare with N, most significant word first
+            const uint32_t *n32 = kr + G.off_n32;
+            int cmp = 0;
+#pragma unroll
+            for (int k = S - 1; k >= 0; --k) cmp = cmp ? cmp : (w[k] > n32[k]) - (w[k] < n32[k]);
+            if (cmp >= 0) atomicOr(r.err, 1u);
+        }
+#pragma unroll
+        for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j + NL);
+        store_row4(tbl, 0, lane, acc);  // c_hi, parked in entry 0 until it is used
+#pragma unroll
+        for (int j = 0; j < NL; ++j) acc[j] = radix_limb<S, LB>(w, j);
+    } else {
+        // 3072/4096 bits: the ciphertext words are read from the tile in memory
+        // (staging up to 128 words in registers would spill)
         const uint32_t *w = fresh_v(r.x32 + (size_t)tile * S * kTile + lane);
         if (h == 0 && r.desc[(size_t)tile * kTile + lane].msg_len) {
             // C must lie in Z_N: compare with N, most significant word first

@@ -96,7 +96,8 @@ struct Request {
     uint8_t *out = nullptr;
     uint64_t msg_len = 0, ct_len = 0, in_len = 0, out_len = 0;
     std::vector<Chunk> chunks;
-    uint64_t next = 0;  // chunks handed to rounds
+    uint64_t next = 0;         // chunks handed to rounds
+    uint64_t done_chunks = 0;  // chunks whose rounds have finished
     uint64_t in_off = 0, out_off = 0;
     int state = PMK_REQ_QUEUED, status = PMK_OK;
     uint64_t t_submit = 0, t_admit = 0, t_done = 0;
@@ -119,6 +120,13 @@ struct Taken {
     uint64_t first, count;
 };
 
+// A launched round: its slot (device buffers), chunks per direction, completion event.
+struct Round {
+    int slot;
+    std::vector<Taken> taken[2];
+    uint64_t t0;
+};
+
 }  // namespace
 
 struct Server {
@@ -137,7 +145,11 @@ struct Server {
     uint8_t *d_slab = nullptr;
     Slab slab;
     hipStream_t stream = nullptr, copy_stream = nullptr;
-    RoundPlan rp[2];
+    // two round slots: with pipeline depth 2 the host builds and queues round
+    // k+1 while round k runs
+    RoundPlan rp[2][2];  // [slot][encrypt, decrypt]
+    hipEvent_t round_done[2] = {};
+    std::deque<Round> flight;
     pmk_server_stats stats{};
 };
 
@@ -325,8 +337,10 @@ void pick_round(Server *sv, std::vector<Taken> out[2]) {
     out[1].clear();
     const uint64_t budget = sv->cfg.round_chunks;
     const size_t n = sv->inflight.size();
-    if (!n) return;
-    const uint64_t share = std::max<uint64_t>(64, budget / n);
+    size_t open = 0;  // requests with chunks not yet handed to a round
+    for (const Request *q : sv->inflight) open += q->next < q->chunks.size();
+    if (!open) return;
+    const uint64_t share = std::max<uint64_t>(64, budget / open);
     std::vector<uint64_t> take(n, 0);
     uint64_t used = 0;
     for (size_t i = 0; i < n && used < budget; ++i) {
@@ -351,8 +365,63 @@ void pick_round(Server *sv, std::vector<Taken> out[2]) {
 void fail_all(Server *sv, int status) {
     for (Request *q : sv->inflight) finish(sv, q, status);
     sv->inflight.clear();
+    sv->flight.clear();
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->fatal = status;
+}
+
+// Waits for the oldest launched round and completes what it finished.
+// Returns a hipError_t.
+int complete_round(Server *sv, std::vector<std::vector<uint8_t>> &nbe) {
+    pmk_ctx *ctx = sv->ctx;
+    Round r = std::move(sv->flight.front());
+    sv->flight.pop_front();
+    int e = (int)hipEventSynchronize(sv->round_done[r.slot]);
+    // device range flag of the decryption part
+    uint32_t flag = 0;
+    if (!e && !r.taken[1].empty()) {
+        e = (int)hipMemcpy(&flag, sv->rp[r.slot][1].pl.d_err, sizeof flag, hipMemcpyDeviceToHost);
+        if (!e && flag) e = (int)hipMemset(sv->rp[r.slot][1].pl.d_err, 0, sizeof flag);
+    }
+    if (e) return e;
+    uint64_t chunks = 0;
+    for (int d = 0; d < 2; ++d)
+        for (const Taken &t : r.taken[d]) {
+            chunks += t.count;
+            t.req->done_chunks += t.count;
+        }
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stats.rounds++;
+        sv->stats.chunks += chunks;
+        sv->stats.busy_ns += now_ns() - r.t0;
+    }
+    if (flag) {
+        for (const Taken &t : r.taken[1]) {
+            for (const Chunk &ch : t.req->chunks)
+                if (nbe[ch.key].empty()) {
+                    const std::vector<uint32_t> &n = ctx->keys[ch.key].n;
+                    for (size_t w = n.size(); w-- > 0;)
+                        for (int b = 3; b >= 0; --b) nbe[ch.key].push_back((uint8_t)(n[w] >> (8 * b)));
+                }
+            if (!blocks_below_moduli(ctx, t.req, nbe)) t.req->status = PMK_ERANGE;
+        }
+    }
+    // completed requests: results to the host, staging released
+    std::vector<Request *> still;
+    for (Request *q : sv->inflight) {
+        if (q->done_chunks < q->chunks.size()) {
+            still.push_back(q);
+            continue;
+        }
+        hipError_t ce = hipSuccess;
+        if (q->out_len) ce = hipMemcpy(q->out, sv->d_slab + q->out_off, q->out_len, hipMemcpyDeviceToHost);
+        sv->slab.release(q->in_off, std::max<uint64_t>(q->in_len, 4));
+        sv->slab.release(q->out_off, std::max<uint64_t>(q->out_len, 4));
+        finish(sv, q, ce != hipSuccess ? PMK_EDEVICE : q->status);
+    }
+    sv->inflight.swap(still);
+    return 0;
 }
 
 void run(Server *sv) {
@@ -364,17 +433,40 @@ void run(Server *sv) {
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            sv->cv_work.wait(lk, [&] { return sv->stopping || !sv->queue.empty() || !sv->inflight.empty(); });
-            if (sv->stopping && sv->queue.empty() && sv->inflight.empty()) break;
+            sv->cv_work.wait(lk, [&] {
+                return sv->stopping || !sv->queue.empty() || !sv->inflight.empty() || !sv->flight.empty();
+            });
+            if (sv->stopping && sv->queue.empty() && sv->inflight.empty() && sv->flight.empty()) break;
         }
         admit(sv);
-        pick_round(sv, round);
-        if (round[0].empty() && round[1].empty()) {
-            // nothing admitted fits yet and nothing runs: wait for more room or work
+        bool launched = false;
+        const size_t depth = sv->cfg.pipeline_depth >= 2 ? 2 : 1;
+        if (sv->flight.size() < depth) {
+            pick_round(sv, round);
+            if (!round[0].empty() || !round[1].empty()) {
+                const int slot = sv->flight.empty() ? 0 : 1 - sv->flight.front().slot;
+                Round r{slot, {}, now_ns()};
+                int e = 0;
+                for (int d = 0; d < 2 && !e; ++d)
+                    if (!round[d].empty()) e = launch_round(sv, sv->rp[slot][d], d, round[d]);
+                if (!e) e = (int)hipEventRecord(sv->round_done[slot], sv->stream);
+                if (e) {
+                    fail_all(sv, PMK_EDEVICE);
+                    continue;
+                }
+                r.taken[0].swap(round[0]);
+                r.taken[1].swap(round[1]);
+                sv->flight.push_back(std::move(r));
+                launched = true;
+            }
+        }
+        if (sv->flight.empty()) {
+            // nothing runs and nothing can be picked: a queued request larger
+            // than the whole free slab can never be admitted
             if (sv->inflight.empty()) {
                 std::unique_lock<std::mutex> lk(sv->mu);
                 if (!sv->queue.empty()) {
-                    Request *q = sv->queue.front();  // larger than the free slab: can never fit
+                    Request *q = sv->queue.front();
                     sv->queue.pop_front();
                     lk.unlock();
                     finish(sv, q, PMK_ESIZE);
@@ -382,65 +474,16 @@ void run(Server *sv) {
             }
             continue;
         }
-        const uint64_t t0 = now_ns();
-        int e = 0;
-        for (int d = 0; d < 2 && !e; ++d)
-            if (!round[d].empty()) e = launch_round(sv, sv->rp[d], d, round[d]);
-        admit(sv);  // overlaps the round's kernels
-        if (!e) e = (int)hipStreamSynchronize(sv->stream);
-        if (e) {
-            fail_all(sv, PMK_EDEVICE);
-            continue;
-        }
-        // device range flag of the decryption round
-        uint32_t flag = 0;
-        if (!round[1].empty()) {
-            e = (int)hipMemcpy(&flag, sv->rp[1].pl.d_err, sizeof flag, hipMemcpyDeviceToHost);
-            if (!e && flag) e = (int)hipMemset(sv->rp[1].pl.d_err, 0, sizeof flag);
-            if (e) {
-                fail_all(sv, PMK_EDEVICE);
-                continue;
-            }
-        }
-        uint64_t chunks = 0;
-        for (int d = 0; d < 2; ++d)
-            for (const Taken &t : round[d]) chunks += t.count;
-        {
-            std::lock_guard<std::mutex> lk(sv->mu);
-            sv->stats.rounds++;
-            sv->stats.chunks += chunks;
-            sv->stats.busy_ns += now_ns() - t0;
-        }
-        if (flag) {
-            for (const Taken &t : round[1]) {
-                for (const Chunk &ch : t.req->chunks)
-                    if (nbe[ch.key].empty()) {
-                        const std::vector<uint32_t> &n = ctx->keys[ch.key].n;
-                        for (size_t w = n.size(); w-- > 0;)
-                            for (int b = 3; b >= 0; --b) nbe[ch.key].push_back((uint8_t)(n[w] >> (8 * b)));
-                    }
-                if (!blocks_below_moduli(ctx, t.req, nbe)) t.req->status = PMK_ERANGE;
-            }
-        }
-        // completed requests: results to the host, staging released
-        std::vector<Request *> still;
-        for (Request *q : sv->inflight) {
-            if (q->next < q->chunks.size()) {
-                still.push_back(q);
-                continue;
-            }
-            hipError_t ce = hipSuccess;
-            if (q->out_len) ce = hipMemcpy(q->out, sv->d_slab + q->out_off, q->out_len, hipMemcpyDeviceToHost);
-            sv->slab.release(q->in_off, std::max<uint64_t>(q->in_len, 4));
-            sv->slab.release(q->out_off, std::max<uint64_t>(q->out_len, 4));
-            finish(sv, q, ce != hipSuccess ? PMK_EDEVICE : q->status);
-        }
-        sv->inflight.swap(still);
+        if (launched && sv->flight.size() < depth) continue;  // queue a second round first if there is work
+        if (complete_round(sv, nbe)) fail_all(sv, PMK_EDEVICE);
     }
 }
 
 void free_server(Server *sv) {
-    for (auto &R : sv->rp) free_plan_memory(&R.pl);
+    for (auto &slot : sv->rp)
+        for (auto &R : slot) free_plan_memory(&R.pl);
+    for (auto &ev : sv->round_done)
+        if (ev) (void)hipEventDestroy(ev);
     if (sv->d_slab) (void)hipFree(sv->d_slab);
     if (sv->stream) (void)hipStreamDestroy(sv->stream);
     if (sv->copy_stream) (void)hipStreamDestroy(sv->copy_stream);
@@ -487,8 +530,10 @@ int pmk_server_start(pmk_ctx *ctx, const pmk_server_cfg *cfg) {
     hipError_t e = hipMalloc(&sv->d_slab, sv->cfg.staging_bytes);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->copy_stream, hipStreamNonBlocking);
-    for (int d = 0; d < 2 && e == hipSuccess; ++d) {
-        pmk_plan &pl = sv->rp[d].pl;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&sv->round_done[i], hipEventDisableTiming);
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+        pmk_plan &pl = sv->rp[k / 2][k % 2].pl;
         pl.ctx = ctx;
         for (int c = 0; c < kNumClasses; ++c) {
             pl.runs[c].cls = c;

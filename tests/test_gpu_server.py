@@ -53,7 +53,8 @@ def make_requests(n, seed, max_len=40_000):
     return reqs
 
 
-def test_served_results_alone_and_in_the_mix(ctx, table):
+@pytest.mark.parametrize("depth", [1, 2])
+def test_served_results_alone_and_in_the_mix(ctx, table, depth):
     reqs = make_requests(24, 851)
     # decryption inputs: the oracle's ciphertext of the request's message
     inputs_ = []
@@ -61,7 +62,7 @@ def test_served_results_alone_and_in_the_mix(ctx, table):
         ct = oracle.encrypt(table, msg, km)
         inputs_.append(ct if op == binding.PMK_OP_DECRYPT else msg)
     print(f"[gpu] server: {len(reqs)} requests", flush=True)
-    srv = ctx.server(staging_bytes=8 << 20, round_chunks=2048)
+    srv = ctx.server(staging_bytes=8 << 20, round_chunks=2048, pipeline_depth=depth)
     try:
         # the first request alone
         op, msg, km = reqs[0]
