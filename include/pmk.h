@@ -56,7 +56,7 @@ typedef struct pmk_plan pmk_plan;
  * One key pair (Sec. 1.1 step 1; Algorithm 1, Initialization: N = p q, public
  * exponent e, private exponent split for CRT decryption into
  * dp = d mod (p-1), dq = d mod (q-1) and qinv = q^-1 mod p, Sec. 2.1).
- *   bits    modulus length: a multiple of 64, 128..4096; N must have exactly
+ *   bits    modulus length: a multiple of 64, 128..8192; N must have exactly
  *           this many bits.
  *   n       bits/32 limbs.
  *   n0inv   -N^-1 mod 2^32 (Montgomery constant of Algorithm 3 for r = 2^32).

@@ -21,6 +21,8 @@ PMK_DECLARE(1024)
 PMK_DECLARE(2048)
 PMK_DECLARE(3072)
 PMK_DECLARE(4096)
+PMK_DECLARE(6144)
+PMK_DECLARE(8192)
 
 #define PMK_DISPATCH(cls, FN, ...)                          \
     switch (cls) {                                          \
@@ -31,6 +33,8 @@ PMK_DECLARE(4096)
         case 4: return FN##_2048(__VA_ARGS__);              \
         case 5: return FN##_3072(__VA_ARGS__);              \
         case 6: return FN##_4096(__VA_ARGS__);              \
+        case 7: return FN##_6144(__VA_ARGS__);              \
+        case 8: return FN##_8192(__VA_ARGS__);              \
         default: return (int)hipErrorInvalidValue;          \
     }
 
@@ -68,13 +72,16 @@ uint64_t table_words_per_slot(int cls, int decrypt, int win) {
         case 4: return slot_words_2048(decrypt, win);
         case 5: return slot_words_3072(decrypt, win);
         case 6: return slot_words_4096(decrypt, win);
+        case 7: return slot_words_6144(decrypt, win);
+        case 8: return slot_words_8192(decrypt, win);
         default: return 0;
     }
 }
 
 uint32_t exp_units(int cls, int decrypt, uint32_t ntiles) {
-    // encryption: one wavefront per 64 / lanes_full chunks; CRT halves: one per tile and prime
-    return decrypt ? 2 * ntiles : ntiles * (uint32_t)lanes_full(kClassBits[cls]);
+    // one wavefront per 64 / L chunks: encryption per tile, CRT halves per tile and prime
+    const int bits = kClassBits[cls];
+    return decrypt ? 2 * ntiles * (uint32_t)lanes_half(bits) : ntiles * (uint32_t)lanes_full(bits);
 }
 
 uint32_t wave_slots(int cls, int decrypt, int num_cus) {
@@ -86,6 +93,8 @@ uint32_t wave_slots(int cls, int decrypt, int num_cus) {
         case 4: return wave_slots_2048(decrypt, num_cus);
         case 5: return wave_slots_3072(decrypt, num_cus);
         case 6: return wave_slots_4096(decrypt, num_cus);
+        case 7: return wave_slots_6144(decrypt, num_cus);
+        case 8: return wave_slots_8192(decrypt, num_cus);
         default: return 1;
     }
 }

@@ -498,10 +498,13 @@ template <int CB>
 constexpr int lds_words_enc() {
     return (make_geom(CB).nlf > make_geom(CB).S ? make_geom(CB).nlf : make_geom(CB).S) * (64 / lanes_full(CB));
 }
-// LDS words of the CRT-halves units (one prefetched table entry per wavefront)
+// LDS words of the CRT-halves units: one-lane classes hold one prefetched
+// table entry per wavefront; lane-group classes one multiplier column per group
 template <int CB>
 constexpr int lds_words_dec() {
-    return pad4(make_geom(CB).nlh) * kTile;
+    return lanes_half(CB) == 1
+               ? pad4(make_geom(CB).nlh) * kTile
+               : (make_geom(CB).nlh > make_geom(CB).S ? make_geom(CB).nlh : make_geom(CB).S) * (64 / lanes_half(CB));
 }
 
 // Unit u encrypts chunks [part NG, part NG + NG) of tile u / L (part = u % L):
@@ -573,12 +576,127 @@ PMK_DEV void encrypt_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uin
     }
 }
 
+// CRT halves with L = 4 lanes per number (6144/8192-bit keys): unit u works on
+// chunks [part 16, part 16 + 16) of tile t modulo p (h = 0) or q (h = 1), with
+// u = (2 t + h) L + part.  The exponent is wave-uniform; the window table holds
+// each lane's K limbs per entry ([entry][limb][lane]).
+template <int CB>
+PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint32_t *lds) {
+    constexpr Geom G = make_geom(CB);
+    constexpr int L = lanes_half(CB), NLT = G.nlh, K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
+    constexpr int NG = 64 / L;  // groups (chunks) per wavefront
+    const int win = r.win, T = 1 << win;
+    const int NW = (32 * SH + win - 1) / win;
+    const uint32_t jt = u / L, tile = jt >> 1;
+    const int h = (int)(jt & 1), part = (int)(u % L);
+    const int lane = threadIdx.x, pos = lane % L, grp = lane / L;
+    const int c = part * NG + grp;  // chunk within the tile
+    uint32_t *col = lds + grp;
+    const uint32_t *kr = r.keys + (size_t)uni(r.tile_key[tile]) * G.stride;
+    const uint32_t *hr = kr + G.off_half[0] + h * G.h_size;
+    uint32_t n[K];
+    load_limbs(n, fresh_v(hr + G.h_m + pos * K));
+    const uint32_t n0 = uni(hr[G.h_m0]);
+    const uint32_t *dexp = hr + (r.exp_sel ? G.h_d2 : G.h_d);
+
+    uint32_t acc[K];
+    for (int k = pos; k < S; k += L) col[k * NG] = r.x32[((size_t)tile * S + k) * kTile + c];
+    if (h == 0 && pos == 0 && r.desc[(size_t)tile * kTile + c].msg_len) {
+        // C must lie in Z_N
+        const uint32_t *n32 = kr + G.off_n32;
+        int cmp = 0;
+        for (int k = S - 1; k >= 0 && cmp == 0; --k) {
+            const uint32_t w = col[k * NG];
+            cmp = (w > n32[k]) - (w < n32[k]);
+        }
+        if (cmp >= 0) atomicOr(r.err, 1u);
+    }
+    limbs_from_words<K, LB>(acc, col, NG, S, NLT + pos * K);  // c_hi
+    store_entry(tbl, 0, lane, acc);
+    limbs_from_words<K, LB>(acc, col, NG, S, pos * K);        // c_lo
+    stage_mem<K>(col, NG, pos, hr + G.h_rr + pos * K, 1);
+
+    // phases as in halves_unit: 0 c_lo R, 1 c_hi R^2 and x~, 2 table,
+    // 3 digits (squarings, then a table product), 4 leave Montgomery form
+    int phase = 0, e = 2, digit = NW - 2, sq = 0;
+    for (;;) {
+        mont_mul_lanes<NLT, LB, L>(acc, acc, col, NG, n, n0, pos);
+        if (phase == 4) break;
+        if (phase == 0) {
+            store_entry(tbl, 1, lane, acc);
+            load_entry(acc, tbl, 0, lane);
+            stage_mem<K>(col, NG, pos, hr + G.h_rrr + pos * K, 1);
+            phase = 1;
+            continue;
+        }
+        if (phase == 1) {
+            // x~ = acc + T[1]: limb-wise, carries across the group's lanes
+            uint32_t lo[K];
+            load_entry(lo, tbl, 1, lane);
+            uint32_t cy = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const uint32_t v = acc[j] + lo[j] + cy;
+                acc[j] = v & Radix<LB>::MASK;
+                cy = v >> LB;
+            }
+#pragma unroll
+            for (int s = 1; s < L; ++s) {
+                uint32_t cin = grp_prev<L>(cy, pos);
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const uint32_t v = acc[j] + cin;
+                    acc[j] = v & Radix<LB>::MASK;
+                    cin = v >> LB;
+                }
+                cy = cin;
+            }
+            store_entry(tbl, 1, lane, acc);
+            stage_limbs(col, NG, pos, acc);  // x~ stays staged for the table
+            phase = 2;
+            continue;
+        }
+        if (phase == 2) {
+            store_entry(tbl, e, lane, acc);
+            if (++e < T) continue;
+            const uint32_t dg = digit_of(dexp, SH, NW - 1, win);
+            if (dg)
+                load_entry(acc, tbl, dg, lane);
+            else
+                load_limbs(acc, fresh_v(hr + G.h_one + pos * K));
+            phase = 3;
+        } else if (sq == win + 1) {  // phase 3: a digit's product is done
+            --digit;
+            sq = 0;
+        }
+        // phase 3: next squaring, the digit's product, or the end
+        if (digit < 0) {
+            stage_one<K>(col, NG, pos);
+            phase = 4;
+        } else if (sq < win) {
+            stage_limbs(col, NG, pos, acc);
+            ++sq;
+        } else {
+            const uint32_t dg = digit_of(dexp, SH, digit, win);
+            if (dg)
+                stage_mem<K>(col, NG, pos, fresh(tbl) + (size_t)dg * K * kTile + lane, kTile);
+            else
+                stage_mem<K>(col, NG, pos, hr + G.h_one + pos * K, 1);
+            sq = win + 1;
+        }
+    }
+    canonicalize_lanes<K, LB, L>(acc, n, pos);
+    uint32_t *dst = r.half + ((size_t)(2 * tile + h) * NLT + pos * K) * kTile + c;
+#pragma unroll
+    for (int j = 0; j < K; ++j) dst[(size_t)j * kTile] = acc[j];
+}
+
 // ------------------------------------------------------------------ per-class kernels
 // Persistent grids: block b owns table slot b and walks units b, b + grid, ...
 template <int CB>
 constexpr int kEncWaves = 2;
 template <int CB>
-constexpr int kDecWaves = make_geom(CB).nlh > 40 ? 2 : 3;
+constexpr int kDecWaves = (make_geom(CB).nlh > 40 || lanes_half(CB) > 1) ? 2 : 3;
 
 template <int CB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kEncWaves<CB>))) void encrypt_kernel(
@@ -597,8 +715,14 @@ template <int CB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kDecWaves<CB>))) void halves_kernel(
     ClassRun r, uint64_t slot_words) {
     uint32_t *tbl = r.table + (size_t)blockIdx.x * slot_words;
-    __shared__ uint32_t lds[lds_words_dec<CB>()];  // one prefetched table entry
-    for (uint32_t u = blockIdx.x; u < 2 * r.ntiles; u += gridDim.x) halves_unit<CB>(r, u, tbl, lds);
+    __shared__ uint32_t lds[lds_words_dec<CB>()];
+    const uint32_t units = 2 * r.ntiles * lanes_half(CB);
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        if constexpr (lanes_half(CB) > 1)
+            halves_lanes_unit<CB>(r, u, tbl, lds);
+        else
+            halves_unit<CB>(r, u, tbl, lds);
+    }
 }
 
 // ------------------------------------------------------------------ Garner
@@ -655,6 +779,148 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(make_geom(CB
     if (slot0 < nslots) {
 #pragma unroll
         for (int k = 0; k < S; ++k) y32[((size_t)tile * S + k) * CPT + c] = radix_word<2 * NL, LB>(m, k);
+    }
+}
+
+// The CRT recombination of the 6144/8192-bit classes (CRT halves of 112/152
+// limbs, kept per lane): the same steps with rolled loops over arrays the
+// compiler places in scratch memory -- the halves are spread over lane groups
+// for the exponentiation, but this once-per-chunk step does not need it.
+template <int NL, int LB>
+PMK_DEV void mont_mul_rolled(uint32_t *r, const uint32_t *a, const uint32_t *b, const uint32_t *n, uint32_t n0) {
+    constexpr uint32_t MASK = Radix<LB>::MASK;
+    static_assert((2.0 * NL + 1) * (double)(1ull << LB) * (double)(1ull << LB) < 18446744073709551615.0,
+                  "column sums may overflow 64 bits");
+    uint64_t t[NL];
+#pragma unroll 1
+    for (int j = 0; j < NL; ++j) t[j] = 0;
+#pragma unroll 1
+    for (int i = 0; i < NL; ++i) {  // operand scanning: t = (t + a b_i + m_i n) / 2^LB
+        const uint64_t bi = b[i];
+#pragma unroll 1
+        for (int j = 0; j < NL; ++j) t[j] += (uint64_t)a[j] * bi;
+        const uint64_t m = ((uint32_t)t[0] * n0) & MASK;
+#pragma unroll 1
+        for (int j = 0; j < NL; ++j) t[j] += m * n[j];
+        const uint64_t c = t[0] >> LB;
+#pragma unroll 1
+        for (int j = 0; j + 1 < NL; ++j) t[j] = t[j + 1];
+        t[NL - 1] = 0;
+        t[0] += c;
+    }
+    uint64_t c = 0;
+#pragma unroll 1
+    for (int j = 0; j < NL; ++j) {
+        const uint64_t v = t[j] + c;
+        r[j] = (uint32_t)v & MASK;
+        c = v >> LB;
+    }
+}
+// x < 2m -> x mod m (rolled)
+template <int NL, int LB>
+PMK_DEV void canonicalize_rolled(uint32_t *x, const uint32_t *n) {
+    constexpr uint32_t MASK = Radix<LB>::MASK;
+    uint32_t d[NL];
+    int32_t borrow = 0;
+#pragma unroll 1
+    for (int j = 0; j < NL; ++j) {
+        const int32_t v = (int32_t)x[j] - (int32_t)n[j] - borrow;
+        d[j] = (uint32_t)v & MASK;
+        borrow = v < 0 ? 1 : 0;
+    }
+    if (!borrow) {
+#pragma unroll 1
+        for (int j = 0; j < NL; ++j) x[j] = d[j];
+    }
+}
+
+template <int CB>
+__global__ __launch_bounds__(64) void garner_rolled_kernel(const uint32_t *__restrict__ keys,
+                                                           const ChunkDesc *__restrict__ desc, uint32_t nslots,
+                                                           const uint32_t *__restrict__ half,
+                                                           uint32_t *__restrict__ y32) {
+    constexpr Geom G = make_geom(CB);
+    constexpr int NL = G.nlh, LB = G.lbh, S = G.S, CPT = chunks_per_tile(CB);
+    constexpr uint32_t MASK = Radix<LB>::MASK;
+    const uint32_t slot0 = blockIdx.x * 64 + threadIdx.x;
+    const uint32_t slot = slot0 < nslots ? slot0 : nslots - 1;
+    const uint32_t tile = slot / CPT, c = slot % CPT;
+    const uint32_t *kr = keys + (size_t)desc[slot].key * G.stride;
+    const uint32_t *hp = kr + G.off_half[0];
+    const uint32_t *hq = kr + G.off_half[1];
+    const uint32_t *mp_src = half + ((size_t)(2 * tile) * NL) * CPT + c;
+    const uint32_t *mq_src = half + ((size_t)(2 * tile + 1) * NL) * CPT + c;
+    uint32_t a[NL], q[NL];
+    {
+        // a = m_p + p - m_q, in (0, 2p)
+        int32_t cy = 0;
+#pragma unroll 1
+        for (int j = 0; j < NL; ++j) {
+            const int32_t v = (int32_t)mp_src[(size_t)j * CPT] + (int32_t)hp[G.h_m + j] -
+                              (int32_t)mq_src[(size_t)j * CPT] + cy;
+            a[j] = (uint32_t)v & MASK;
+            cy = v >> LB;
+        }
+    }
+    mont_mul_rolled<NL, LB>(a, a, kr + G.off_qinvr, hp + G.h_m, hp[G.h_m0]);
+    canonicalize_rolled<NL, LB>(a, hp + G.h_m);  // h
+#pragma unroll 1
+    for (int j = 0; j < NL; ++j) q[j] = hq[G.h_m + j];
+    // m = m_q + h q, column by column, written out word by word as columns complete
+    uint64_t cy = 0, wacc = 0;
+    int wbits = 0, k32 = 0;
+#pragma unroll 1
+    for (int k = 0; k < 2 * NL && k32 < S; ++k) {
+        uint64_t acc = cy + (k < NL ? mq_src[(size_t)k * CPT] : 0u);
+        const int lo = k - NL + 1 > 0 ? k - NL + 1 : 0, hi = k < NL ? k : NL - 1;
+#pragma unroll 1
+        for (int i = lo; i <= hi; ++i) acc += (uint64_t)a[i] * q[k - i];
+        wacc |= (uint64_t)((uint32_t)acc & MASK) << wbits;
+        wbits += LB;
+        cy = acc >> LB;
+        while (wbits >= 32 && k32 < S) {
+            if (slot0 < nslots) y32[((size_t)tile * S + k32) * CPT + c] = (uint32_t)wacc;
+            wacc >>= 32;
+            wbits -= 32;
+            ++k32;
+        }
+    }
+    for (; k32 < S; ++k32) {  // (not reached: 2 NL LB >= 32 S)
+        if (slot0 < nslots) y32[((size_t)tile * S + k32) * CPT + c] = (uint32_t)wacc;
+        wacc >>= 32;
+    }
+}
+
+// blinded decryption, rolled form of blind_combine_kernel (6144/8192-bit classes)
+template <int CB>
+__global__ __launch_bounds__(64) void blind_combine_rolled_kernel(const uint32_t *__restrict__ keys,
+                                                                  const ChunkDesc *__restrict__ desc,
+                                                                  uint32_t nslots, uint32_t *__restrict__ half,
+                                                                  const uint32_t *__restrict__ half2,
+                                                                  uint32_t *err) {
+    constexpr Geom G = make_geom(CB);
+    constexpr int NL = G.nlh, LB = G.lbh, CPT = chunks_per_tile(CB);
+    const uint32_t slot0 = blockIdx.x * 64 + threadIdx.x;
+    const uint32_t slot = slot0 < nslots ? slot0 : nslots - 1;
+    const int h = blockIdx.y;
+    const uint32_t tile = slot / CPT, c = slot % CPT;
+    const uint32_t *hr = keys + (size_t)desc[slot].key * G.stride + G.off_half[h];
+    const size_t base = ((size_t)(2 * tile + h) * NL) * CPT + c;
+    uint32_t x[NL], y[NL];
+    uint32_t any = 0;
+#pragma unroll 1
+    for (int j = 0; j < NL; ++j) {
+        x[j] = half[base + (size_t)j * CPT];
+        y[j] = half2[base + (size_t)j * CPT];
+        any |= y[j];
+    }
+    mont_mul_rolled<NL, LB>(x, x, y, hr + G.h_m, hr[G.h_m0]);
+    mont_mul_rolled<NL, LB>(x, x, hr + G.h_rr, hr + G.h_m, hr[G.h_m0]);
+    canonicalize_rolled<NL, LB>(x, hr + G.h_m);
+    if (slot0 < nslots && desc[slot].msg_len) {
+        if (!any) atomicOr(err, 2u);
+#pragma unroll 1
+        for (int j = 0; j < NL; ++j) half[base + (size_t)j * CPT] = x[j];
     }
 }
 

@@ -135,7 +135,7 @@ int class_for_bits(uint32_t bits) {
 }
 
 bool check_key(const pmk_key &k, std::string *msg) {
-    if (k.bits < 128 || k.bits > 4096 || k.bits % 64) return fail(msg, "bits must be a multiple of 64 in 128..4096");
+    if (k.bits < 128 || k.bits > 8192 || k.bits % 64) return fail(msg, "bits must be a multiple of 64 in 128..8192");
     if (!k.n || !k.rr || !k.e || !k.p || !k.q || !k.dp || !k.dq || !k.qinv) return fail(msg, "null key field");
     const int S = k.bits / 32, SH = k.bits / 64;
     const Words n = from(k.n, S, S);

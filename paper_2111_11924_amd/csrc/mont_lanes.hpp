@@ -1,16 +1,16 @@
 // Montgomery multiplication with one bignum spread over a group of L adjacent
-// lanes (L = 2 or 4), for the moduli whose limbs do not fit one lane's
-// registers (3072- and 4096-bit keys).
+// lanes (L = 2, 4 or 8), for the numbers whose limbs do not fit one lane's
+// registers (full-size 3072- to 8192-bit moduli, 3072/4096-bit CRT halves).
 //
 // Same arithmetic as mont.hpp (Sec. 3.2, Algorithm 3; LB-bit limbs, 64-bit
 // column accumulators, no carry handling inside the loop), in operand-scanning
 // order (CIOS): lane `pos` of a group owns limbs [pos K, pos K + K) of a, n and
 // of the running accumulator t.  Step i adds a b_i (b_i read from LDS, one
 // address per group: a broadcast), forms the reduction digit m_i from the
-// group's lowest accumulator limb (broadcast from lane 0 by a DPP quad
-// permutation), adds m_i n, and divides t by 2^LB: every lane hands its lowest
-// limb to the lane below (DPP), lane 0 folds the carry of its lowest limb into
-// the next one.  Carries between lanes are settled once, after the last step.
+// group's lowest accumulator limb (broadcast from lane 0 by DPP: a quad
+// permutation, plus a row shift for groups of 8), adds m_i n, and divides t by
+// 2^LB: every lane hands its lowest limb to the lane below (DPP), lane 0 folds
+// the carry of its lowest limb into the next one.  Carries between lanes are settled once, after the last step.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -27,27 +27,50 @@ __device__ __forceinline__ uint32_t dpp(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, 0xF, 0xF, false);
 }
 
+// DPP row shifts (within 16-lane rows): lane i receives lane i + n (shl) or
+// lane i - n (shr); lanes whose source lies outside the row receive 0.
+template <int N>
+__device__ __forceinline__ uint32_t row_shl(uint32_t v) { return dpp<0x100 + N>(v); }
+template <int N>
+__device__ __forceinline__ uint32_t row_shr(uint32_t v) { return dpp<0x110 + N>(v); }
+
+// Groups of L = 2, 4 or 8 adjacent lanes (aligned, so a group never crosses a
+// 16-lane row).  pos = lane % L.
 // value held by lane 0 of the group
 template <int L>
-__device__ __forceinline__ uint32_t grp_first(uint32_t v) {
-    static_assert(L == 2 || L == 4, "groups of 2 or 4 lanes");
-    return L == 2 ? dpp<qperm(0, 0, 2, 2)>(v) : dpp<qperm(0, 0, 0, 0)>(v);
+__device__ __forceinline__ uint32_t grp_first(uint32_t v, int pos) {
+    static_assert(L == 2 || L == 4 || L == 8, "groups of 2, 4 or 8 lanes");
+    if constexpr (L == 2) return dpp<qperm(0, 0, 2, 2)>(v);
+    if constexpr (L == 4) return dpp<qperm(0, 0, 0, 0)>(v);
+    const uint32_t q = dpp<qperm(0, 0, 0, 0)>(v);  // lane 0 of each quad
+    const uint32_t u = row_shr<4>(q);              // upper quad: the lower quad's lane 0
+    return pos < 4 ? q : u;
 }
 // value held by the group's last lane
 template <int L>
-__device__ __forceinline__ uint32_t grp_last(uint32_t v) {
-    return L == 2 ? dpp<qperm(1, 1, 3, 3)>(v) : dpp<qperm(3, 3, 3, 3)>(v);
+__device__ __forceinline__ uint32_t grp_last(uint32_t v, int pos) {
+    if constexpr (L == 2) return dpp<qperm(1, 1, 3, 3)>(v);
+    if constexpr (L == 4) return dpp<qperm(3, 3, 3, 3)>(v);
+    const uint32_t q = dpp<qperm(3, 3, 3, 3)>(v);  // lane 3 of each quad
+    const uint32_t l = row_shl<4>(q);              // lower quad: the upper quad's lane 3
+    return pos < 4 ? l : q;
 }
 // value of the next lane of the group (the last lane gets 0)
 template <int L>
 __device__ __forceinline__ uint32_t grp_next(uint32_t v, int pos) {
-    const uint32_t x = L == 2 ? dpp<qperm(1, 1, 3, 3)>(v) : dpp<qperm(1, 2, 3, 3)>(v);
+    uint32_t x;
+    if constexpr (L == 2) x = dpp<qperm(1, 1, 3, 3)>(v);
+    else if constexpr (L == 4) x = dpp<qperm(1, 2, 3, 3)>(v);
+    else x = row_shl<1>(v);
     return pos == L - 1 ? 0u : x;
 }
 // value of the previous lane of the group (lane 0 gets 0)
 template <int L>
 __device__ __forceinline__ uint32_t grp_prev(uint32_t v, int pos) {
-    const uint32_t x = L == 2 ? dpp<qperm(0, 0, 2, 2)>(v) : dpp<qperm(0, 0, 1, 2)>(v);
+    uint32_t x;
+    if constexpr (L == 2) x = dpp<qperm(0, 0, 2, 2)>(v);
+    else if constexpr (L == 4) x = dpp<qperm(0, 0, 1, 2)>(v);
+    else x = row_shr<1>(v);
     return pos == 0 ? 0u : x;
 }
 template <int L>
@@ -75,23 +98,30 @@ __device__ __forceinline__ void mont_mul_lanes(uint32_t (&r)[NLT / L], const uin
 #pragma unroll
     for (int j = 0; j < K; ++j) t[j] = 0;
     __builtin_amdgcn_sched_barrier(0);
+    // NLT = L K steps, as L blocks of K unrolled steps: t shifts by one limb
+    // per step, so after K steps its registers are back in place and the
+    // block's code serves every block (code size K steps, not NLT)
+#pragma unroll 1
+    for (int blk = 0; blk < L; ++blk) {
+        const uint32_t *bb = bl + blk * K * bstride;
 #pragma unroll
-    for (int i = 0; i < NLT; ++i) {
-        const uint32_t bi = bl[i * bstride];
+        for (int ii = 0; ii < K; ++ii) {
+            const uint32_t bi = bb[ii * bstride];
 #pragma unroll
-        for (int j = 0; j < K; ++j) t[j] += (uint64_t)a[j] * bi;
-        const uint32_t m = (grp_first<L>((uint32_t)t[0]) * n0) & MASK;
+            for (int j = 0; j < K; ++j) t[j] += (uint64_t)a[j] * bi;
+            const uint32_t m = (grp_first<L>((uint32_t)t[0], pos) * n0) & MASK;
 #pragma unroll
-        for (int j = 0; j < K; ++j) t[j] += (uint64_t)m * n[j];
-        // lane 0's lowest column is now a multiple of 2^LB: its carry moves up;
-        // every other lane's lowest column moves down to the lane below
-        const uint64_t c = pos == 0 ? t[0] >> LB : 0;
-        const uint64_t in = grp_next64<L>(t[0], pos);
+            for (int j = 0; j < K; ++j) t[j] += (uint64_t)m * n[j];
+            // lane 0's lowest column is now a multiple of 2^LB: its carry moves up;
+            // every other lane's lowest column moves down to the lane below
+            const uint64_t c = pos == 0 ? t[0] >> LB : 0;
+            const uint64_t in = grp_next64<L>(t[0], pos);
 #pragma unroll
-        for (int j = 0; j < K - 1; ++j) t[j] = t[j + 1];
-        t[K - 1] = in;
-        t[0] += c;
-        __builtin_amdgcn_sched_barrier(0);
+            for (int j = 0; j < K - 1; ++j) t[j] = t[j + 1];
+            t[K - 1] = in;
+            t[0] += c;
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
     // settle carries: within each lane, then L-1 rounds across lane boundaries
     uint64_t c = 0;
@@ -134,7 +164,7 @@ __device__ __forceinline__ void canonicalize_lanes(uint32_t (&x)[K], const uint3
         bout = (uint32_t)borrow;
         bin = grp_prev<L>(bout, pos);
     }
-    const bool keep = grp_last<L>(bout) == 0;
+    const bool keep = grp_last<L>(bout, pos) == 0;
 #pragma unroll
     for (int j = 0; j < K; ++j) x[j] = keep ? d[j] : x[j];
 }

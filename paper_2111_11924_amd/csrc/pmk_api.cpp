@@ -212,7 +212,7 @@ int pmk_plan_validate(const uint32_t *key_bits, uint32_t nkeys, const uint32_t *
                       uint64_t msg_len, uint64_t *ct_len) {
     if (nkeys && !key_bits) return PMK_EINVAL;
     for (uint32_t i = 0; i < nkeys; ++i)
-        if (key_bits[i] < 128 || key_bits[i] > 4096 || key_bits[i] % 64) return PMK_EINVAL;
+        if (key_bits[i] < 128 || key_bits[i] > 8192 || key_bits[i] % 64) return PMK_EINVAL;
     return walk_chunks(key_bits, nkeys, key_map, nchunks, msg_len, ct_len, nullptr,
                        [](uint64_t, uint32_t, uint64_t, uint64_t, uint64_t) {});
 }
@@ -499,7 +499,7 @@ int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, v
         ClassRun r = pl->runs[c];
         if (!r.ntiles) continue;
         e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(r, in, decrypt, stream); });
-        if (decrypt || c < kWideFirst) order[nl++] = c;
+        if (decrypt || !is_wide_class(c)) order[nl++] = c;
     }
     if (decrypt) {  // classes by canonical work, largest first
         auto work = [&](int c) {

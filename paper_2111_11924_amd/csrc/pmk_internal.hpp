@@ -14,9 +14,9 @@ namespace pmk {
 // largest one built).  A key of `bits`
 // bits runs in the smallest class with at least that many bits: Montgomery
 // arithmetic only needs R > 4m, so a smaller modulus fits a larger class.
-constexpr int kNumClasses = 7;
-constexpr int kClassBits[kNumClasses] = {128, 256, 512, 1024, 2048, 3072, 4096};
-constexpr int kMaxClass = 6;
+constexpr int kNumClasses = 9;
+constexpr int kClassBits[kNumClasses] = {128, 256, 512, 1024, 2048, 3072, 4096, 6144, 8192};
+constexpr int kMaxClass = 8;
 
 PMK_HD constexpr int nl_for(int bits, int lb) { return (bits + 2 + lb - 1) / lb; }
 
@@ -25,13 +25,13 @@ PMK_HD constexpr int nl_for(int bits, int lb) { return (bits + 2 + lb - 1) / lb;
 PMK_HD constexpr int lb_full(int bits) { return bits > 3072 ? 27 : 28; }
 PMK_HD constexpr int lb_half(int bits) { return lb_full(bits / 2); }
 
-// Lanes per full-size bignum: one lane holds a whole number up to 2048-bit
-// moduli; the 3072- and 4096-bit classes spread each full-size number over a
-// group of 4 lanes so its limbs fit the registers.  CRT halves (at most 2048
-// bits) always fit one lane.
-PMK_HD constexpr int lanes_full(int bits) { return bits >= 3072 ? 4 : 1; }
-// chunks per tile: a tile is one wavefront of CRT halves (64 numbers); the
-// encryption of a 3072/4096-bit tile takes lanes_full wavefronts of 64/L chunks
+// Lanes per bignum.  Full-size numbers: one lane up to 2048-bit moduli, a
+// group of 4 lanes at 3072/4096 bits and of 8 lanes at 6144/8192 bits.  CRT
+// halves: one lane up to 2048-bit primes (4096-bit keys), 4 lanes above.
+PMK_HD constexpr int lanes_full(int bits) { return bits >= 6144 ? 8 : (bits >= 3072 ? 4 : 1); }
+PMK_HD constexpr int lanes_half(int bits) { return bits >= 6144 ? 4 : 1; }
+// chunks per tile: 64, one wavefront of one-lane numbers; with L lanes per
+// number a tile's exponentiation takes L wavefronts of 64/L chunks each
 PMK_HD constexpr int chunks_per_tile(int) { return 64; }
 PMK_HD constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -66,7 +66,7 @@ PMK_HD constexpr Geom make_geom(int bits) {
     g.lbf = lb_full(bits);
     g.nlf = round_up(nl_for(bits, g.lbf), lanes_full(bits));
     g.lbh = lb_half(bits);
-    g.nlh = nl_for(bits / 2, g.lbh);
+    g.nlh = round_up(nl_for(bits / 2, g.lbh), lanes_half(bits));
     g.ew = 2;
     const int pf = pad4(g.nlf), ph = pad4(g.nlh);
     int o = 0;
@@ -139,9 +139,10 @@ constexpr int kMaxWin = 6;
 // as one persistent kernel whose waves take work units from a device counter,
 // 4096-bit units first.
 constexpr int kWideClasses = 2;
-constexpr int kWideFirst = kNumClasses - kWideClasses;  // class index of 3072 bits
+constexpr int kClass3072 = 5, kClass4096 = 6;
 // class of entry i of the wide batch: 4096 bits, then 3072 bits
-constexpr int wide_class(int i) { return kNumClasses - 1 - i; }
+constexpr int wide_class(int i) { return kClass4096 - i; }
+constexpr bool is_wide_class(int c) { return c == kClass3072 || c == kClass4096; }
 struct BatchArgs {
     ClassRun runs[kWideClasses];       // runs[i] is class wide_class(i)
     uint32_t start[kWideClasses + 1];  // first unit of runs[i]; start[2] = total

@@ -251,7 +251,7 @@ int launch_round(Server *sv, RoundPlan &R, int decrypt, const std::vector<Taken>
         r.err = R.pl.d_err;
         r.slots_enc = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 0, ctx->num_cus), exp_units(c, 0, r.ntiles)));
         r.slots_dec = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 1, ctx->num_cus), exp_units(c, 1, r.ntiles)));
-        if (c >= kWideFirst) units += exp_units(c, 0, r.ntiles);
+        if (is_wide_class(c)) units += exp_units(c, 0, r.ntiles);
         e = hipMemcpyAsync(R.desc[c], R.h_desc[c].data(), R.h_desc[c].size() * sizeof(ChunkDesc),
                            hipMemcpyHostToDevice, sv->stream);
         if (e == hipSuccess)

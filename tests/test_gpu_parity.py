@@ -357,3 +357,68 @@ def test_autotune_cache_and_results(torch, ctx, tmp_path):
     finally:
         for b in bits:
             ctx.set_window(b, default[b])
+
+
+# ---------------------------------------------------------------- 6144/8192-bit keys
+# (the paper's largest key sizes: full-size numbers over 8 lanes, CRT halves over 4)
+
+@pytest.mark.parametrize("bits", [6144, 8192])
+def test_large_classes_several_tiles_ragged(torch, ctx, bits):
+    keys = inputs.make_keys([bits] * 3, 700000 + bits)
+    kb = bits // 8
+    nch = 64 * 2 + 9  # several tiles per key, ragged last tile
+    msg_len = (nch - 1) * (kb - 4) + 5
+    msg = inputs.make_message(msg_len, bits)
+    km = inputs.round_robin_map(msg_len, [bits] * 3)
+    assert len(km) == nch
+    T = oracle.KeyTable(keys)
+    ct, pt = gpu_roundtrip(torch, ctx, keys, msg, km)
+    assert (ct == oracle.encrypt(T, msg, km)).all()
+    assert (pt == msg).all()
+    for i in (0, 1, 64, nch - 1):  # CRT decryption of single blocks by the oracle
+        k = int(km[i])
+        c = int.from_bytes(bytes(ct[i * kb:(i + 1) * kb]), "big")
+        m = int.from_bytes(bytes(msg[i * (kb - 4):(i + 1) * (kb - 4)]), "big")
+        assert oracle.rsa_int(T, k, "crt", c) == m
+
+
+def test_large_and_small_classes_mixed_batch_and_blinded(torch, ctx):
+    bits = [6144, 8192, 5120, 2048, 1024]  # 5120 runs in the 6144-bit class
+    keys = inputs.make_keys(bits, 890)
+    msg = inputs.make_message(90_000 + 17, 890)
+    km = inputs.random_map(len(msg), bits, 890)
+    T = oracle.KeyTable(keys)
+    ref_ct = oracle.encrypt(T, msg, km)
+    ctx.load_keys(keys)
+    plan = ctx.plan(km, len(msg))
+    try:
+        outs = batch_roundtrip(torch, ctx, plan, msg, replays=2)
+        rblk = inputs.make_blinding(keys, km, 890)
+        cs, cr = plan.encrypt_blinded(dev(torch, msg), dev(torch, rblk))
+        pt_b = plan.decrypt_blinded(cs, cr)
+        assert plan.check() == binding.PMK_OK
+        cs_h = host(cs, plan.ct_len)
+        cr_h = host(cr, plan.ct_len)
+        pt_bh = host(pt_b, len(msg))
+    finally:
+        plan.close()
+    for k, (ct, pt) in enumerate(outs):
+        assert (ct == ref_ct).all(), f"replay {k}"
+        assert (pt == msg).all(), f"replay {k}"
+    assert (pt_bh == msg).all()
+    # one blinded chunk of each key against the oracle's blinding routine
+    off = ct_off = 0
+    seen = set()
+    for i, k in enumerate(km.tolist()):
+        kb = keys[k].bits // 8
+        ln = min(kb - 4, len(msg) - off)
+        if k not in seen and ln == kb - 4:
+            seen.add(k)
+            m = int.from_bytes(bytes(msg[off:off + ln]), "big")
+            r = int.from_bytes(bytes(rblk[ct_off:ct_off + kb]), "big")
+            c_star, c_r = oracle.blind_int(T, k, "enc", m, r)
+            assert bytes(cs_h[ct_off:ct_off + kb]) == c_star.to_bytes(kb, "big")
+            assert bytes(cr_h[ct_off:ct_off + kb]) == c_r.to_bytes(kb, "big")
+        off += ln
+        ct_off += kb
+    assert len(seen) == len(bits)
