@@ -189,6 +189,64 @@ def serve_measure(nreq: int, loads, seed: int = 5, staging_mib: int = 2048, roun
     return out
 
 
+# The paper's Table 2, configuration D (P100 + Xeon, 16 keys, 100 KB): seconds
+PAPER_TABLE2_D = {2048: (0.0009, 0.0611), 3072: (0.0014, 0.1419), 4096: (0.0021, 0.2763),
+                  6144: (0.0036, 0.7873), 8192: (0.0060, 1.6665)}
+
+
+def paper_table(steps: int, warmup: int):
+    """Per-size experiment of the paper (Sec. 4, Tables 1-2): 100 KB under 16
+    keys of each size, plain RSA chunks and blinded PMKRSA chunks, device-resident,
+    event-timed per call; the paper's configuration-D seconds beside them."""
+    import numpy as np
+    import torch
+
+    from paper_2111_11924_amd import binding, inputs
+
+    rows = []
+    stream = torch.cuda.current_stream()
+    for bits in inputs.TABLE_BITS:
+        w = inputs.table_workload(bits)
+        keys, msg, km = w.keys(), w.message(), w.key_map()
+        ctx = binding.Context(0)
+        ctx.load_keys(keys)
+        plan = ctx.plan(km, len(msg))
+        d_msg = torch.from_numpy(msg).to("cuda")
+        d_r = torch.from_numpy(inputs.make_blinding(keys, km, w.seed)).to("cuda")
+        d_ct = torch.empty(plan.ct_len, dtype=torch.uint8, device="cuda")
+        d_cs = torch.empty(plan.ct_len, dtype=torch.uint8, device="cuda")
+        d_cr = torch.empty(plan.ct_len, dtype=torch.uint8, device="cuda")
+        d_pt = torch.empty(len(msg), dtype=torch.uint8, device="cuda")
+        d_pb = torch.empty(len(msg), dtype=torch.uint8, device="cuda")
+        ops = {
+            "enc": lambda: binding.pmk_encrypt_plan(plan.handle, d_msg, d_ct, stream, ctx.handle),
+            "dec": lambda: binding.pmk_decrypt_plan(plan.handle, d_ct, d_pt, stream, ctx.handle),
+            "enc_blinded": lambda: binding.pmk_encrypt_blinded_plan(plan.handle, d_msg, d_r, d_cs, d_cr, stream,
+                                                                    ctx.handle),
+            "dec_blinded": lambda: binding.pmk_decrypt_blinded_plan(plan.handle, d_cs, d_cr, d_pb, stream,
+                                                                    ctx.handle),
+        }
+        row = {"bits": bits, "keys": 16, "message_bytes": len(msg), "chunks": len(km)}
+        for name, fn in ops.items():
+            for _ in range(warmup):
+                fn()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            torch.cuda.synchronize()
+            ev[0].record(stream)
+            for _ in range(steps):
+                fn()
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            row[name + "_s"] = ev[0].elapsed_time(ev[1]) / steps / 1e3
+        row["ok"] = bool(plan.check(stream) == binding.PMK_OK and torch.equal(d_pt, d_msg)
+                         and torch.equal(d_pb, d_msg))
+        row["paper_D_enc_s"], row["paper_D_dec_s"] = PAPER_TABLE2_D[bits]
+        rows.append(row)
+        plan.close()
+        ctx.close()
+    return rows
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +258,8 @@ def main() -> int:
     ap.add_argument("--window", type=int, default=0, help="fix the CRT window width of every class")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the short serving pass that fills p99_request_ms")
+    ap.add_argument("--paper-table", action="store_true",
+                    help="the paper's per-size experiment: 100 KB under 16 keys of 2048..8192 bits")
     ap.add_argument("--serve", action="store_true",
                     help="serving workload only: capacity, then Poisson loads 0.5/0.8/1.2 of it")
     ap.add_argument("--serve-requests", type=int, default=0,
@@ -238,6 +298,15 @@ def main() -> int:
                                                                     "load_for_value": 0.8}})
         print(json.dumps(res))
         return 0 if res["results_ok"] else 1
+
+    if args.paper_table:
+        rows = paper_table(args.steps, args.warmup)
+        print(json.dumps({"metric": "seconds per 100 KB, encrypt / CRT decrypt, plain and blinded PMKRSA chunks",
+                          "unit": "s", "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
+                          "config": {"workload": "table-100KB-16keys", "key_bits": [r["bits"] for r in rows]},
+                          "rows": rows,
+                          "paper_context": "paper Table 2, configuration D: NVIDIA P100 + Xeon, context only"}))
+        return 0 if all(r["ok"] for r in rows) else 1
 
     if args.copy_probe:
         # a copy of known size: what FETCH_SIZE / WRITE_SIZE read for it scales

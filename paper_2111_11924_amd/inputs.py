@@ -329,6 +329,18 @@ def config(idx: int) -> Workload:
     raise ValueError(idx)
 
 
+# Key sizes of the paper's per-size experiment (Sec. 4, Tables 1 and 2).
+TABLE_BITS = (2048, 3072, 4096, 6144, 8192)
+
+
+def table_workload(bits: int) -> Workload:
+    """The paper's per-size experiment (Sec. 4, Tables 1-2, configuration D):
+    a 102,400-byte random plaintext under 16 key pairs of one size, chunk i
+    under key i mod 16."""
+    return Workload(f"table-{bits}b-100KB", 600 + bits // 64, [bits] * 16, 102_400, "round_robin",
+                    "16 keys, 100 KB, round-robin")
+
+
 CONFIGS: Dict[int, str] = {i: config(i).name for i in range(1, 6)}
 
 
