@@ -257,6 +257,25 @@ int pmk_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uint32
                 uint64_t nchunks, uint8_t *d_msg, uint64_t msg_len, void *stream);
 
 /*
+ * Batched primality testing for key generation: the primes p, q of every key
+ * pair of Algorithm 1's initialisation (Sec. 1.1 step 1; Sec. 3.1), tested on
+ * the GPU, one lane per candidate.  `bits` is the key size the primes are for:
+ * 1024, 2048, 3072 or 4096 (candidates of up to bits/2 bits; PMK_EUNSUPPORTED
+ * otherwise).  Candidate i is the bits/64 little-endian 32-bit words at
+ * d_cand[i * bits/64], odd and above 3 (above 4096 for the sieve).  Device
+ * buffers; asynchronous on `stream`.
+ *   pmk_sieve: d_flags[i] = 1 if no odd prime below 4096 divides candidate i, else 0.
+ *   pmk_miller_rabin: d_result[i] = 1 if candidate i passes Miller-Rabin for
+ *     every one of its `rounds` bases (1..256), base r at
+ *     d_bases[(i * rounds + r) * bits/64] with 1 < base < m - 1 (the caller draws
+ *     them); 0 if some base shows it composite.  Uses the context's window width
+ *     for the `bits` class; keeps a table scratch on the context.
+ */
+int pmk_sieve(pmk_ctx *ctx, uint32_t bits, const uint32_t *d_cand, uint32_t count, uint32_t *d_flags, void *stream);
+int pmk_miller_rabin(pmk_ctx *ctx, uint32_t bits, const uint32_t *d_cand, uint32_t count, const uint32_t *d_bases,
+                     uint32_t rounds, uint32_t *d_result, void *stream);
+
+/*
  * Request server (continuous batching).  A scheduler thread on the context
  * serves encryption and CRT-decryption requests of any size against the
  * loaded key table: the chunks of every admitted request join batching rounds

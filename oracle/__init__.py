@@ -222,3 +222,45 @@ def threads() -> int:
 
 def set_threads(n: int) -> None:
     lib().oracle_set_threads(int(n))
+
+
+# ---------- primality (key generation) -----------------------------------------------------
+
+def small_odd_primes(limit: int = 4096):
+    """Odd primes below `limit`, by a plain sieve of Eratosthenes."""
+    comp = [False] * limit
+    out = []
+    for i in range(3, limit, 2):
+        if not comp[i]:
+            out.append(i)
+            for j in range(i * i, limit, 2 * i):
+                comp[j] = True
+    return out
+
+
+def trial_division_pass(m: int, limit: int = 4096) -> bool:
+    """True if no odd prime below `limit` divides m."""
+    return all(m % p for p in small_odd_primes(limit))
+
+
+def miller_rabin(m: int, bases) -> bool:
+    """The Miller-Rabin test written out (m odd, m > 3): with m - 1 = 2^s d, d
+    odd, base a passes if a^d = 1 or a^(2^j d) = m - 1 for some 0 <= j < s
+    (Python's built-in pow is the modular exponentiation step).  True if every
+    base passes (probable prime), False if one shows m composite."""
+    d, s = m - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        s += 1
+    for a in bases:
+        x = pow(a, d, m)
+        if x == 1 or x == m - 1:
+            continue
+        for _ in range(s - 1):
+            x = x * x % m
+            if x == m - 1:
+                break
+        else:
+            return False
+    return True
+

@@ -116,6 +116,8 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "pmk_set_window": (C.c_int, [vp, u32, C.c_int]),
         "pmk_get_window": (C.c_int, [vp, u32]),
         "pmk_autotune": (C.c_int, [vp, C.c_char_p, C.c_int]),
+        "pmk_sieve": (C.c_int, [vp, u32, vp, u32, vp, vp]),
+        "pmk_miller_rabin": (C.c_int, [vp, u32, vp, u32, vp, u32, vp, vp]),
         "pmk_server_start": (C.c_int, [vp, C.POINTER(pmk_server_cfg)]),
         "pmk_submit": (C.c_int, [vp, C.POINTER(pmk_request), C.POINTER(u64)]),
         "pmk_poll": (C.c_int, [vp, u64, C.POINTER(pmk_ticket_info)]),
@@ -331,6 +333,16 @@ def pmk_decrypt(ctx: int, d_ct, ct_len: int, key_map, d_msg, msg_len: int, strea
     km = _map_array(key_map)
     return load_library().pmk_decrypt(ctx, _dev_ptr(d_ct), int(ct_len), km.ctypes.data_as(U32P), len(km),
                                       _dev_ptr(d_msg), int(msg_len), _stream(stream))
+
+
+def pmk_sieve(ctx: int, bits: int, d_cand, count: int, d_flags, stream=None) -> None:
+    _check(load_library().pmk_sieve(ctx, int(bits), _dev_ptr(d_cand), int(count), _dev_ptr(d_flags),
+                                    _stream(stream)), ctx)
+
+
+def pmk_miller_rabin(ctx: int, bits: int, d_cand, count: int, d_bases, rounds: int, d_result, stream=None) -> None:
+    _check(load_library().pmk_miller_rabin(ctx, int(bits), _dev_ptr(d_cand), int(count), _dev_ptr(d_bases),
+                                           int(rounds), _dev_ptr(d_result), _stream(stream)), ctx)
 
 
 def pmk_server_start(ctx: int, staging_bytes: int = 0, round_chunks: int = 0, pipeline_depth: int = 0) -> None:

@@ -139,6 +139,7 @@ void pmk_destroy(pmk_ctx *ctx) {
     while (!ctx->plans.empty()) pmk_plan_destroy(*ctx->plans.begin());
     for (auto &p : ctx->d_keys)
         if (p) (void)hipFree(p);
+    if (ctx->mr_table) (void)hipFree(ctx->mr_table);
     delete ctx;
 }
 
@@ -782,6 +783,52 @@ int pmk_autotune(pmk_ctx *ctx, const char *cache_path, int flags) {
         std::fclose(f);
     }
     return PMK_OK;
+}
+
+static int prime_args(pmk_ctx *ctx, uint32_t bits, const void *cand, uint32_t count, const void *out, int *cls) {
+    if (!ctx) return PMK_EINVAL;
+    const int c = class_for_bits(bits);
+    if (c < 0 || kClassBits[c] != (int)bits || !prime_class_ok(c))
+        return set_err(ctx, PMK_EUNSUPPORTED, "primality tests take candidates for 1024-, 2048-, 3072- or 4096-bit keys");
+    if (count && (!cand || !out)) return set_err(ctx, PMK_EINVAL, "NULL buffer");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
+    *cls = c;
+    return PMK_OK;
+}
+
+int pmk_sieve(pmk_ctx *ctx, uint32_t bits, const uint32_t *d_cand, uint32_t count, uint32_t *d_flags, void *stream) {
+    int c = 0;
+    const int rc = prime_args(ctx, bits, d_cand, count, d_flags, &c);
+    if (rc != PMK_OK || count == 0) return rc;
+    const int e = launch_sieve_class(c, d_cand, count, d_flags, ctx->device, stream);
+    return e ? hip_err(ctx, (hipError_t)e, "sieve launch") : PMK_OK;
+}
+
+int pmk_miller_rabin(pmk_ctx *ctx, uint32_t bits, const uint32_t *d_cand, uint32_t count, const uint32_t *d_bases,
+                     uint32_t rounds, uint32_t *d_result, void *stream) {
+    int c = 0;
+    int rc = prime_args(ctx, bits, d_cand, count, d_result, &c);
+    if (rc != PMK_OK || count == 0) return rc;
+    if (!d_bases || rounds == 0 || rounds > 256) return set_err(ctx, PMK_EINVAL, "need 1..256 bases per candidate");
+    const int win = ctx->win[c];
+    const uint32_t units = (count + kTile - 1) / kTile;
+    const uint32_t grid = std::max<uint32_t>(1, std::min(units, mr_wave_slots(c, ctx->num_cus)));
+    const uint64_t slot = mr_slot_words(c, win);
+    const uint64_t need = (uint64_t)grid * slot;
+    if (need > ctx->mr_cap) {
+        (void)hipDeviceSynchronize();  // earlier tests may still use the old table
+        if (ctx->mr_table) (void)hipFree(ctx->mr_table);
+        ctx->mr_table = nullptr;
+        ctx->mr_cap = 0;
+        void *v = nullptr;
+        const hipError_t e = hipMalloc(&v, need * sizeof(uint32_t));
+        if (e != hipSuccess) return hip_err(ctx, e, "primality test tables");
+        ctx->mr_table = (uint32_t *)v;
+        ctx->mr_cap = need;
+    }
+    const int e = launch_mr_class(c, d_cand, count, d_bases, (int)rounds, win, ctx->mr_table, slot, grid, d_result,
+                                  stream);
+    return e ? hip_err(ctx, (hipError_t)e, "Miller-Rabin launch") : PMK_OK;
 }
 
 int pmk_plan_check(pmk_plan *pl, void *stream) {

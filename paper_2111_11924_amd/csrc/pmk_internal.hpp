@@ -172,4 +172,12 @@ uint32_t batch_wave_slots(int num_cus);
 // table words per wave slot of the wide batch kernel
 uint64_t batch_slot_words();
 
+// primality testing for key generation (kprime.hip); classes 3..6 (1024..4096-bit keys)
+int prime_class_ok(int cls);
+uint64_t mr_slot_words(int cls, int win);
+uint32_t mr_wave_slots(int cls, int num_cus);
+int launch_sieve_class(int cls, const uint32_t *cand, uint32_t count, uint32_t *flags, int device, void *stream);
+int launch_mr_class(int cls, const uint32_t *cand, uint32_t count, const uint32_t *bases, int rounds, int win,
+                    uint32_t *table, uint64_t slot_words, uint32_t grid, uint32_t *result, void *stream);
+
 }  // namespace pmk

@@ -38,6 +38,8 @@ struct pmk_ctx {
     uint32_t epoch = 0;         // bumped when a tuning choice changes (captured graphs go stale)
     std::string device_name;
     pmk::Server *server = nullptr;  // request server (pmk_server_start), if running
+    uint32_t *mr_table = nullptr;   // window tables of the primality tests
+    uint64_t mr_cap = 0;            // words at mr_table
 };
 
 struct TimedLaunch {
