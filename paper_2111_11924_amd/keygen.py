@@ -23,15 +23,36 @@ def _words(x: int, n: int) -> np.ndarray:
     return np.frombuffer(int(x).to_bytes(4 * n, "little"), dtype=np.uint32)
 
 
+def _bases(rng: np.random.Generator, count: int, rounds: int, words: int) -> np.ndarray:
+    """Random bases 1 < a < m - 1 for candidates whose top word is at least
+    2^31 (top two bits set): a's top word is below 2^31, and a = 0 or 1 is
+    replaced by 2."""
+    a = rng.integers(0, 1 << 32, size=(count, rounds, words), dtype=np.uint64).astype(np.uint32)
+    a[:, :, -1] &= np.uint32(0x7FFFFFFF)
+    tiny = (a[:, :, 1:] == 0).all(axis=2) & (a[:, :, 0] < 2)
+    a[:, :, 0][tiny] = 2
+    return a
+
+
 def gpu_primes(ctx: "binding.Context", bits: int, count: int, seed: int, rounds: int = 40,
-               batch: int = 8192, e: int = inputs.E_DEFAULT) -> List[int]:
-    """`count` distinct probable primes of bits/2 bits for `bits`-bit keys."""
+               batch: int = 16384, e: int = inputs.E_DEFAULT) -> List[int]:
+    """`count` distinct probable primes of bits/2 bits for `bits`-bit keys:
+    GPU trial division, then one Miller-Rabin round on every survivor and the
+    remaining rounds on those that pass it."""
     import torch
 
-    half, words = bits // 2, bits // 64
+    words = bits // 64
     rng = np.random.Generator(np.random.PCG64(seed * 1000 + 6))
     found: List[int] = []
     seen = set()
+
+    def mr(packed: np.ndarray, r: int) -> np.ndarray:
+        d_c = torch.from_numpy(np.ascontiguousarray(packed).reshape(-1)).to("cuda")
+        d_b = torch.from_numpy(_bases(rng, len(packed), r, words).reshape(-1)).to("cuda")
+        d_r = torch.zeros(len(packed), dtype=torch.int32, device="cuda")
+        binding.pmk_miller_rabin(ctx.handle, bits, d_c, len(packed), d_b, r, d_r)
+        return d_r.cpu().numpy().astype(bool)
+
     while len(found) < count:
         raw = rng.integers(0, 1 << 32, size=(batch, words), dtype=np.uint64).astype(np.uint32)
         raw[:, 0] |= 1                                   # odd
@@ -39,24 +60,17 @@ def gpu_primes(ctx: "binding.Context", bits: int, count: int, seed: int, rounds:
         d_cand = torch.from_numpy(raw.reshape(-1)).to("cuda")
         d_flags = torch.zeros(batch, dtype=torch.int32, device="cuda")
         binding.pmk_sieve(ctx.handle, bits, d_cand, batch, d_flags)
-        keep = np.nonzero(d_flags.cpu().numpy())[0]
-        cands = [int.from_bytes(raw[i].tobytes(), "little") for i in keep.tolist()]
-        cands = [m for m in cands if math.gcd(e, m - 1) == 1 and m not in seen]
-        if not cands:
+        surv = raw[d_flags.cpu().numpy().astype(bool)]
+        if len(surv) == 0:
             continue
-        bases = np.zeros((len(cands), rounds, words), dtype=np.uint32)
-        for i, m in enumerate(cands):
-            for r in range(rounds):
-                a = 2 + inputs.rand_int(rng, half + 64) % (m - 3)
-                bases[i, r] = _words(a, words)
-        packed = np.stack([_words(m, words) for m in cands])
-        d_c = torch.from_numpy(packed.reshape(-1)).to("cuda")
-        d_b = torch.from_numpy(bases.reshape(-1)).to("cuda")
-        d_r = torch.zeros(len(cands), dtype=torch.int32, device="cuda")
-        binding.pmk_miller_rabin(ctx.handle, bits, d_c, len(cands), d_b, rounds, d_r)
-        res = d_r.cpu().numpy()
-        for m, ok in zip(cands, res.tolist()):
-            if ok and m not in seen:
+        surv = surv[mr(surv, 1)]                         # one round weeds out the composites
+        if len(surv) == 0:
+            continue
+        if rounds > 1:
+            surv = surv[mr(surv, rounds - 1)]
+        for row in surv:
+            m = int.from_bytes(row.tobytes(), "little")
+            if math.gcd(e, m - 1) == 1 and m not in seen:
                 seen.add(m)
                 found.append(m)
     return found[:count]
