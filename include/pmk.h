@@ -257,6 +257,58 @@ int pmk_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uint32
                 uint64_t nchunks, uint8_t *d_msg, uint64_t msg_len, void *stream);
 
 /*
+ * Multi-prime keys (Sec. 2.1, the multi-prime variant: N is the product of b
+ * distinct primes of bits/b bits, and decryption runs b exponentiations modulo
+ * the primes, on numbers of bits/b bits, then one recombination; against two
+ * CRT halves of bits/2 bits that is b^2/4 times less work).  Supported: b = 3 with 3072-bit N and b = 4 with
+ * 4096-bit N, every prime of exactly 1024 bits.
+ *   bits     3072 or 4096.
+ *   nprimes  bits / 1024.
+ *   n        bits/32 limbs.
+ *   primes   nprimes x 32 limbs: p_0, p_1, ... one after another.
+ *   d        nprimes x 32 limbs: d_i = d mod (p_i - 1), below p_i.
+ * Checked at load time: N odd with exactly `bits` bits, every prime odd with
+ * 1024 bits, product of the primes = N, primes pairwise coprime, d_i < p_i.
+ * The caller keeps ownership of the arrays; the library copies them.
+ */
+typedef struct {
+    uint32_t bits;
+    uint32_t nprimes;
+    const uint32_t *n;
+    const uint32_t *primes;
+    const uint32_t *d;
+} pmk_key_mp;
+
+/* Host-only check of one multi-prime key: PMK_OK or PMK_EINVAL (reason in
+ * msg[0..msg_cap), msg may be NULL). */
+int pmk_mp_key_check(const pmk_key_mp *key, char *msg, size_t msg_cap);
+
+/*
+ * Load (replace) the context's multi-prime key table, separate from the
+ * two-prime table of pmk_keys_load (key indices of pmk_mp_decrypt name rows of
+ * this table).  Derives the per-prime Montgomery constants and the inverses
+ * p_j^-1 mod p_i of the recombination.  Synchronous; PMK_EINVAL names the
+ * first bad key.
+ */
+int pmk_mp_keys_load(pmk_ctx *ctx, const pmk_key_mp *keys, uint32_t nkeys);
+uint32_t pmk_mp_key_count(const pmk_ctx *ctx);
+
+/*
+ * Decrypt a ciphertext made under multi-prime keys: the chunk layout of
+ * pmk_plan_create (chunk i of key key_map[i] carries up to bits/8 - 4
+ * plaintext bytes in one bits/8-byte block; key_map is host memory), every
+ * block m = C^d mod N by one exponentiation per prime, m_i = C^(d_i) mod p_i,
+ * and Garner's mixed-radix recombination
+ * m = v_0 + p_0 (v_1 + p_1 (v_2 + ...)).  d_ct (ct_len bytes) and d_msg
+ * (msg_len bytes) are device memory, 4-byte aligned.  Synchronous on
+ * `stream`; allocates and frees its scratch.  PMK_EKEY / PMK_ESIZE as
+ * pmk_plan_create, PMK_ERANGE when a block is not below its modulus (the
+ * output is then unspecified).
+ */
+int pmk_mp_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uint32_t *key_map,
+                   uint64_t nchunks, uint8_t *d_msg, uint64_t msg_len, void *stream);
+
+/*
  * Batched primality testing for key generation: the primes p, q of every key
  * pair of Algorithm 1's initialisation (Sec. 1.1 step 1; Sec. 3.1), tested on
  * the GPU, one lane per candidate.  `bits` is the key size the primes are for:

@@ -56,6 +56,10 @@ class pmk_key(C.Structure):
                 ("dq", U32P), ("qinv", U32P)]
 
 
+class pmk_key_mp(C.Structure):
+    _fields_ = [("bits", C.c_uint32), ("nprimes", C.c_uint32), ("n", U32P), ("primes", U32P), ("d", U32P)]
+
+
 class pmk_server_cfg(C.Structure):
     _fields_ = [("staging_bytes", C.c_uint64), ("round_chunks", C.c_uint64), ("pipeline_depth", C.c_uint32)]
 
@@ -129,6 +133,10 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "pmk_plan_kernel_time": (C.c_int, [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(u64)]),
         "pmk_encrypt": (C.c_int, [vp, vp, u64, U32P, u64, vp, u64, vp]),
         "pmk_decrypt": (C.c_int, [vp, vp, u64, U32P, u64, vp, u64, vp]),
+        "pmk_mp_key_check": (C.c_int, [C.POINTER(pmk_key_mp), C.c_char_p, C.c_size_t]),
+        "pmk_mp_keys_load": (C.c_int, [vp, C.POINTER(pmk_key_mp), u32]),
+        "pmk_mp_key_count": (u32, [vp]),
+        "pmk_mp_decrypt": (C.c_int, [vp, vp, u64, U32P, u64, vp, u64, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -167,6 +175,30 @@ class KeyArray:
             st.n0inv = int(k.n0inv)
             st.e_limbs = el
             for f, a in fields.items():
+                self._keep.append(a)
+                setattr(st, f, a.ctypes.data_as(U32P))
+
+    def ptr(self):
+        return self.arr
+
+
+class MpKeyArray:
+    """pmk_key_mp structs for key objects with int fields bits, n and lists
+    primes, exps (d_i = d mod (p_i - 1)); keeps the limb arrays alive."""
+
+    def __init__(self, keys: Sequence):
+        self.count = len(keys)
+        self.arr = (pmk_key_mp * max(1, self.count))()
+        self._keep: List[np.ndarray] = []
+        for i, k in enumerate(keys):
+            bits = int(k.bits)
+            primes = np.concatenate([_limbs(int(p), 32) for p in k.primes]) if len(k.primes) else _limbs(0, 1)
+            exps = np.concatenate([_limbs(int(d), 32) for d in k.exps]) if len(k.exps) else _limbs(0, 1)
+            n = _limbs(int(k.n), bits // 32)
+            st = self.arr[i]
+            st.bits = bits
+            st.nprimes = len(k.primes)
+            for f, a in (("n", n), ("primes", primes), ("d", exps)):
                 self._keep.append(a)
                 setattr(st, f, a.ctypes.data_as(U32P))
 
@@ -333,6 +365,28 @@ def pmk_decrypt(ctx: int, d_ct, ct_len: int, key_map, d_msg, msg_len: int, strea
     km = _map_array(key_map)
     return load_library().pmk_decrypt(ctx, _dev_ptr(d_ct), int(ct_len), km.ctypes.data_as(U32P), len(km),
                                       _dev_ptr(d_msg), int(msg_len), _stream(stream))
+
+
+def pmk_mp_key_check(key) -> Tuple[int, str]:
+    ka = MpKeyArray([key])
+    buf = C.create_string_buffer(256)
+    rc = load_library().pmk_mp_key_check(ka.ptr(), buf, 256)
+    return rc, buf.value.decode()
+
+
+def pmk_mp_keys_load(ctx: int, keys: Sequence) -> None:
+    ka = keys if isinstance(keys, MpKeyArray) else MpKeyArray(keys)
+    _check(load_library().pmk_mp_keys_load(ctx, ka.ptr(), ka.count), ctx)
+
+
+def pmk_mp_key_count(ctx: int) -> int:
+    return load_library().pmk_mp_key_count(ctx)
+
+
+def pmk_mp_decrypt(ctx: int, d_ct, ct_len: int, key_map, d_msg, msg_len: int, stream=None) -> int:
+    km = _map_array(key_map)
+    return load_library().pmk_mp_decrypt(ctx, _dev_ptr(d_ct), int(ct_len), km.ctypes.data_as(U32P), len(km),
+                                         _dev_ptr(d_msg), int(msg_len), _stream(stream))
 
 
 def pmk_sieve(ctx: int, bits: int, d_cand, count: int, d_flags, stream=None) -> None:
@@ -525,6 +579,18 @@ class Context:
 
     def load_keys(self, keys: Sequence) -> None:
         pmk_keys_load(self.handle, keys)
+
+    def load_mp_keys(self, keys: Sequence) -> None:
+        pmk_mp_keys_load(self.handle, keys)
+
+    def mp_decrypt(self, ct, key_map, msg_len: int, msg=None, stream=None):
+        """Multi-prime CRT decryption (pmk_mp_decrypt, synchronous); returns the message tensor."""
+        import torch
+
+        if msg is None:
+            msg = torch.empty(max(1, msg_len), dtype=torch.uint8, device=ct.device)
+        _check(pmk_mp_decrypt(self.handle, ct, ct.numel(), key_map, msg, msg_len, stream), self.handle)
+        return msg
 
     def set_window(self, bits: int, win: int) -> None:
         pmk_set_window(self.handle, bits, win)

@@ -121,6 +121,78 @@ void mont_consts(const Words &m, int lb, int nl, uint32_t *one, uint32_t *rr, ui
     }
 }
 
+bool is_one(const Words &x) {
+    if (x.empty() || x[0] != 1u) return false;
+    for (size_t i = 1; i < x.size(); ++i)
+        if (x[i]) return false;
+    return true;
+}
+
+bool is_zero(const Words &x) {
+    for (uint32_t v : x)
+        if (v) return false;
+    return true;
+}
+
+void halve(Words &x) {  // x >>= 1
+    for (size_t i = 0; i < x.size(); ++i) x[i] = (x[i] >> 1) | (i + 1 < x.size() ? x[i + 1] << 31 : 0u);
+}
+
+// x = x / 2 mod m for odd m, 0 <= x < m: (x + m) / 2 when x is odd
+void half_mod(Words &x, const Words &m) {
+    if (!(x[0] & 1u)) {
+        halve(x);
+        return;
+    }
+    uint64_t c = 0;
+    for (size_t i = 0; i < x.size(); ++i) {
+        const uint64_t v = (uint64_t)x[i] + m[i] + c;
+        x[i] = (uint32_t)v;
+        c = v >> 32;
+    }
+    halve(x);
+    x.back() |= (uint32_t)c << 31;
+}
+
+// x = x - y mod m, both below m
+void mod_sub(Words &x, const Words &y, const Words &m) {
+    if (cmp(x, y) >= 0) {
+        sub_in(x, y);
+        return;
+    }
+    Words d = y;
+    sub_in(d, x);  // y - x, below m
+    x = m;
+    sub_in(x, d);
+}
+
+// a^-1 mod m for odd m and 0 < a < m by the binary extended Euclidean
+// algorithm (invariants x1 a = u, x2 a = v mod m); false when gcd(a, m) > 1
+bool mod_inverse(const Words &a, const Words &m, Words *out) {
+    Words u = a, v = m, x1(m.size(), 0), x2(m.size(), 0);
+    x1[0] = 1;
+    while (!is_one(u) && !is_one(v)) {
+        if (is_zero(u)) return false;  // gcd = v > 1
+        while (!(u[0] & 1u)) {
+            halve(u);
+            half_mod(x1, m);
+        }
+        while (!(v[0] & 1u)) {
+            halve(v);
+            half_mod(x2, m);
+        }
+        if (cmp(u, v) >= 0) {
+            sub_in(u, v);
+            mod_sub(x1, x2, m);
+        } else {
+            sub_in(v, u);
+            mod_sub(x2, x1, m);
+        }
+    }
+    *out = is_one(u) ? x1 : x2;
+    return true;
+}
+
 bool fail(std::string *msg, const char *what) {
     if (msg) *msg = what;
     return false;
@@ -205,6 +277,65 @@ void build_record(const pmk_key &k, int cls, uint32_t *rec) {
         Words x = from(k.qinv, SH, g.SH);
         for (int i = 0; i < g.lbh * g.nlh; ++i) mod_double(x, p);
         to_radix(x, g.lbh, g.nlh, rec + g.off_qinvr);
+    }
+}
+
+bool check_key_mp(const pmk_key_mp &k, std::string *msg) {
+    if (k.bits != 3072 && k.bits != 4096) return fail(msg, "multi-prime keys must have 3072 or 4096 bits");
+    if (k.nprimes != k.bits / 1024) return fail(msg, "nprimes must be bits / 1024 (primes of 1024 bits)");
+    if (!k.n || !k.primes || !k.d) return fail(msg, "null key field");
+    const int S = k.bits / 32, P = (int)k.nprimes;
+    const Words n = from(k.n, S, S);
+    if (!(n[0] & 1u)) return fail(msg, "modulus must be odd");
+    if (bitlen(n) != (int)k.bits) return fail(msg, "modulus must have exactly `bits` bits");
+    std::vector<Words> p(P);
+    Words prod(1, 1u);
+    for (int i = 0; i < P; ++i) {
+        p[i] = from(k.primes + 32 * i, 32, 32);
+        if (!(p[i][0] & 1u) || bitlen(p[i]) != 1024) return fail(msg, "every prime must be odd with exactly 1024 bits");
+        if (cmp(from(k.d + 32 * i, 32, 32), p[i]) >= 0) return fail(msg, "d_i must be below p_i");
+        prod = mul(prod, p[i]);
+    }
+    if (cmp(prod, n) != 0) return fail(msg, "the product of the primes is not N");
+    for (int i = 1; i < P; ++i)
+        for (int j = 0; j < i; ++j) {
+            Words a = p[j], inv;
+            if (cmp(a, p[i]) >= 0) sub_in(a, p[i]);  // p_j < 2 p_i
+            if (!mod_inverse(a, p[i], &inv)) return fail(msg, "primes must be pairwise coprime");
+            Words unit(32, 0);
+            unit[0] = 1;
+            if (cmp(mulmod(inv, a, p[i]), unit) != 0) return fail(msg, "prime inverse check failed");
+        }
+    return true;
+}
+
+void build_record_mp(const pmk_key_mp &k, int cls, uint32_t *rec) {
+    const MpGeom g = make_mp_geom(cls);
+    std::memset(rec, 0, sizeof(uint32_t) * g.stride);
+    const Words n = from(k.n, g.S, g.S);
+    for (int i = 0; i < g.S; ++i) rec[g.off_n32 + i] = n[i];
+    rec[g.off_kbytes] = k.bits / 8;
+    constexpr int PL = pad4(kMpNL), RB = kMpLB * kMpNL;  // R = 2^RB
+    for (int i = 0; i < g.parts; ++i) {
+        uint32_t *qr = rec + g.off_part[i];
+        const Words m = from(k.primes + 32 * i, 32, 32);
+        to_radix(m, kMpLB, kMpNL, qr + g.q_m);
+        qr[g.q_m0] = (0u - inv32(m[0])) & ((1u << kMpLB) - 1u);
+        Words x(32, 0);
+        x[0] = 1;
+        for (int r = 1; r <= g.parts + 1; ++r) {  // R^r mod p
+            for (int b = 0; b < RB; ++b) mod_double(x, m);
+            if (r == 1) to_radix(x, kMpLB, kMpNL, qr + g.q_one);
+            else to_radix(x, kMpLB, kMpNL, qr + g.q_rpow + (r - 2) * PL);
+        }
+        for (int w = 0; w < 32; ++w) qr[g.q_d + w] = k.d[32 * i + w];
+        for (int j = 0; j < i; ++j) {
+            Words a = from(k.primes + 32 * j, 32, 32), inv;
+            if (cmp(a, m) >= 0) sub_in(a, m);
+            mod_inverse(a, m, &inv);  // checked by check_key_mp
+            for (int b = 0; b < RB; ++b) mod_double(inv, m);
+            to_radix(inv, kMpLB, kMpNL, qr + g.q_cinv + j * PL);
+        }
     }
 }
 

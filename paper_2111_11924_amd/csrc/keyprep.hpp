@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "../../include/pmk.h"
+#include "mp_geom.hpp"
 #include "pmk_internal.hpp"
 
 namespace pmk {
@@ -20,5 +21,11 @@ bool check_key(const pmk_key &k, std::string *msg);
 
 // Writes the Geom(kClassBits[cls]).stride-word record of a checked key.
 void build_record(const pmk_key &k, int cls, uint32_t *rec);
+
+// Multi-prime keys: checks (3072 bits with 3 or 4096 bits with 4 primes of
+// exactly 1024 bits, product N, pairwise coprime, d_i < p_i) and the
+// make_mp_geom(cls).stride-word record (cls 0: 3072 bits, 1: 4096 bits).
+bool check_key_mp(const pmk_key_mp &k, std::string *msg);
+void build_record_mp(const pmk_key_mp &k, int cls, uint32_t *rec);
 
 }  // namespace pmk

@@ -140,6 +140,8 @@ void pmk_destroy(pmk_ctx *ctx) {
     for (auto &p : ctx->d_keys)
         if (p) (void)hipFree(p);
     if (ctx->mr_table) (void)hipFree(ctx->mr_table);
+    for (auto &p : ctx->d_mp_keys)
+        if (p) (void)hipFree(p);
     delete ctx;
 }
 

@@ -40,6 +40,9 @@ struct pmk_ctx {
     pmk::Server *server = nullptr;  // request server (pmk_server_start), if running
     uint32_t *mr_table = nullptr;   // window tables of the primality tests
     uint64_t mr_cap = 0;            // words at mr_table
+    // multi-prime key table (pmk_mp_keys_load): records per class (3072 / 4096 bits)
+    std::vector<KeySlot> mp_keys;
+    uint32_t *d_mp_keys[2] = {};
 };
 
 struct TimedLaunch {

@@ -188,6 +188,48 @@ def make_key(bits: int, seed: int, index: int, e: int = E_DEFAULT) -> RsaKey:
     return key
 
 
+@dataclass
+class MpKey:
+    """A multi-prime key (Sec. 2.1, multi-prime variant): N = p_0 ... p_(b-1);
+    ``exps`` holds d_i = d mod (p_i - 1).  ``p, q, dp, dq, qinv`` are zero (no
+    two-prime split), so the oracle's plain c^d route is the one that applies."""
+
+    bits: int
+    n: int
+    e: int
+    d: int
+    primes: List[int]
+    exps: List[int]
+    p: int = 0
+    q: int = 0
+    dp: int = 0
+    dq: int = 0
+    qinv: int = 0
+
+
+def make_mp_key(bits: int, seed: int, index: int, e: int = E_DEFAULT) -> MpKey:
+    """Multi-prime key ``index`` of stream ``seed``: bits/1024 distinct primes of
+    1024 bits (3072 bits: 3 primes, 4096 bits: 4); d = e^-1 mod lcm(p_i - 1)."""
+    if bits not in (3072, 4096):
+        raise ValueError("multi-prime keys are 3072 or 4096 bits")
+    rng = np.random.Generator(np.random.PCG64([seed, index, bits, 7]))
+    primes: List[int] = []
+    while True:
+        while len(primes) < bits // 1024:
+            p = gen_prime(1024, rng, e)
+            if p not in primes:
+                primes.append(p)
+        n = math.prod(primes)
+        if n.bit_length() == bits:
+            break
+        primes.remove(min(primes))  # product one bit short: redraw its smallest prime
+    lam = 1
+    for p in primes:
+        lam = lam * (p - 1) // math.gcd(lam, p - 1)
+    d = pow(e, -1, lam)
+    return MpKey(bits=bits, n=n, e=e, d=d, primes=primes, exps=[d % (p - 1) for p in primes])
+
+
 def _make_key_args(args):
     return make_key(*args).to_json()
 

@@ -99,3 +99,54 @@ def test_plan_validate_errors():
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(RuntimeError):
         binding.load_library(str(tmp_path / "libpmk.so"))
+
+
+# ---------- multi-prime keys (host-side checks) -----------------------------------------
+
+@pytest.fixture(scope="module")
+def mp_keys():
+    return [inputs.make_mp_key(3072, 57, 0), inputs.make_mp_key(4096, 57, 1)]
+
+
+def test_mp_keys_satisfy_the_rsa_identity(mp_keys):
+    """Generated multi-prime keys: N = product of the primes, e d = 1 modulo
+    every p_i - 1, so (m^e)^d = m mod N (Sec. 1.1 correctness)."""
+    for k in mp_keys:
+        n = 1
+        for p, d in zip(k.primes, k.exps):
+            n *= p
+            assert p.bit_length() == 1024 and (k.e * d) % (p - 1) == 1
+        assert n == k.n and n.bit_length() == k.bits
+        m = 0x1234567 ** 40 % k.n
+        assert pow(pow(m, k.e, k.n), k.d, k.n) == m
+
+
+def test_mp_key_check_accepts_generated_keys(mp_keys):
+    for k in mp_keys:
+        assert binding.pmk_mp_key_check(k) == (binding.PMK_OK, "")
+
+
+def _mp_mut(k, **kw):
+    d = dict(k.__dict__)
+    d.update(kw)
+    return inputs.MpKey(**d)
+
+
+def test_mp_key_check_rejects_bad_material(mp_keys):
+    k = mp_keys[0]
+    p0, p1, p2 = k.primes
+    small = (1 << 1023) - 1  # odd, 1023 bits
+    bad = {
+        "bits": _mp_mut(k, bits=5120),
+        "bits vs nprimes": _mp_mut(k, bits=4096),
+        "nprimes": _mp_mut(k, primes=[p0, p1], exps=k.exps[:2]),
+        "product": _mp_mut(k, n=k.n + 2),
+        "prime size": _mp_mut(k, primes=[small, p1, p2], n=small * p1 * p2 | (1 << 3071)),
+        "repeated prime": _mp_mut(k, primes=[p0, p0, p2], n=p0 * p0 * p2),
+        "d_i >= p_i": _mp_mut(k, exps=[p0, k.exps[1], k.exps[2]]),
+        "even n": _mp_mut(k, n=k.n - 1),
+    }
+    for what, key in bad.items():
+        rc, msg = binding.pmk_mp_key_check(key)
+        assert rc == binding.PMK_EINVAL, what
+        assert msg, what
