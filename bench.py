@@ -247,6 +247,67 @@ def paper_table(steps: int, warmup: int):
     return rows
 
 
+def mp_products(bits: int) -> int:
+    """Canonical word products of one multi-prime CRT decryption (bits/1024
+    primes of 1024 bits): per prime one exponentiation by a 1024-bit exponent
+    (the 2048-bit key's half count) plus the reduction of the input's remaining
+    pieces, then the recombination's b(b-1)/2 products modulo the primes."""
+    b = bits // 1024
+    return b * (half_products(2048) + (b - 2) * mm_products(32)) + b * (b - 1) // 2 * mm_products(32)
+
+
+def multi_prime_measure(steps: int, warmup: int, mib: int = 64):
+    """Multi-prime CRT decryption (Sec. 2.1: b primes of bits/b bits) against
+    two-prime CRT decryption of the same ciphertext under keys of the same
+    size, both through their synchronous one-shot entry points (plan, run,
+    check, free), wall-clocked per call.  Ciphertext: seeded random blocks
+    below 2^(bits-8), device-resident; 4 keys per size, chunk i under key i mod 4."""
+    import numpy as np
+    import torch
+
+    from paper_2111_11924_amd import binding, inputs
+
+    rows = []
+    for bits in (3072, 4096):
+        mp_keys = [inputs.make_mp_key(bits, 77, i) for i in range(4)]
+        two = inputs.make_keys([bits] * 4, 77)
+        msg_len = mib << 20
+        km = inputs.round_robin_map(msg_len, [bits] * 4)
+        kb = bits // 8
+        g = np.random.Generator(np.random.PCG64([77, bits]))
+        ct = g.integers(0, 256, size=len(km) * kb, dtype=np.uint8)
+        ct.reshape(-1, kb)[:, 0] = 0
+        d_ct = torch.from_numpy(ct).to("cuda")
+        d_mp = torch.empty(msg_len, dtype=torch.uint8, device="cuda")
+        d_2p = torch.empty(msg_len, dtype=torch.uint8, device="cuda")
+        ctx = binding.Context(0)
+        ctx.load_mp_keys(mp_keys)
+        ctx.load_keys(two)
+        calls = {
+            "multi_prime": lambda: binding.pmk_mp_decrypt(ctx.handle, d_ct, len(ct), km, d_mp, msg_len),
+            "two_prime": lambda: binding.pmk_decrypt(ctx.handle, d_ct, len(ct), km, d_2p, msg_len),
+        }
+        row = {"bits": bits, "primes": bits // 1024, "keys": 4, "message_bytes": msg_len, "chunks": len(km)}
+        ok = True
+        for name, fn in calls.items():
+            for _ in range(warmup):
+                ok &= fn() == binding.PMK_OK
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ok &= fn() == binding.PMK_OK
+            torch.cuda.synchronize()
+            row[name + "_ms"] = (time.perf_counter() - t0) / steps * 1e3
+            row[name + "_chunks_per_s"] = len(km) / row[name + "_ms"] * 1e3
+        row["speedup"] = row["two_prime_ms"] / row["multi_prime_ms"]
+        row["model_speedup"] = (bits // 1024) ** 2 / 4
+        row["mp_mad_frac_wall"] = len(km) * mp_products(bits) / (row["multi_prime_ms"] / 1e3) / PEAK_MAD_PER_S
+        row["ok"] = bool(ok)
+        rows.append(row)
+        ctx.close()
+    return rows
+
+
 def keygen_measure(bits: int, count: int, rounds: int, seed: int = 950):
     """Key generation with the GPU primality tests (sieve + Miller-Rabin) against
     the host's own search (inputs.gen_prime: numpy sieve + Python pow) on a
@@ -288,6 +349,8 @@ def main() -> int:
                     help="the paper's per-size experiment: 100 KB under 16 keys of 2048..8192 bits")
     ap.add_argument("--keygen", action="store_true",
                     help="key generation with the GPU primality tests (2048-bit keys)")
+    ap.add_argument("--multi-prime", action="store_true",
+                    help="multi-prime CRT decryption (3072/3 and 4096/4 primes) against two-prime CRT")
     ap.add_argument("--serve", action="store_true",
                     help="serving workload only: capacity, then Poisson loads 0.5/0.8/1.2 of it")
     ap.add_argument("--serve-requests", type=int, default=0,
@@ -334,6 +397,15 @@ def main() -> int:
                     "higher_is_better": True, "config": {"workload": "keygen-2048b"}})
         print(json.dumps(res))
         return 0 if res["keys_ok"] else 1
+
+    if args.multi_prime:
+        rows = multi_prime_measure(args.steps, args.warmup)
+        print(json.dumps({"metric": "multi-prime CRT decryption, chunks per second (one-shot calls)",
+                          "unit": "chunks/s", "n_gpus": 1, "data": "synthetic", "higher_is_better": True,
+                          "value": rows[-1]["multi_prime_chunks_per_s"],
+                          "config": {"workload": "mp-64MiB-4keys", "key_bits": [r["bits"] for r in rows]},
+                          "rows": rows}))
+        return 0 if all(r["ok"] for r in rows) else 1
 
     if args.paper_table:
         rows = paper_table(args.steps, args.warmup)
