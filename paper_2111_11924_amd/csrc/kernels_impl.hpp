@@ -300,9 +300,9 @@ PMK_DEV void encrypt_unit(const ClassRun r, uint32_t tile, uint32_t *tbl) {
 // Job tile jt = 2 t + h works on tile t's chunks modulo p (h = 0) or q (h = 1).
 // Reduction and entry into Montgomery form at once:
 // x~ = MM(c_lo, R^2) + MM(c_hi, R^3) = c R mod p (below 4p), with
-// c = c_hi 2^(LB NL) + c_lo.  Table T[k] = x~^k (T[0] = R mod p), then
-// fixed windows of r.win bits from the top: win squarings and one multiply by
-// T[digit].
+// c = c_hi 2^(LB NL) + c_lo.  The one-lane form exponentiates with sliding
+// windows of at most r.win bits (table of the odd powers x~^(2j+1)); the
+// lane-group form with fixed windows (table T[k] = x~^k, T[0] = R mod p).
 PMK_DEV uint32_t digit_of(const uint32_t *d, int SH, int k, int w) {
     const int pos = k * w;
     const int wd = pos >> 5, sh = pos & 31;
@@ -311,12 +311,47 @@ PMK_DEV uint32_t digit_of(const uint32_t *d, int SH, int k, int w) {
     return (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & ((1u << w) - 1u);
 }
 
+// Bits of a wave-uniform exponent of SH words (scalar registers and branches).
+PMK_DEV uint32_t exp_bit(const uint32_t *d, int k) { return (uni(d[k >> 5]) >> (k & 31)) & 1u; }
+// bits [l, l + len) of d, len <= 32
+PMK_DEV uint32_t exp_bits(const uint32_t *d, int SH, int l, int len) {
+    const int wd = l >> 5, sh = l & 31;
+    const uint32_t lo = uni(d[wd]);
+    const uint32_t hi = (wd + 1) < SH ? uni(d[wd + 1]) : 0u;
+    return (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & (uint32_t)((1ull << len) - 1u);
+}
+PMK_DEV int exp_top_bit(const uint32_t *d, int SH) {  // index of the highest set bit, -1 for d = 0
+    for (int k = SH - 1; k >= 0; --k) {
+        const uint32_t v = uni(d[k]);
+        if (v) return 32 * k + 31 - __builtin_clz(v);
+    }
+    return -1;
+}
+// One step of the left-to-right sliding-window schedule, from bit i down: the
+// zero bits above the next set bit j, then the window [l, j] of at most w bits
+// that ends in a set bit at l.  The step squares nsq = (i - j) + (j - l + 1)
+// times, then multiplies by the odd power x^v (table index v >> 1), v = d[l..j].
+// Without a set bit left (j < 0) it squares i + 1 times and has no product.
+struct WinStep {
+    int nsq;
+    uint32_t idx;
+    bool mul;
+    int next;  // bit where the following step starts (l - 1)
+};
+PMK_DEV WinStep win_step(const uint32_t *d, int SH, int i, int w) {
+    int j = i;
+    while (j >= 0 && !exp_bit(d, j)) --j;
+    if (j < 0) return WinStep{i + 1, 0u, false, -1};
+    int l = j - w + 1 > 0 ? j - w + 1 : 0;
+    while (!exp_bit(d, l)) ++l;
+    return WinStep{i - l + 1, exp_bits(d, SH, l, j - l + 1) >> 1, true, l - 1};
+}
+
 template <int CB>
 PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t *lds) {
     constexpr Geom G = make_geom(CB);
     constexpr int NL = G.nlh, LB = G.lbh, S = G.S, SH = G.SH;
-    const int win = r.win, T = 1 << win;
-    const int NW = (32 * SH + win - 1) / win;  // digits of the exponent
+    const int win = r.win;
     const int lane = threadIdx.x;
     const uint32_t tile = jt >> 1;
     const int h = jt & 1;
@@ -327,6 +362,7 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t 
     const uint32_t n0 = uni(hr[G.h_m0]);
     const uint32_t *dexp = hr + (r.exp_sel ? G.h_d2 : G.h_d);
     const uint32_t *one_h = hr + G.h_one;
+    const int TH = 1 << (win - 1);  // odd powers x~, x~^3, ..., x~^(2 TH - 1)
 
     uint32_t acc[NL], b[NL];
     if constexpr (S <= 64) {
@@ -371,22 +407,30 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t 
 
     // One call site each for the product and the square keeps the loop's
     // code within the instruction cache.  Phases:
-    //   0  MM(c_lo, R^2) = c_lo R mod p            (parked in T[1])
-    //   1  MM(c_hi, R^3) = c_hi R^2 mod p; x~ = sum (below 4p), T[1] = x~
-    //   2  T[e] = T[e-1] x~ for e = 2 .. T-1
-    //   3  per digit below the top one: win squarings (while T[digit] is
-    //      copied into LDS), then times T[digit]
+    //   0  MM(c_lo, R^2) = c_lo R mod p            (parked in entry 1)
+    //   1  MM(c_hi, R^3) = c_hi R^2 mod p; x~ = sum (below 4p) -> entry 0
+    //   2  x~^2 (the step between odd powers)
+    //   5  entry e = x~^(2e+1) = entry e-1 times x~^2, e = 1 .. TH-1
+    //   3  per window step: its squarings (while the step's odd power is
+    //      copied into LDS), then times that power
     //   4  MM(., 1): leave Montgomery form
-    int phase = 0, e = 2, digit = NW - 2, sq = 0;
+    int phase = 0, e = 1, sq = 0;
+    WinStep st{0, 0u, false, -1};
     for (;;) {
         if (phase == 3) {
-            if (sq < win) {
-                if (sq == 0) prefetch_row4<NL>(lds, tbl, digit_of(dexp, SH, digit, win), lane);
+            if (sq < st.nsq) {
+                if (sq == 0 && st.mul) prefetch_row4<NL>(lds, tbl, st.idx, lane);
                 mont_sqr<NL, LB>(acc, acc, n, n0);
                 ++sq;
                 continue;
             }
-            take_row4(b, lds, lane);
+            if (st.mul) {
+                take_row4(b, lds, lane);
+            } else {  // trailing zero bits done
+#pragma unroll
+                for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
+                phase = 4;
+            }
         }
         mont_mul<NL, LB>(acc, acc, b, n, n0);
         if (phase == 4) break;
@@ -396,8 +440,8 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t 
             load_limbs(b, hr + G.h_rrr);
             phase = 1;
             // table-building steps leave nothing in flight: the wait the
-            // compiler puts where the digit loop joins them would otherwise
-            // also wait for the digit prefetch
+            // compiler puts where the window loop joins them would otherwise
+            // also wait for the window's prefetch
             __builtin_amdgcn_s_waitcnt(0);
             continue;
         }
@@ -410,32 +454,45 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t 
                 acc[j] = v & Radix<LB>::MASK;
                 c = v >> LB;
             }
-            store_row4(tbl, 1, lane, acc);
+            store_row4(tbl, 0, lane, acc);
 #pragma unroll
-            for (int j = 0; j < NL; ++j) b[j] = acc[j];  // x~, the multiplier of phase 2
+            for (int j = 0; j < NL; ++j) b[j] = acc[j];  // next: x~ x~
             phase = 2;
             __builtin_amdgcn_s_waitcnt(0);
-        } else if (phase == 2) {
+            continue;
+        }
+        if (phase == 2) {
+#pragma unroll
+            for (int j = 0; j < NL; ++j) b[j] = acc[j];  // x~^2, the multiplier of phase 5
+            load_row4(acc, tbl, 0, lane);
+            phase = 5;
+            __builtin_amdgcn_s_waitcnt(0);
+            continue;
+        }
+        if (phase == 5) {
             store_row4(tbl, e, lane, acc);
             ++e;
             __builtin_amdgcn_s_waitcnt(0);
-        } else {  // phase 3: the digit's multiply is done
-            --digit;
-            sq = 0;
-        }
-        if (phase == 2 && e == T) {
-            // table complete: T[0] = R mod p (the Montgomery one), start from the top digit
-            load_limbs(b, one_h);
-            store_row4(tbl, 0, lane, b);
-            load_row4(acc, tbl, digit_of(dexp, SH, NW - 1, win), lane);
+            if (e < TH) continue;
+            // table complete: the first window starts at the top set bit
+            // (no squarings of 1); d = 0 gives the Montgomery one
+            const int top = exp_top_bit(dexp, SH);
+            if (top < 0) {
+                load_limbs(acc, one_h);
+                st = WinStep{0, 0u, false, -1};
+            } else {
+                const WinStep first = win_step(dexp, SH, top, win);
+                load_row4(acc, tbl, first.idx, lane);
+                st = first.next >= 0 ? win_step(dexp, SH, first.next, win) : WinStep{0, 0u, false, -1};
+            }
             __builtin_amdgcn_s_waitcnt(0);
             phase = 3;
+            sq = 0;
+            continue;
         }
-        if (phase == 3 && digit < 0) {
-#pragma unroll
-            for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
-            phase = 4;
-        }
+        // phase 3: the step's product is done
+        st = st.next >= 0 ? win_step(dexp, SH, st.next, win) : WinStep{0, 0u, false, -1};
+        sq = 0;
     }
     canonicalize<NL, LB>(acc, n);
     uint32_t *dst = r.half + ((size_t)jt * NL) * kTile + lane;
