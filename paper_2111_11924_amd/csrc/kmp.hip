@@ -4,7 +4,7 @@
 //   mp_part_kernel    one lane per chunk, one job per (tile, prime): c mod p_i
 //                     and into Montgomery form at once, as the sum of
 //                     MM(c_k, R^(k+2)) over the b radix pieces c_k of c (so
-//                     x~ = c R mod p_i), then the fixed-window exponentiation;
+//                     x~ = c R mod p_i), then the sliding-window exponentiation;
 //   mp_garner_kernel  v_i = (...((m_i - v_0) p_0^-1 - v_1) p_1^-1 ... - v_(i-1)) p_(i-1)^-1
 //                     mod p_i, then Horner's rule over the v_i.
 #include "kernels_impl.hpp"
@@ -20,8 +20,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void mp
     constexpr MpGeom G = make_mp_geom(K);
     constexpr int NL = kMpNL, LB = kMpLB, S = G.S, P = G.parts, SP = kMpSP, PL = pad4(kMpNL);
     constexpr uint32_t MASK = Radix<LB>::MASK;
-    const int lane = threadIdx.x, T = 1 << win;
-    const int NW = (32 * SP + win - 1) / win;
+    const int lane = threadIdx.x;
     uint32_t *tbl = table + (size_t)blockIdx.x * slot_words;
     const uint32_t units = ntiles * P;
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
@@ -46,25 +45,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void mp
             if (cmp >= 0) atomicOr(err, 1u);
         }
         uint32_t acc[NL], b[NL];
-        // pieces: c = sum_k c_k R^k; MM(c_k, R^(k+2)) = c_k R^(k+1) mod p, summed in T[1]
+        // pieces: c = sum_k c_k R^k; MM(c_k, R^(k+2)) = c_k R^(k+1) mod p, summed
+        // (below 2 P p, inside R) into x~ = c R mod p.  Phases: 0 pieces (running
+        // sum parked in entry 1), 1 x~^2, 5 odd powers: entry e = x~^(2e+1),
+        // 2 sliding-window steps (squarings, then times an odd power), 3 MM(., 1)
 #pragma unroll
         for (int j = 0; j < NL; ++j) acc[j] = radix_limb_mem<S, LB>(w, kTile, j);
         load_limbs(b, qr + G.q_rpow);
-        // phases: 0 pieces, 1 table, 2 digits (squarings, then a table product), 3 leave Montgomery form
-        int phase = 0, piece = 0, e = 2, digit = NW - 2, sq = 0;
+        const int TH = 1 << (win - 1);
+        int phase = 0, piece = 0, e = 1, sq = 0;
+        WinStep st{0, 0u, false, -1};
         for (;;) {
             if (phase == 2) {
-                if (sq < win) {
+                if (sq < st.nsq) {
                     mont_sqr<NL, LB>(acc, acc, n, n0);
                     ++sq;
                     continue;
                 }
-                load_entry(b, tbl, digit_of(dexp, SP, digit, win), lane);
+                if (st.mul) {
+                    load_entry(b, tbl, st.idx, lane);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
+                    phase = 3;
+                }
             }
             mont_mul<NL, LB>(acc, acc, b, n, n0);
             if (phase == 3) break;
             if (phase == 0) {
-                if (piece > 0) {  // running sum (below 2 P p, inside R)
+                if (piece > 0) {
                     load_entry(b, tbl, 1, lane);
                     uint32_t c = 0;
 #pragma unroll
@@ -74,35 +83,45 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void mp
                         c = v >> LB;
                     }
                 }
-                store_entry(tbl, 1, lane, acc);
                 if (++piece < P) {
+                    store_entry(tbl, 1, lane, acc);
 #pragma unroll
                     for (int j = 0; j < NL; ++j) acc[j] = radix_limb_mem<S, LB>(w, kTile, piece * NL + j);
                     load_limbs(b, qr + G.q_rpow + piece * PL);
                     continue;
                 }
+                store_entry(tbl, 0, lane, acc);  // x~
 #pragma unroll
-                for (int j = 0; j < NL; ++j) b[j] = acc[j];  // x~, the multiplier of the table
+                for (int j = 0; j < NL; ++j) b[j] = acc[j];
                 phase = 1;
                 continue;
             }
             if (phase == 1) {
+#pragma unroll
+                for (int j = 0; j < NL; ++j) b[j] = acc[j];  // x~^2, the step between odd powers
+                load_entry(acc, tbl, 0, lane);
+                phase = 5;
+                continue;
+            }
+            if (phase == 5) {
                 store_entry(tbl, e, lane, acc);
-                if (++e < T) continue;
-                load_limbs(acc, qr + G.q_one);
-                store_entry(tbl, 0, lane, acc);  // T[0] = R mod p
-                load_entry(acc, tbl, digit_of(dexp, SP, NW - 1, win), lane);
+                if (++e < TH) continue;
+                const int top = exp_top_bit(dexp, SP);
+                if (top < 0) {
+                    load_limbs(acc, qr + G.q_one);
+                    st = WinStep{0, 0u, false, -1};
+                } else {
+                    const WinStep first = win_step(dexp, SP, top, win);
+                    load_entry(acc, tbl, first.idx, lane);
+                    st = first.next >= 0 ? win_step(dexp, SP, first.next, win) : WinStep{0, 0u, false, -1};
+                }
                 phase = 2;
                 sq = 0;
-            } else {  // phase 2: a digit's product is done
-                --digit;
-                sq = 0;
+                continue;
             }
-            if (phase == 2 && digit < 0) {
-#pragma unroll
-                for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
-                phase = 3;
-            }
+            // phase 2: the step's product is done
+            st = st.next >= 0 ? win_step(dexp, SP, st.next, win) : WinStep{0, 0u, false, -1};
+            sq = 0;
         }
         canonicalize<NL, LB>(acc, n);
         uint32_t *dst = parts + ((size_t)(tile * P + part) * NL) * kTile + lane;
@@ -250,7 +269,7 @@ int mp_launch_garner(int k, const uint32_t *keys, const ChunkDesc *desc, uint32_
     return (int)hipGetLastError();
 }
 
-uint64_t mp_slot_words(int win) { return (uint64_t)(1u << win) * kMpNL * kTile; }
+uint64_t mp_slot_words(int win) { return (uint64_t)(1u << (win - 1)) * kMpNL * kTile; }
 
 uint32_t mp_wave_slots(int num_cus) {
     int nb = 0;
