@@ -300,9 +300,8 @@ PMK_DEV void encrypt_unit(const ClassRun r, uint32_t tile, uint32_t *tbl) {
 // Job tile jt = 2 t + h works on tile t's chunks modulo p (h = 0) or q (h = 1).
 // Reduction and entry into Montgomery form at once:
 // x~ = MM(c_lo, R^2) + MM(c_hi, R^3) = c R mod p (below 4p), with
-// c = c_hi 2^(LB NL) + c_lo.  The one-lane form exponentiates with sliding
-// windows of at most r.win bits (table of the odd powers x~^(2j+1)); the
-// lane-group form with fixed windows (table T[k] = x~^k, T[0] = R mod p).
+// c = c_hi 2^(LB NL) + c_lo.  Then sliding windows of at most r.win bits over
+// a table of the odd powers x~^(2j+1), and a last product by 1.
 PMK_DEV uint32_t digit_of(const uint32_t *d, int SH, int k, int w) {
     const int pos = k * w;
     const int wd = pos >> 5, sh = pos & 31;
@@ -333,19 +332,72 @@ PMK_DEV int exp_top_bit(const uint32_t *d, int SH) {  // index of the highest se
 // times, then multiplies by the odd power x^v (table index v >> 1), v = d[l..j].
 // Without a set bit left (j < 0) it squares i + 1 times and has no product.
 struct WinStep {
-    int nsq;
-    uint32_t idx;
-    bool mul;
-    int next;  // bit where the following step starts (l - 1)
+    // packed into one scalar register: nsq in bits 0-12, idx in 13-17, the
+    // product flag in 18, next + 1 in 19-31 (exponents of up to 8191 bits)
+    uint32_t v;
+    PMK_DEV static WinStep make(int nsq, uint32_t idx, bool mul, int next) {
+        return WinStep{(uint32_t)nsq | (idx << 13) | ((uint32_t)mul << 18) | ((uint32_t)(next + 1) << 19)};
+    }
+    PMK_DEV int nsq() const { return (int)(v & 0x1FFFu); }
+    PMK_DEV uint32_t idx() const { return (v >> 13) & 0x1Fu; }
+    PMK_DEV bool mul() const { return (v >> 18) & 1u; }
+    PMK_DEV int next() const { return (int)(v >> 19) - 1; }
 };
 PMK_DEV WinStep win_step(const uint32_t *d, int SH, int i, int w) {
     int j = i;
     while (j >= 0 && !exp_bit(d, j)) --j;
-    if (j < 0) return WinStep{i + 1, 0u, false, -1};
+    if (j < 0) return WinStep::make(i + 1, 0u, false, -1);
     int l = j - w + 1 > 0 ? j - w + 1 : 0;
     while (!exp_bit(d, l)) ++l;
-    return WinStep{i - l + 1, exp_bits(d, SH, l, j - l + 1) >> 1, true, l - 1};
+    return WinStep::make(i - l + 1, exp_bits(d, SH, l, j - l + 1) >> 1, true, l - 1);
 }
+
+// The three exponent words that end at bit i (words below bit 0 read as 0).
+// Plain loads, issued one step ahead: nothing waits for them until the next
+// step is planned, so their latency hides behind the current step's squarings.
+struct ExpWords {
+    uint32_t w0, w1, w2;
+};
+PMK_DEV ExpWords exp_words(const uint32_t *d, int i) {
+    const int k = i >> 5;
+    return ExpWords{k >= 2 ? d[k - 2] : 0u, k >= 1 ? d[k - 1] : 0u, d[k]};
+}
+// win_step from the 64 bits [i - 63, i] of preloaded words; bit by bit from
+// memory when the zero run or the window reaches below them
+PMK_DEV WinStep win_step_words(const uint32_t *d, int SH, int i, int w, ExpWords x) {
+    const int sh = 31 - (i & 31);  // puts bit i at bit 63
+    const uint64_t top = ((uint64_t)uni(x.w2) << 32) | uni(x.w1);
+    const uint64_t v = sh ? (top << sh) | (uni(x.w0) >> (32 - sh)) : top;
+    if (v == 0) return i < 64 ? WinStep::make(i + 1, 0u, false, -1) : win_step(d, SH, i, w);
+    const int z = __builtin_clzll(v);
+    if (z > 64 - w) return win_step(d, SH, i, w);
+    const int j = i - z;                        // next set bit
+    const int len = j - w + 1 >= 0 ? w : j + 1;  // window [j - len + 1, j]
+    uint32_t val = (uint32_t)((v << z) >> (64 - len));
+    const int tz = __builtin_ctz(val);
+    val >>= tz;
+    const int l = j - len + 1 + tz;
+    return WinStep::make(i - l + 1, val >> 1, true, l - 1);
+}
+// the step after st, and the loads for the one after that
+PMK_DEV void win_advance(WinStep &st, ExpWords &nx, const uint32_t *d, int SH, int w) {
+    st = st.next() >= 0 ? win_step_words(d, SH, st.next(), w, nx) : WinStep::make(0, 0u, false, -1);
+    if (st.next() >= 0) nx = exp_words(d, st.next());
+}
+// the first window (it starts at the top set bit top >= 0), with the loads for the step after it
+PMK_DEV WinStep win_first(ExpWords &nx, const uint32_t *d, int SH, int top, int w) {
+    const WinStep first = win_step(d, SH, top, w);
+    if (first.next() >= 0) nx = exp_words(d, first.next());
+    return first;
+}
+
+// Sliding windows (odd-power table, 2^(w-1) entries) where they measured
+// faster: the one-lane classes up to 2048 bits (three waves per SIMD) and the
+// lane-group classes; the 3072/4096-bit one-lane halves (two waves per SIMD)
+// measured 6 % slower and 0 % faster with them and keep fixed windows (2^w
+// entries, T[0] = R mod p).
+template <int CB>
+constexpr bool kSlidingHalves = lanes_half(CB) > 1 || make_geom(CB).nlh <= 40;
 
 template <int CB>
 PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t *lds) {
@@ -362,7 +414,6 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t 
     const uint32_t n0 = uni(hr[G.h_m0]);
     const uint32_t *dexp = hr + (r.exp_sel ? G.h_d2 : G.h_d);
     const uint32_t *one_h = hr + G.h_one;
-    const int TH = 1 << (win - 1);  // odd powers x~, x~^3, ..., x~^(2 TH - 1)
 
     uint32_t acc[NL], b[NL];
     if constexpr (S <= 64) {
@@ -405,94 +456,170 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t 
     }
     load_limbs(b, hr + G.h_rr);
 
-    // One call site each for the product and the square keeps the loop's
-    // code within the instruction cache.  Phases:
-    //   0  MM(c_lo, R^2) = c_lo R mod p            (parked in entry 1)
-    //   1  MM(c_hi, R^3) = c_hi R^2 mod p; x~ = sum (below 4p) -> entry 0
-    //   2  x~^2 (the step between odd powers)
-    //   5  entry e = x~^(2e+1) = entry e-1 times x~^2, e = 1 .. TH-1
-    //   3  per window step: its squarings (while the step's odd power is
-    //      copied into LDS), then times that power
-    //   4  MM(., 1): leave Montgomery form
-    int phase = 0, e = 1, sq = 0;
-    WinStep st{0, 0u, false, -1};
-    for (;;) {
-        if (phase == 3) {
-            if (sq < st.nsq) {
-                if (sq == 0 && st.mul) prefetch_row4<NL>(lds, tbl, st.idx, lane);
-                mont_sqr<NL, LB>(acc, acc, n, n0);
-                ++sq;
+    if constexpr (kSlidingHalves<CB>) {
+        const int TH = 1 << (win - 1);  // odd powers x~, x~^3, ..., x~^(2 TH - 1)
+        // One call site each for the product and the square keeps the loop's
+        // code within the instruction cache.  Phases:
+        //   0  MM(c_lo, R^2) = c_lo R mod p            (parked in entry 1)
+        //   1  MM(c_hi, R^3) = c_hi R^2 mod p; x~ = sum (below 4p) -> entry 0
+        //   2  x~^2 (the step between odd powers)
+        //   5  entry e = x~^(2e+1) = entry e-1 times x~^2, e = 1 .. TH-1
+        //   3  per window step: its squarings (while the step's odd power is
+        //      copied into LDS), then times that power
+        //   4  MM(., 1): leave Montgomery form
+        int phase = 0, e = 1, sq = 0;
+        WinStep st = WinStep::make(0, 0u, false, -1);
+        ExpWords nx{0u, 0u, 0u};
+        for (;;) {
+            if (phase == 3) {
+                if (sq < st.nsq()) {
+                    if (sq == 0 && st.mul()) prefetch_row4<NL>(lds, tbl, st.idx(), lane);
+                    mont_sqr<NL, LB>(acc, acc, n, n0);
+                    ++sq;
+                    continue;
+                }
+                if (st.mul()) {
+                    take_row4(b, lds, lane);
+                } else {  // trailing zero bits done
+#pragma unroll
+                    for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
+                    phase = 4;
+                }
+            }
+            mont_mul<NL, LB>(acc, acc, b, n, n0);
+            if (phase == 4) break;
+            if (phase == 0) {
+                store_row4(tbl, 1, lane, acc);
+                load_row4(acc, tbl, 0, lane);
+                load_limbs(b, hr + G.h_rrr);
+                phase = 1;
+                // table-building steps leave nothing in flight: the wait the
+                // compiler puts where the window loop joins them would otherwise
+                // also wait for the window's prefetch
+                __builtin_amdgcn_s_waitcnt(0);
                 continue;
             }
-            if (st.mul) {
+            if (phase == 1) {
+                load_row4(b, tbl, 1, lane);
+                uint32_t c = 0;
+#pragma unroll
+                for (int j = 0; j < NL; ++j) {
+                    const uint32_t v = acc[j] + b[j] + c;
+                    acc[j] = v & Radix<LB>::MASK;
+                    c = v >> LB;
+                }
+                store_row4(tbl, 0, lane, acc);
+#pragma unroll
+                for (int j = 0; j < NL; ++j) b[j] = acc[j];  // next: x~ x~
+                phase = 2;
+                __builtin_amdgcn_s_waitcnt(0);
+                continue;
+            }
+            if (phase == 2) {
+#pragma unroll
+                for (int j = 0; j < NL; ++j) b[j] = acc[j];  // x~^2, the multiplier of phase 5
+                load_row4(acc, tbl, 0, lane);
+                phase = 5;
+                __builtin_amdgcn_s_waitcnt(0);
+                continue;
+            }
+            if (phase == 5) {
+                store_row4(tbl, e, lane, acc);
+                ++e;
+                __builtin_amdgcn_s_waitcnt(0);
+                if (e < TH) continue;
+                // table complete: the first window starts at the top set bit
+                // (no squarings of 1); d = 0 gives the Montgomery one
+                const int top = exp_top_bit(dexp, SH);
+                if (top < 0) {
+                    load_limbs(acc, one_h);
+                    st = WinStep::make(0, 0u, false, -1);
+                } else {
+                    st = win_first(nx, dexp, SH, top, win);
+                    load_row4(acc, tbl, st.idx(), lane);
+                    win_advance(st, nx, dexp, SH, win);
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+                phase = 3;
+                sq = 0;
+                continue;
+            }
+            // phase 3: the step's product is done
+            win_advance(st, nx, dexp, SH, win);
+            sq = 0;
+        }
+    } else {
+        // fixed windows of win bits from the top: T[k] = x~^k (T[0] = R mod p)
+        const int T = 1 << win;
+        const int NW = (32 * SH + win - 1) / win;  // digits of the exponent
+        // One call site each for the product and the square keeps the loop's
+        // code within the instruction cache.  Phases:
+        //   0  MM(c_lo, R^2) = c_lo R mod p            (parked in T[1])
+        //   1  MM(c_hi, R^3) = c_hi R^2 mod p; x~ = sum (below 4p), T[1] = x~
+        //   2  T[e] = T[e-1] x~ for e = 2 .. T-1
+        //   3  per digit below the top one: win squarings (while T[digit] is
+        //      copied into LDS), then times T[digit]
+        //   4  MM(., 1): leave Montgomery form
+        int phase = 0, e = 2, digit = NW - 2, sq = 0;
+        for (;;) {
+            if (phase == 3) {
+                if (sq < win) {
+                    if (sq == 0) prefetch_row4<NL>(lds, tbl, digit_of(dexp, SH, digit, win), lane);
+                    mont_sqr<NL, LB>(acc, acc, n, n0);
+                    ++sq;
+                    continue;
+                }
                 take_row4(b, lds, lane);
-            } else {  // trailing zero bits done
+            }
+            mont_mul<NL, LB>(acc, acc, b, n, n0);
+            if (phase == 4) break;
+            if (phase == 0) {
+                store_row4(tbl, 1, lane, acc);
+                load_row4(acc, tbl, 0, lane);
+                load_limbs(b, hr + G.h_rrr);
+                phase = 1;
+                // table-building steps leave nothing in flight: the wait the
+                // compiler puts where the digit loop joins them would otherwise
+                // also wait for the digit prefetch
+                __builtin_amdgcn_s_waitcnt(0);
+                continue;
+            }
+            if (phase == 1) {
+                load_row4(b, tbl, 1, lane);
+                uint32_t c = 0;
+#pragma unroll
+                for (int j = 0; j < NL; ++j) {
+                    const uint32_t v = acc[j] + b[j] + c;
+                    acc[j] = v & Radix<LB>::MASK;
+                    c = v >> LB;
+                }
+                store_row4(tbl, 1, lane, acc);
+#pragma unroll
+                for (int j = 0; j < NL; ++j) b[j] = acc[j];  // x~, the multiplier of phase 2
+                phase = 2;
+                __builtin_amdgcn_s_waitcnt(0);
+            } else if (phase == 2) {
+                store_row4(tbl, e, lane, acc);
+                ++e;
+                __builtin_amdgcn_s_waitcnt(0);
+            } else {  // phase 3: the digit's multiply is done
+                --digit;
+                sq = 0;
+            }
+            if (phase == 2 && e == T) {
+                // table complete: T[0] = R mod p (the Montgomery one), start from the top digit
+                load_limbs(b, one_h);
+                store_row4(tbl, 0, lane, b);
+                load_row4(acc, tbl, digit_of(dexp, SH, NW - 1, win), lane);
+                __builtin_amdgcn_s_waitcnt(0);
+                phase = 3;
+            }
+            if (phase == 3 && digit < 0) {
 #pragma unroll
                 for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
                 phase = 4;
             }
         }
-        mont_mul<NL, LB>(acc, acc, b, n, n0);
-        if (phase == 4) break;
-        if (phase == 0) {
-            store_row4(tbl, 1, lane, acc);
-            load_row4(acc, tbl, 0, lane);
-            load_limbs(b, hr + G.h_rrr);
-            phase = 1;
-            // table-building steps leave nothing in flight: the wait the
-            // compiler puts where the window loop joins them would otherwise
-            // also wait for the window's prefetch
-            __builtin_amdgcn_s_waitcnt(0);
-            continue;
-        }
-        if (phase == 1) {
-            load_row4(b, tbl, 1, lane);
-            uint32_t c = 0;
-#pragma unroll
-            for (int j = 0; j < NL; ++j) {
-                const uint32_t v = acc[j] + b[j] + c;
-                acc[j] = v & Radix<LB>::MASK;
-                c = v >> LB;
-            }
-            store_row4(tbl, 0, lane, acc);
-#pragma unroll
-            for (int j = 0; j < NL; ++j) b[j] = acc[j];  // next: x~ x~
-            phase = 2;
-            __builtin_amdgcn_s_waitcnt(0);
-            continue;
-        }
-        if (phase == 2) {
-#pragma unroll
-            for (int j = 0; j < NL; ++j) b[j] = acc[j];  // x~^2, the multiplier of phase 5
-            load_row4(acc, tbl, 0, lane);
-            phase = 5;
-            __builtin_amdgcn_s_waitcnt(0);
-            continue;
-        }
-        if (phase == 5) {
-            store_row4(tbl, e, lane, acc);
-            ++e;
-            __builtin_amdgcn_s_waitcnt(0);
-            if (e < TH) continue;
-            // table complete: the first window starts at the top set bit
-            // (no squarings of 1); d = 0 gives the Montgomery one
-            const int top = exp_top_bit(dexp, SH);
-            if (top < 0) {
-                load_limbs(acc, one_h);
-                st = WinStep{0, 0u, false, -1};
-            } else {
-                const WinStep first = win_step(dexp, SH, top, win);
-                load_row4(acc, tbl, first.idx, lane);
-                st = first.next >= 0 ? win_step(dexp, SH, first.next, win) : WinStep{0, 0u, false, -1};
-            }
-            __builtin_amdgcn_s_waitcnt(0);
-            phase = 3;
-            sq = 0;
-            continue;
-        }
-        // phase 3: the step's product is done
-        st = st.next >= 0 ? win_step(dexp, SH, st.next, win) : WinStep{0, 0u, false, -1};
-        sq = 0;
     }
     canonicalize<NL, LB>(acc, n);
     uint32_t *dst = r.half + ((size_t)jt * NL) * kTile + lane;
@@ -642,8 +769,7 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
     constexpr Geom G = make_geom(CB);
     constexpr int L = lanes_half(CB), NLT = G.nlh, K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
     constexpr int NG = 64 / L;  // groups (chunks) per wavefront
-    const int win = r.win, T = 1 << win;
-    const int NW = (32 * SH + win - 1) / win;
+    const int win = r.win, TH = 1 << (win - 1);  // odd powers x~, x~^3, ..., x~^(2 TH - 1)
     const uint32_t jt = u / L, tile = jt >> 1;
     const int h = (int)(jt & 1), part = (int)(u % L);
     const int lane = threadIdx.x, pos = lane % L, grp = lane / L;
@@ -673,9 +799,12 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
     limbs_from_words<K, LB>(acc, col, NG, S, pos * K);        // c_lo
     stage_mem<K>(col, NG, pos, hr + G.h_rr + pos * K, 1);
 
-    // phases as in halves_unit: 0 c_lo R, 1 c_hi R^2 and x~, 2 table,
-    // 3 digits (squarings, then a table product), 4 leave Montgomery form
-    int phase = 0, e = 2, digit = NW - 2, sq = 0;
+    // phases as in halves_unit: 0 c_lo R, 1 c_hi R^2 and x~ (entry 0), 2 x~^2,
+    // 5 odd powers (entry e = x~^(2e+1)), 3 sliding-window steps (squarings,
+    // then a table product), 4 leave Montgomery form
+    int phase = 0, e = 1, sq = 0;
+    WinStep st = WinStep::make(0, 0u, false, -1);
+    ExpWords nx{0u, 0u, 0u};
     for (;;) {
         mont_mul_lanes<NLT, LB, L>(acc, acc, col, NG, n, n0, pos);
         if (phase == 4) break;
@@ -687,7 +816,7 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
             continue;
         }
         if (phase == 1) {
-            // x~ = acc + T[1]: limb-wise, carries across the group's lanes
+            // x~ = acc + entry 1: limb-wise, carries across the group's lanes
             uint32_t lo[K];
             load_entry(lo, tbl, 1, lane);
             uint32_t cy = 0;
@@ -708,38 +837,46 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
                 }
                 cy = cin;
             }
-            store_entry(tbl, 1, lane, acc);
-            stage_limbs(col, NG, pos, acc);  // x~ stays staged for the table
+            store_entry(tbl, 0, lane, acc);
+            stage_limbs(col, NG, pos, acc);  // next: x~ x~
             phase = 2;
             continue;
         }
         if (phase == 2) {
+            stage_limbs(col, NG, pos, acc);  // x~^2, the step between odd powers
+            load_entry(acc, tbl, 0, lane);
+            phase = 5;
+            continue;
+        }
+        if (phase == 5) {
             store_entry(tbl, e, lane, acc);
-            if (++e < T) continue;
-            const uint32_t dg = digit_of(dexp, SH, NW - 1, win);
-            if (dg)
-                load_entry(acc, tbl, dg, lane);
-            else
+            if (++e < TH) continue;
+            // table complete: the first window starts at the top set bit
+            const int top = exp_top_bit(dexp, SH);
+            if (top < 0) {
                 load_limbs(acc, fresh_v(hr + G.h_one + pos * K));
+                st = WinStep::make(0, 0u, false, -1);
+            } else {
+                st = win_first(nx, dexp, SH, top, win);
+                load_entry(acc, tbl, st.idx(), lane);
+                win_advance(st, nx, dexp, SH, win);
+            }
             phase = 3;
-        } else if (sq == win + 1) {  // phase 3: a digit's product is done
-            --digit;
+            sq = 0;
+        } else if (sq > st.nsq()) {  // phase 3: the step's product is done
+            win_advance(st, nx, dexp, SH, win);
             sq = 0;
         }
-        // phase 3: next squaring, the digit's product, or the end
-        if (digit < 0) {
-            stage_one<K>(col, NG, pos);
-            phase = 4;
-        } else if (sq < win) {
+        // phase 3: next squaring, the step's product, or the end
+        if (sq < st.nsq()) {
             stage_limbs(col, NG, pos, acc);
             ++sq;
+        } else if (st.mul()) {
+            stage_mem<K>(col, NG, pos, fresh(tbl) + (size_t)st.idx() * K * kTile + lane, kTile);
+            sq = st.nsq() + 1;
         } else {
-            const uint32_t dg = digit_of(dexp, SH, digit, win);
-            if (dg)
-                stage_mem<K>(col, NG, pos, fresh(tbl) + (size_t)dg * K * kTile + lane, kTile);
-            else
-                stage_mem<K>(col, NG, pos, hr + G.h_one + pos * K, 1);
-            sq = win + 1;
+            stage_one<K>(col, NG, pos);
+            phase = 4;
         }
     }
     canonicalize_lanes<K, LB, L>(acc, n, pos);

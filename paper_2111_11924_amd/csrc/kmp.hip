@@ -54,16 +54,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void mp
         load_limbs(b, qr + G.q_rpow);
         const int TH = 1 << (win - 1);
         int phase = 0, piece = 0, e = 1, sq = 0;
-        WinStep st{0, 0u, false, -1};
+        WinStep st = WinStep::make(0, 0u, false, -1);
+        ExpWords nx{0u, 0u, 0u};
         for (;;) {
             if (phase == 2) {
-                if (sq < st.nsq) {
+                if (sq < st.nsq()) {
                     mont_sqr<NL, LB>(acc, acc, n, n0);
                     ++sq;
                     continue;
                 }
-                if (st.mul) {
-                    load_entry(b, tbl, st.idx, lane);
+                if (st.mul()) {
+                    load_entry(b, tbl, st.idx(), lane);
                 } else {
 #pragma unroll
                     for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
@@ -109,18 +110,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void mp
                 const int top = exp_top_bit(dexp, SP);
                 if (top < 0) {
                     load_limbs(acc, qr + G.q_one);
-                    st = WinStep{0, 0u, false, -1};
+                    st = WinStep::make(0, 0u, false, -1);
                 } else {
-                    const WinStep first = win_step(dexp, SP, top, win);
-                    load_entry(acc, tbl, first.idx, lane);
-                    st = first.next >= 0 ? win_step(dexp, SP, first.next, win) : WinStep{0, 0u, false, -1};
+                    st = win_first(nx, dexp, SP, top, win);
+                    load_entry(acc, tbl, st.idx(), lane);
+                    win_advance(st, nx, dexp, SP, win);
                 }
                 phase = 2;
                 sq = 0;
                 continue;
             }
             // phase 2: the step's product is done
-            st = st.next >= 0 ? win_step(dexp, SP, st.next, win) : WinStep{0, 0u, false, -1};
+            win_advance(st, nx, dexp, SP, win);
             sq = 0;
         }
         canonicalize<NL, LB>(acc, n);
