@@ -422,3 +422,59 @@ def test_large_and_small_classes_mixed_batch_and_blinded(torch, ctx):
         off += ln
         ct_off += kb
     assert len(seen) == len(bits)
+
+
+# ---------------------------------------------------------------- exponent shapes
+# The window schedule is read from the private exponents themselves.  Key
+# material with CRT exponents of unusual shape -- zero, one, a single bit, zero
+# runs longer than the 64 exponent bits a step reads ahead, a set bit only at
+# the top -- is still a valid input to the CRT route (m = C^d' mod N with
+# d' = dp mod p-1, dq mod q-1), so the GPU must match the oracle's CRT route
+# bit for bit on every block, and the blinded form (exponent p-1-dp) likewise.
+
+def _special_exponents(h):
+    return [
+        (0, 1),
+        (1, 3),
+        (1 << (h - 2), (1 << (h - 2)) | 1),
+        ((1 << (h - 2)) | 1, (1 << 200) | (1 << 130) | 5),
+        ((0b101101 << (h - 8)) | (1 << 65) | 1, (1 << 63) | (1 << 64)),
+        ((1 << (h - 3)) - 1, 7 << 70),
+    ]
+
+
+@pytest.mark.parametrize("bits", [1024, 2048, 3072, 6144])
+def test_unusual_crt_exponents(torch, ctx, bits):
+    base = inputs.make_keys([bits], 850 + bits // 64)[0]
+    h = bits // 2
+    keys = []
+    for dp, dq in _special_exponents(h):
+        d = dict(base.__dict__)
+        d.update(dp=dp % base.p, dq=dq % base.q)
+        keys.append(inputs.RsaKey(**d))
+    kb = bits // 8
+    per_key = 70  # a full tile and a ragged one per key
+    km = np.repeat(np.arange(len(keys), dtype=np.uint32), per_key)
+    g = np.random.Generator(np.random.PCG64([851, bits]))
+    ct = g.integers(0, 256, size=len(km) * kb, dtype=np.uint8)
+    ct.reshape(-1, kb)[:, 0] = 0  # every block below N
+    msg_len = len(km) * (kb - 4)
+    print(f"[gpu] unusual CRT exponents, {bits} bits, {len(km)} blocks", flush=True)
+    ctx.load_keys(keys)
+    plan = ctx.plan(km, msg_len)
+    T = oracle.KeyTable(keys)
+    try:
+        d_pt = plan.decrypt(dev(torch, ct))
+        assert plan.check() == binding.PMK_OK
+        pt = host(d_pt, msg_len)
+        # every block up to 2048 bits; above, sampled blocks of every key
+        # (first, second, last of the full tile, the ragged tile's first and last)
+        rows = range(len(km)) if bits <= 2048 else \
+            [k * per_key + j for k in range(len(keys)) for j in (0, 1, 63, 64, per_key - 1)]
+        for i in rows:
+            c = int.from_bytes(bytes(ct[i * kb:(i + 1) * kb]), "big")
+            m = oracle.rsa_int(T, int(km[i]), "crt", c) % (1 << (8 * (kb - 4)))
+            got = int.from_bytes(bytes(pt[i * (kb - 4):(i + 1) * (kb - 4)]), "big")
+            assert got == m, f"block {i} (key {km[i]})"
+    finally:
+        plan.close()
