@@ -627,6 +627,188 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t 
     for (int j = 0; j < NL; ++j) dst[(size_t)j * kTile] = acc[j];
 }
 
+// ------------------------------------------------------------------ blinded halves, one pass
+// Blinded decryption (Sec. 3.1): per prime, (c*)^d_p (c_R^d_p)^-1 = (c*)^d_p c_R^(p-1-d_p)
+// mod p.  Both powers in one chain (interleaved sliding windows, Moller 2001): one
+// squaring per exponent bit for both exponents, and a product by the odd power of c* or
+// c_R wherever a window of d_p or of p-1-d_p ends; two odd-power tables.  Against two
+// separate exponentiations this drops one of the two squaring chains.  c* comes from
+// r.x32, c_R from r.fin32; the result goes to r.half like a CRT half.  A c_R divisible
+// by the prime sets bit 1 of r.err.
+template <int CB>
+PMK_DEV void halves_joint_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t *lds) {
+    constexpr Geom G = make_geom(CB);
+    constexpr int NL = G.nlh, LB = G.lbh, S = G.S, SH = G.SH;
+    constexpr uint32_t MASK = Radix<LB>::MASK;
+    const int win = r.win, TH = 1 << (win - 1);  // T1 = entries [0, TH), T2 = [TH, 2 TH)
+    const int lane = threadIdx.x;
+    const uint32_t tile = jt >> 1;
+    const int h = jt & 1;
+    const uint32_t *kr = r.keys + (size_t)uni(r.tile_key[tile]) * G.stride;  // wave-uniform
+    const uint32_t *hr = kr + G.off_half[0] + h * G.h_size;
+    uint32_t n[NL];
+    load_uniform(n, hr + G.h_m);
+    const uint32_t n0 = uni(hr[G.h_m0]);
+    const uint32_t *d1 = hr + G.h_d, *d2 = hr + G.h_d2;
+    const uint32_t *w1 = fresh_v(r.x32 + (size_t)tile * S * kTile + lane);
+    const uint32_t *w2 = fresh_v(r.fin32 + (size_t)tile * S * kTile + lane);
+    if (h == 0 && r.desc[(size_t)tile * kTile + lane].msg_len) {
+        // both blocks must lie in Z_N: compare with N, most significant word first
+        const uint32_t *n32 = kr + G.off_n32;
+        int cmp1 = 0, cmp2 = 0;
+#pragma unroll 1
+        for (int k = S - 1; k >= 0 && (cmp1 == 0 || cmp2 == 0); --k) {
+            const uint32_t y = n32[k], a = w1[(size_t)k * kTile], b = w2[(size_t)k * kTile];
+            if (cmp1 == 0) cmp1 = (a > y) - (a < y);
+            if (cmp2 == 0) cmp2 = (b > y) - (b < y);
+        }
+        if (cmp1 >= 0 || cmp2 >= 0) atomicOr(r.err, 1u);
+    }
+    uint32_t acc[NL], b[NL];
+    // c*_hi parked in entry 0, c*_lo first
+#pragma unroll
+    for (int j = 0; j < NL; ++j) acc[j] = radix_limb_mem<S, LB>(w1, kTile, j + NL);
+    store_row4(tbl, 0, lane, acc);
+#pragma unroll
+    for (int j = 0; j < NL; ++j) acc[j] = radix_limb_mem<S, LB>(w1, kTile, j);
+    load_limbs(b, hr + G.h_rr);
+    // Phases, for input k = 0 (c*, table base 0) then k = 1 (c_R, table base TH):
+    //   0 MM(lo, R^2) parked in base+1; 1 MM(hi, R^3) + parked = x~ -> entry base;
+    //   2 x~^2; 3 odd powers base+e; 4 (c_R only) MM(x~, 1) = c_R mod p for the
+    //   divisibility check; then 5 the joint chain: squarings down to the next
+    //   window end, products by the odd powers ending there; 6 MM(., 1).
+    int phase = 0, k = 0, e = 1, sq = 0, nsq = 0, pos = 0;
+    uint32_t pend = 0;  // bit 0: a product by T1 at this event, bit 1: by T2
+    WinStep s1 = WinStep::make(0, 0u, false, -1), s2 = s1;
+    ExpWords nx1{0u, 0u, 0u}, nx2{0u, 0u, 0u};
+    for (;;) {
+        if (phase == 5) {
+            if (sq < nsq) {
+                if (sq == 0 && pend) prefetch_row4<NL>(lds, tbl, (pend & 1u) ? s1.idx() : TH + s2.idx(), lane);
+                mont_sqr<NL, LB>(acc, acc, n, n0);
+                ++sq;
+                continue;
+            }
+            if (!pend) {  // squarings below the last window done
+#pragma unroll
+                for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
+                phase = 6;
+            } else if (sq == nsq) {  // the event's first product: its entry is in LDS
+                take_row4(b, lds, lane);
+                sq = nsq + 1;
+            } else {  // windows of both exponents end here: the T2 product, from memory
+                load_row4(b, tbl, TH + s2.idx(), lane);
+                __builtin_amdgcn_s_waitcnt(0);
+                sq = nsq + 2;
+            }
+        }
+        mont_mul<NL, LB>(acc, acc, b, n, n0);
+        if (phase == 6) break;
+        const int base = k * TH;
+        if (phase == 0) {
+            store_row4(tbl, base + 1, lane, acc);
+            load_row4(acc, tbl, base, lane);
+            load_limbs(b, hr + G.h_rrr);
+            phase = 1;
+            __builtin_amdgcn_s_waitcnt(0);
+            continue;
+        }
+        if (phase == 1) {
+            load_row4(b, tbl, base + 1, lane);
+            uint32_t c = 0;
+#pragma unroll
+            for (int j = 0; j < NL; ++j) {
+                const uint32_t v = acc[j] + b[j] + c;
+                acc[j] = v & MASK;
+                c = v >> LB;
+            }
+            store_row4(tbl, base, lane, acc);
+            if (k == 1) {
+#pragma unroll
+                for (int j = 0; j < NL; ++j) b[j] = j == 0 ? 1u : 0u;
+                phase = 4;
+            } else {
+#pragma unroll
+                for (int j = 0; j < NL; ++j) b[j] = acc[j];  // next: x~ x~
+                phase = 2;
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            continue;
+        }
+        if (phase == 4) {
+            // acc = c_R mod p in [0, p]: zero or p means p divides c_R
+            uint32_t z = 0, q = 0;
+#pragma unroll
+            for (int j = 0; j < NL; ++j) {
+                z |= acc[j];
+                q |= acc[j] ^ n[j];
+            }
+            if ((z == 0 || q == 0) && r.desc[(size_t)tile * kTile + lane].msg_len) atomicOr(r.err, 2u);
+            load_row4(acc, tbl, base, lane);
+#pragma unroll
+            for (int j = 0; j < NL; ++j) b[j] = acc[j];  // next: x~ x~
+            phase = 2;
+            __builtin_amdgcn_s_waitcnt(0);
+            continue;
+        }
+        if (phase == 2) {
+#pragma unroll
+            for (int j = 0; j < NL; ++j) b[j] = acc[j];  // x~^2, the step between odd powers
+            load_row4(acc, tbl, base, lane);
+            phase = 3;
+            e = 1;
+            __builtin_amdgcn_s_waitcnt(0);
+            continue;
+        }
+        if (phase == 3) {
+            store_row4(tbl, base + e, lane, acc);
+            ++e;
+            __builtin_amdgcn_s_waitcnt(0);
+            if (e < TH) continue;
+            if (k == 0) {  // c_R next: its hi part parked in entry TH, lo first
+                k = 1;
+                // an opaque copy of the base: the limb addresses are formed here,
+                // not hoisted out of the loop into registers
+                const uint32_t *wc = fresh_v(w2);
+#pragma unroll
+                for (int j = 0; j < NL; ++j) acc[j] = radix_limb_mem<S, LB>(wc, kTile, j + NL);
+                store_row4(tbl, TH, lane, acc);
+                wc = fresh_v(wc);
+#pragma unroll
+                for (int j = 0; j < NL; ++j) acc[j] = radix_limb_mem<S, LB>(wc, kTile, j);
+                load_limbs(b, hr + G.h_rr);
+                phase = 0;
+                __builtin_amdgcn_s_waitcnt(0);
+                continue;
+            }
+            // tables complete: the chain starts from the Montgomery one above the
+            // higher of the two top bits
+            load_limbs(acc, hr + G.h_one);
+            const int t1 = exp_top_bit(d1, SH), t2 = exp_top_bit(d2, SH);
+            if (t1 >= 0) s1 = win_first(nx1, d1, SH, t1, win);
+            if (t2 >= 0) s2 = win_first(nx2, d2, SH, t2, win);
+            pos = (t1 > t2 ? t1 : t2) + 1;
+            phase = 5;
+        } else if (sq == nsq + 1 && pend == 3u) {
+            continue;  // phase 5: the T1 product is done, the T2 product of the same event follows
+        } else {  // phase 5: the event's products are done
+            if (pend & 1u) win_advance(s1, nx1, d1, SH, win);
+            if (pend & 2u) win_advance(s2, nx2, d2, SH, win);
+        }
+        // next event: the higher window end still pending (window [l, ...], l = next + 1)
+        const int l1 = s1.mul() ? s1.next() + 1 : -1, l2 = s2.mul() ? s2.next() + 1 : -1;
+        const int ev = l1 > l2 ? l1 : l2;
+        pend = ev < 0 ? 0u : (l1 == ev ? 1u : 0u) | (l2 == ev ? 2u : 0u);
+        nsq = pos - (ev < 0 ? 0 : ev);  // no window left: square down to bit 0, then MM(., 1)
+        pos = ev < 0 ? 0 : ev;
+        sq = 0;
+    }
+    canonicalize<NL, LB>(acc, n);
+    uint32_t *dst = r.half + ((size_t)jt * NL) * kTile + lane;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) dst[(size_t)j * kTile] = acc[j];
+}
+
 // ------------------------------------------------------------------ lane groups
 // 3072- and 4096-bit classes: a number is spread over a group of L lanes, lane
 // `pos` holding limbs [pos K, pos K + K).  The multiplier of every product is
@@ -903,6 +1085,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kEncWaves<CB
     } else {
         for (uint32_t u = blockIdx.x; u < r.ntiles; u += gridDim.x) encrypt_unit<CB>(r, u, tbl);
     }
+}
+
+// blinded decryption in one pass (one-lane classes with sliding windows); two
+// waves per SIMD: the second table's state does not fit the three-wave budget
+template <int CB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void halves_joint_kernel(
+    ClassRun r, uint64_t slot_words) {
+    uint32_t *tbl = r.table + (size_t)blockIdx.x * slot_words;
+    __shared__ uint32_t lds[lds_words_dec<CB>()];
+    const uint32_t units = 2 * r.ntiles;
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) halves_joint_unit<CB>(r, u, tbl, lds);
 }
 
 template <int CB>

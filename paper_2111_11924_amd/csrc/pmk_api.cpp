@@ -420,8 +420,30 @@ int pmk_decrypt_blinded_plan(pmk_plan *pl, const uint8_t *d_ct_star, const uint8
     int rc = blind_prepare(pl);
     if (rc != PMK_OK) return rc;
     for (int c = 0; c < kNumClasses; ++c) {
+        ClassRun &r = pl->runs[c];
+        if (!r.ntiles || !joint_class(c)) continue;
+        // the one-pass form keeps two odd-power tables per slot
+        const hipError_t te = regrow(pl, &r.table, pl->table_cap[c], 2 * r.slots_dec * table_words_per_slot(c, 1, r.win));
+        if (te != hipSuccess) return hip_err(ctx, te, "window table allocation");
+    }
+    for (int c = 0; c < kNumClasses; ++c) {
         const ClassRun &r = pl->runs[c];
         if (!r.ntiles) continue;
+        if (joint_class(c)) {  // (c*)^d_p c_R^(p-1-d_p) in one chain per prime
+            ClassRun rj = r;
+            rj.fin32 = pl->x32b[c];
+            int e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(r, d_ct_star, 1, stream); });
+            if (!e) {
+                ClassRun rr = r;
+                rr.x32 = pl->x32b[c];
+                e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(rr, d_ct_r, 1, stream); });
+            }
+            if (!e) e = timed_launch(pl, PMK_KERNEL_CRT_HALVES, stream, [&] { return launch_decrypt_joint(rj, stream); });
+            if (!e) e = timed_launch(pl, PMK_KERNEL_GARNER, stream, [&] { return launch_garner(r, stream); });
+            if (!e) e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, d_msg, 1, stream); });
+            if (e) return hip_err(ctx, (hipError_t)e, "blinded decrypt launch");
+            continue;
+        }
         ClassRun rr = r;  // c_R^(p-1-d_p), c_R^(q-1-d_q) into half2
         rr.x32 = pl->x32b[c];
         rr.half = pl->half2[c];

@@ -158,6 +158,11 @@ int launch_decrypt_halves(const ClassRun &r, void *stream);
 int launch_garner(const ClassRun &r, void *stream);
 // blinded decryption: half[h] = half[h] * half2[h] mod p_h for both primes
 int launch_blind_combine(const ClassRun &r, const uint32_t *half2, void *stream);
+// blinded decryption in one pass per prime: half[h] = (c*)^d_h c_R^(p_h-1-d_h) mod p_h
+// with c* at r.x32 and c_R at r.fin32; tables need 2 table_words_per_slot(cls, 1, win)
+// words per slot.  Only where joint_class(cls) holds.
+bool joint_class(int cls);
+int launch_decrypt_joint(const ClassRun &r, void *stream);
 int launch_unpack(const ClassRun &r, uint8_t *dst, int decrypt, void *stream);
 // table words needed per wave slot for a class (decryption: at window width win)
 uint64_t table_words_per_slot(int cls, int decrypt, int win);
