@@ -478,3 +478,46 @@ def test_unusual_crt_exponents(torch, ctx, bits):
             assert got == m, f"block {i} (key {km[i]})"
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("bits", [1024, 2048, 3072])
+def test_blinded_decryption_with_unusual_exponents(torch, ctx, bits):
+    """Blinded decryption (one chain for c* and c_R up to 2048 bits, two passes
+    above) with private exponents of unusual shape: d below both primes, so
+    dp = dq = d keeps the shape, and the second exponent p-1-d is dense.
+    Against the oracle's blinded route m = (c*)^d (c_R^d)^-1 mod N."""
+    base = inputs.make_keys([bits], 850 + bits // 64)[0]
+    h = bits // 2
+    exps = [1, 3, (1 << 70) + 5, (1 << (h - 3)) - 1, (1 << (h - 2)) | 1, (1 << 100) | (1 << 37)]
+    keys = []
+    for d in exps:
+        assert d < base.q - 1 and d < base.p - 1
+        f = dict(base.__dict__)
+        f.update(d=d, dp=d, dq=d)
+        keys.append(inputs.RsaKey(**f))
+    kb = bits // 8
+    per_key = 66
+    km = np.repeat(np.arange(len(keys), dtype=np.uint32), per_key)
+    g = np.random.Generator(np.random.PCG64([852, bits]))
+    cs = g.integers(0, 256, size=len(km) * kb, dtype=np.uint8)
+    cr = g.integers(0, 256, size=len(km) * kb, dtype=np.uint8)
+    cs.reshape(-1, kb)[:, 0] = 0
+    cr.reshape(-1, kb)[:, 0] = 0
+    msg_len = len(km) * (kb - 4)
+    print(f"[gpu] blinded decryption, unusual exponents, {bits} bits, {len(km)} blocks", flush=True)
+    ctx.load_keys(keys)
+    plan = ctx.plan(km, msg_len)
+    T = oracle.KeyTable(keys)
+    try:
+        d_pt = plan.decrypt_blinded(dev(torch, cs), dev(torch, cr))
+        assert plan.check() == binding.PMK_OK
+        pt = host(d_pt, msg_len)
+        rows = [k * per_key + j for k in range(len(keys)) for j in (0, 1, 63, 64, per_key - 1)]
+        for i in rows:
+            c1 = int.from_bytes(bytes(cs[i * kb:(i + 1) * kb]), "big")
+            c2 = int.from_bytes(bytes(cr[i * kb:(i + 1) * kb]), "big")
+            m, _ = oracle.blind_int(T, int(km[i]), "dec", c1, c2)
+            got = int.from_bytes(bytes(pt[i * (kb - 4):(i + 1) * (kb - 4)]), "big")
+            assert got == m % (1 << (8 * (kb - 4))), f"block {i} (key {km[i]})"
+    finally:
+        plan.close()
