@@ -12,8 +12,6 @@ namespace pmk {
     int launch_halves_##B(const ClassRun &, hipStream_t);                                  \
     int launch_garner_##B(const ClassRun &, hipStream_t);                                  \
     int launch_blind_combine_##B(const ClassRun &, const uint32_t *, hipStream_t);         \
-    int launch_joint_##B(const ClassRun &, hipStream_t);                                   \
-    bool joint_ok_##B();                                                                   \
     uint32_t wave_slots_##B(int, int);                                                     \
     uint64_t slot_words_##B(int, int);
 PMK_DECLARE(128)
@@ -63,25 +61,6 @@ int launch_garner(const ClassRun &r, void *stream) {
 int launch_blind_combine(const ClassRun &r, const uint32_t *half2, void *stream) {
     if (r.ntiles == 0) return 0;
     PMK_DISPATCH(r.cls, launch_blind_combine, r, half2, (hipStream_t)stream);
-}
-
-int launch_decrypt_joint(const ClassRun &r, void *stream) {
-    if (r.ntiles == 0) return 0;
-    PMK_DISPATCH(r.cls, launch_joint, r, (hipStream_t)stream);
-}
-bool joint_class(int cls) {
-    switch (cls) {
-        case 0: return joint_ok_128();
-        case 1: return joint_ok_256();
-        case 2: return joint_ok_512();
-        case 3: return joint_ok_1024();
-        case 4: return joint_ok_2048();
-        case 5: return joint_ok_3072();
-        case 6: return joint_ok_4096();
-        case 7: return joint_ok_6144();
-        case 8: return joint_ok_8192();
-        default: return false;
-    }
 }
 
 uint64_t table_words_per_slot(int cls, int decrypt, int win) {

@@ -1,0 +1,54 @@
+// Blinded decryption in one pass per prime (halves_joint_kernel) for the
+// one-lane size classes with sliding windows (128- to 2048-bit keys).  A
+// translation unit of its own, so the per-class objects stay as they are.
+#include "kernels_impl.hpp"
+
+namespace pmk {
+
+namespace {
+
+template <int CB>
+int launch_joint_class(const ClassRun &r, hipStream_t s) {
+    static_assert(lanes_half(CB) == 1 && kSlidingHalves<CB>, "one-lane sliding-window classes only");
+    // resident blocks on this device; never more than the r.slots_dec table slots
+    // (those of the CRT-halves kernel, which is at least as occupied and capped by
+    // the same unit count)
+    static const int oj = [] {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)halves_joint_kernel<CB>, 64, 0) !=
+                hipSuccess ||
+            nb < 1)
+            nb = 1;
+        return nb;
+    }();
+    int dev = 0, ncu = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        ncu = 1;
+    const uint64_t resident = (uint64_t)oj * (uint64_t)ncu;
+    const uint32_t units = 2 * r.ntiles;
+    uint64_t grid = units < resident ? units : resident;
+    if (grid > r.slots_dec) grid = r.slots_dec;
+    const uint64_t slot = 2 * table_words_per_slot(r.cls, 1, r.win);  // two odd-power tables
+    hipLaunchKernelGGL(halves_joint_kernel<CB>, dim3((uint32_t)grid), dim3(64), 0, s, r, slot);
+    return (int)hipGetLastError();
+}
+
+}  // namespace
+
+bool joint_class(int cls) { return cls >= 0 && cls <= 4; }  // 128 .. 2048 bits
+
+int launch_decrypt_joint(const ClassRun &r, void *stream) {
+    if (r.ntiles == 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    switch (r.cls) {
+        case 0: return launch_joint_class<128>(r, s);
+        case 1: return launch_joint_class<256>(r, s);
+        case 2: return launch_joint_class<512>(r, s);
+        case 3: return launch_joint_class<1024>(r, s);
+        case 4: return launch_joint_class<2048>(r, s);
+        default: return (int)hipErrorNotSupported;
+    }
+}
+
+}  // namespace pmk
