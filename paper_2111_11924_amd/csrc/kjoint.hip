@@ -9,7 +9,7 @@ namespace {
 
 template <int CB>
 int launch_joint_class(const ClassRun &r, hipStream_t s) {
-    static_assert(lanes_half(CB) == 1 && kSlidingHalves<CB>, "one-lane sliding-window classes only");
+    static_assert(lanes_half(CB) == 1, "one-lane classes only");
     // resident blocks on this device; never more than the r.slots_dec table slots
     // (those of the CRT-halves kernel, which is at least as occupied and capped by
     // the same unit count)
@@ -36,7 +36,7 @@ int launch_joint_class(const ClassRun &r, hipStream_t s) {
 
 }  // namespace
 
-bool joint_class(int cls) { return cls >= 0 && cls <= 4; }  // 128 .. 2048 bits
+bool joint_class(int cls) { return cls >= 0 && cls <= 5; }  // 128 .. 3072 bits
 
 int launch_decrypt_joint(const ClassRun &r, void *stream) {
     if (r.ntiles == 0) return 0;
@@ -47,6 +47,7 @@ int launch_decrypt_joint(const ClassRun &r, void *stream) {
         case 2: return launch_joint_class<512>(r, s);
         case 3: return launch_joint_class<1024>(r, s);
         case 4: return launch_joint_class<2048>(r, s);
+        case 5: return launch_joint_class<3072>(r, s);
         default: return (int)hipErrorNotSupported;
     }
 }
