@@ -36,7 +36,7 @@ int launch_joint_class(const ClassRun &r, hipStream_t s) {
 
 }  // namespace
 
-bool joint_class(int cls) { return cls >= 0 && cls <= 5; }  // 128 .. 3072 bits
+bool joint_class(int cls) { return cls >= 0 && cls <= 6; }  // 128 .. 4096 bits
 
 int launch_decrypt_joint(const ClassRun &r, void *stream) {
     if (r.ntiles == 0) return 0;
@@ -48,6 +48,7 @@ int launch_decrypt_joint(const ClassRun &r, void *stream) {
         case 3: return launch_joint_class<1024>(r, s);
         case 4: return launch_joint_class<2048>(r, s);
         case 5: return launch_joint_class<3072>(r, s);
+        case 6: return launch_joint_class<4096>(r, s);
         default: return (int)hipErrorNotSupported;
     }
 }
