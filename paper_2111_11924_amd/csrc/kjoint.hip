@@ -1,6 +1,6 @@
 // Blinded decryption in one pass per prime (halves_joint_kernel) for the
-// one-lane size classes with sliding windows (128- to 2048-bit keys).  A
-// translation unit of its own, so the per-class objects stay as they are.
+// one-lane size classes (128- to 4096-bit keys).  A translation unit of its
+// own, so the per-class objects stay as they are.
 #include "kernels_impl.hpp"
 
 namespace pmk {
