@@ -1087,8 +1087,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kEncWaves<CB
     }
 }
 
-// blinded decryption in one pass (one-lane classes with sliding windows); two
-// waves per SIMD: the second table's state does not fit the three-wave budget
+// blinded decryption in one pass (one-lane classes; the chain uses sliding
+// windows whatever the class's plain decryption uses); two waves per SIMD: the
+// second table's state does not fit the three-wave budget
 template <int CB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void halves_joint_kernel(
     ClassRun r, uint64_t slot_words) {
