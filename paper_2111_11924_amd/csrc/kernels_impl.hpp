@@ -1067,6 +1067,179 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
     for (int j = 0; j < K; ++j) dst[(size_t)j * kTile] = acc[j];
 }
 
+// Blinded decryption in one pass per prime for the lane-group classes (CRT
+// halves spread over L lanes): the chain of halves_joint_unit, with each
+// product's multiplier staged in LDS as in halves_lanes_unit.
+template <int CB>
+PMK_DEV void halves_lanes_joint_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint32_t *lds) {
+    constexpr Geom G = make_geom(CB);
+    constexpr int L = lanes_half(CB), NLT = G.nlh, K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
+    constexpr int NG = 64 / L;  // groups (chunks) per wavefront
+    const int win = r.win, TH = 1 << (win - 1);  // T1 = entries [0, TH), T2 = [TH, 2 TH)
+    const uint32_t jt = u / L, tile = jt >> 1;
+    const int h = (int)(jt & 1), part = (int)(u % L);
+    const int lane = threadIdx.x, pos = lane % L, grp = lane / L;
+    const int c = part * NG + grp;  // chunk within the tile
+    uint32_t *col = lds + grp;
+    const uint32_t *kr = r.keys + (size_t)uni(r.tile_key[tile]) * G.stride;
+    const uint32_t *hr = kr + G.off_half[0] + h * G.h_size;
+    uint32_t n[K];
+    load_limbs(n, fresh_v(hr + G.h_m + pos * K));
+    const uint32_t n0 = uni(hr[G.h_m0]);
+    const uint32_t *d1 = hr + G.h_d, *d2 = hr + G.h_d2;
+    const bool live = r.desc[(size_t)tile * kTile + c].msg_len != 0;
+    uint32_t acc[K];
+    // input x (c* or c_R): words staged in the group's LDS column, range check,
+    // hi part parked in entry `base`, lo part in acc, R^2 staged as the multiplier
+    auto take_input = [&](const uint32_t *x32, int base) {
+        for (int k = pos; k < S; k += L) col[k * NG] = x32[((size_t)tile * S + k) * kTile + c];
+        if (h == 0 && pos == 0 && live) {
+            const uint32_t *n32 = kr + G.off_n32;
+            int cmp = 0;
+            for (int k = S - 1; k >= 0 && cmp == 0; --k) {
+                const uint32_t w = col[k * NG];
+                cmp = (w > n32[k]) - (w < n32[k]);
+            }
+            if (cmp >= 0) atomicOr(r.err, 1u);
+        }
+        limbs_from_words<K, LB>(acc, col, NG, S, NLT + pos * K);
+        store_entry(tbl, base, lane, acc);
+        limbs_from_words<K, LB>(acc, col, NG, S, pos * K);
+        stage_mem<K>(col, NG, pos, hr + G.h_rr + pos * K, 1);
+    };
+    take_input(r.x32, 0);
+    // phases as in halves_joint_unit: 0 lo R, 1 hi R^2 and x~ (entry base),
+    // 4 (c_R) MM(x~, 1) for the divisibility check, 2 x~^2, 3 odd powers, 5 the
+    // joint chain, 6 MM(., 1)
+    int phase = 0, k = 0, e = 1, sq = 0, nsq = 0, at = 0;
+    uint32_t pend = 0;
+    WinStep s1 = WinStep::make(0, 0u, false, -1), s2 = s1;
+    ExpWords nx1{0u, 0u, 0u}, nx2{0u, 0u, 0u};
+    for (;;) {
+        mont_mul_lanes<NLT, LB, L>(acc, acc, col, NG, n, n0, pos);
+        if (phase == 6) break;
+        const int base = k * TH;
+        if (phase == 0) {
+            store_entry(tbl, base + 1, lane, acc);
+            load_entry(acc, tbl, base, lane);
+            stage_mem<K>(col, NG, pos, hr + G.h_rrr + pos * K, 1);
+            phase = 1;
+            continue;
+        }
+        if (phase == 1) {
+            // x~ = acc + entry base+1: limb-wise, carries across the group's lanes
+            uint32_t lo[K];
+            load_entry(lo, tbl, base + 1, lane);
+            uint32_t cy = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const uint32_t v = acc[j] + lo[j] + cy;
+                acc[j] = v & Radix<LB>::MASK;
+                cy = v >> LB;
+            }
+#pragma unroll
+            for (int s = 1; s < L; ++s) {
+                uint32_t cin = grp_prev<L>(cy, pos);
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const uint32_t v = acc[j] + cin;
+                    acc[j] = v & Radix<LB>::MASK;
+                    cin = v >> LB;
+                }
+                cy = cin;
+            }
+            store_entry(tbl, base, lane, acc);
+            if (k == 1) {
+                stage_one<K>(col, NG, pos);
+                phase = 4;
+            } else {
+                stage_limbs(col, NG, pos, acc);  // next: x~ x~
+                phase = 2;
+            }
+            continue;
+        }
+        if (phase == 4) {
+            // acc = c_R mod p in [0, p], over the group: zero or p means p divides c_R
+            uint32_t z = 0, q = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                z |= acc[j];
+                q |= acc[j] ^ n[j];
+            }
+#pragma unroll
+            for (int off = 1; off < L; off <<= 1) {
+                z |= (uint32_t)__shfl_xor((int)z, off, 64);
+                q |= (uint32_t)__shfl_xor((int)q, off, 64);
+            }
+            if ((z == 0 || q == 0) && pos == 0 && live) atomicOr(r.err, 2u);
+            load_entry(acc, tbl, base, lane);
+            stage_limbs(col, NG, pos, acc);  // next: x~ x~
+            phase = 2;
+            continue;
+        }
+        if (phase == 2) {
+            stage_limbs(col, NG, pos, acc);  // x~^2, the step between odd powers
+            load_entry(acc, tbl, base, lane);
+            phase = 3;
+            e = 1;
+            continue;
+        }
+        bool plan = false;
+        if (phase == 3) {
+            store_entry(tbl, base + e, lane, acc);
+            if (++e < TH) continue;
+            if (k == 0) {  // c_R next
+                k = 1;
+                take_input(r.fin32, TH);
+                phase = 0;
+                continue;
+            }
+            // tables complete: the chain starts from the Montgomery one above the
+            // higher of the two top bits
+            load_limbs(acc, fresh_v(hr + G.h_one + pos * K));
+            const int t1 = exp_top_bit(d1, SH), t2 = exp_top_bit(d2, SH);
+            if (t1 >= 0) s1 = win_first(nx1, d1, SH, t1, win);
+            if (t2 >= 0) s2 = win_first(nx2, d2, SH, t2, win);
+            at = (t1 > t2 ? t1 : t2) + 1;
+            phase = 5;
+            plan = true;
+        } else if (sq > nsq) {  // phase 5: a product of the event is done
+            if (sq == nsq + 1 && pend == 3u) {  // windows of both exponents end here: T2 next
+                stage_mem<K>(col, NG, pos, fresh(tbl) + (size_t)(TH + s2.idx()) * K * kTile + lane, kTile);
+                sq = nsq + 2;
+                continue;
+            }
+            if (pend & 1u) win_advance(s1, nx1, d1, SH, win);
+            if (pend & 2u) win_advance(s2, nx2, d2, SH, win);
+            plan = true;
+        }
+        if (plan) {  // next event: the higher window end still pending (l = next + 1)
+            const int l1 = s1.mul() ? s1.next() + 1 : -1, l2 = s2.mul() ? s2.next() + 1 : -1;
+            const int ev = l1 > l2 ? l1 : l2;
+            pend = ev < 0 ? 0u : (l1 == ev ? 1u : 0u) | (l2 == ev ? 2u : 0u);
+            nsq = at - (ev < 0 ? 0 : ev);
+            at = ev < 0 ? 0 : ev;
+            sq = 0;
+        }
+        // phase 5: the next squaring, the event's first product, or the end
+        if (sq < nsq) {
+            stage_limbs(col, NG, pos, acc);
+            ++sq;
+        } else if (!pend) {
+            stage_one<K>(col, NG, pos);
+            phase = 6;
+        } else {
+            const uint32_t ent = (pend & 1u) ? s1.idx() : TH + s2.idx();
+            stage_mem<K>(col, NG, pos, fresh(tbl) + (size_t)ent * K * kTile + lane, kTile);
+            sq = nsq + 1;
+        }
+    }
+    canonicalize_lanes<K, LB, L>(acc, n, pos);
+    uint32_t *dst = r.half + ((size_t)(2 * tile + h) * NLT + pos * K) * kTile + c;
+#pragma unroll
+    for (int j = 0; j < K; ++j) dst[(size_t)j * kTile] = acc[j];
+}
+
 // ------------------------------------------------------------------ per-class kernels
 // Persistent grids: block b owns table slot b and walks units b, b + grid, ...
 template <int CB>
@@ -1087,16 +1260,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kEncWaves<CB
     }
 }
 
-// blinded decryption in one pass (one-lane classes; the chain uses sliding
-// windows whatever the class's plain decryption uses); two waves per SIMD: the
-// second table's state does not fit the three-wave budget
+// blinded decryption in one pass (every class: one lane per number up to 4096
+// bits, lane groups above; the chain uses sliding windows whatever the class's
+// plain decryption uses); two waves per SIMD: the second table's state does not
+// fit the three-wave budget
 template <int CB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void halves_joint_kernel(
     ClassRun r, uint64_t slot_words) {
     uint32_t *tbl = r.table + (size_t)blockIdx.x * slot_words;
     __shared__ uint32_t lds[lds_words_dec<CB>()];
-    const uint32_t units = 2 * r.ntiles;
-    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) halves_joint_unit<CB>(r, u, tbl, lds);
+    const uint32_t units = 2 * r.ntiles * lanes_half(CB);
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        if constexpr (lanes_half(CB) > 1)
+            halves_lanes_joint_unit<CB>(r, u, tbl, lds);
+        else
+            halves_joint_unit<CB>(r, u, tbl, lds);
+    }
 }
 
 template <int CB>

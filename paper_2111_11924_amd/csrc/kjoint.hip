@@ -1,6 +1,6 @@
-// Blinded decryption in one pass per prime (halves_joint_kernel) for the
-// one-lane size classes (128- to 4096-bit keys).  A translation unit of its
-// own, so the per-class objects stay as they are.
+// Blinded decryption in one pass per prime (halves_joint_kernel) for every
+// size class.  A translation unit of its own, so the per-class objects stay as
+// they are.
 #include "kernels_impl.hpp"
 
 namespace pmk {
@@ -9,7 +9,6 @@ namespace {
 
 template <int CB>
 int launch_joint_class(const ClassRun &r, hipStream_t s) {
-    static_assert(lanes_half(CB) == 1, "one-lane classes only");
     // resident blocks on this device; never more than the r.slots_dec table slots
     // (those of the CRT-halves kernel, which is at least as occupied and capped by
     // the same unit count)
@@ -26,7 +25,7 @@ int launch_joint_class(const ClassRun &r, hipStream_t s) {
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
         ncu = 1;
     const uint64_t resident = (uint64_t)oj * (uint64_t)ncu;
-    const uint32_t units = 2 * r.ntiles;
+    const uint32_t units = 2 * r.ntiles * lanes_half(CB);
     uint64_t grid = units < resident ? units : resident;
     if (grid > r.slots_dec) grid = r.slots_dec;
     const uint64_t slot = 2 * table_words_per_slot(r.cls, 1, r.win);  // two odd-power tables
@@ -36,7 +35,7 @@ int launch_joint_class(const ClassRun &r, hipStream_t s) {
 
 }  // namespace
 
-bool joint_class(int cls) { return cls >= 0 && cls <= 6; }  // 128 .. 4096 bits
+bool joint_class(int cls) { return cls >= 0 && cls < kNumClasses; }
 
 int launch_decrypt_joint(const ClassRun &r, void *stream) {
     if (r.ntiles == 0) return 0;
@@ -49,6 +48,8 @@ int launch_decrypt_joint(const ClassRun &r, void *stream) {
         case 4: return launch_joint_class<2048>(r, s);
         case 5: return launch_joint_class<3072>(r, s);
         case 6: return launch_joint_class<4096>(r, s);
+        case 7: return launch_joint_class<6144>(r, s);
+        case 8: return launch_joint_class<8192>(r, s);
         default: return (int)hipErrorNotSupported;
     }
 }
