@@ -162,7 +162,7 @@ int pmk_decrypt_plan(pmk_plan *plan, const uint8_t *d_ct, uint8_t *d_msg, void *
  * bytes each, same block layout).  Decryption computes
  * m_i = (c*_i)^d (c_R,i^d)^-1 mod N, i.e. r'_i = c_R,i^d = r_i is divided out,
  * through CRT: per prime, (c*)^(d_p) times c_R^(p-1-d_p) (Fermat's inverse;
- * up to 4096-bit keys both powers in one squaring chain), then Garner.  A c* or c_R block not below N sets PMK_ERANGE, a c_R divisible
+ * both powers in one squaring chain), then Garner.  A c* or c_R block not below N sets PMK_ERANGE, a c_R divisible
  * by p or q sets PMK_EBLIND (both from pmk_plan_check).  Asynchronous on
  * `stream`; every buffer device memory, 4-byte aligned.
  */
