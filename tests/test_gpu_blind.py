@@ -47,6 +47,7 @@ def chunk_spans(keys, km, msg_len):
 
 @pytest.mark.parametrize("bits,nbytes,samples", [
     ([512, 1024, 256], 64 * 3 * 60 + 11, 24),   # several tiles per class, ragged
+    ([128, 192], 64 * 3 * 12 + 5, 24),          # the two smallest classes (192 bits runs in the 256-bit one)
     ([2048, 2048], 140 * 252 + 5, 12),
     ([3072, 4096, 1536], 40 * 400 + 3, 6),      # lane-group classes and a non-class size
 ])
