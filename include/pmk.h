@@ -301,7 +301,9 @@ uint32_t pmk_mp_key_count(const pmk_ctx *ctx);
  * and Garner's mixed-radix recombination
  * m = v_0 + p_0 (v_1 + p_1 (v_2 + ...)).  d_ct (ct_len bytes) and d_msg
  * (msg_len bytes) are device memory, 4-byte aligned.  Synchronous on
- * `stream`; allocates and frees its scratch.  PMK_EKEY / PMK_ESIZE as
+ * `stream`; its device scratch is a context-held arena, grown when a call
+ * needs more and freed by pmk_destroy (calls on one context must not overlap).
+ * PMK_EKEY / PMK_ESIZE as
  * pmk_plan_create, PMK_ERANGE when a block is not below its modulus (the
  * output is then unspecified).
  */

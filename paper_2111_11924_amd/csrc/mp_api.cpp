@@ -1,6 +1,6 @@
 // C ABI of the multi-prime decryption (declared in include/pmk.h): key table
 // load and the one-shot decryption, pack -> one exponentiation per prime ->
-// Garner -> unpack.
+// Garner -> unpack, in a device arena the context keeps between calls.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -16,23 +16,8 @@ using namespace pmk;
 
 namespace {
 
-// device buffers of one call, freed together once `stream` has drained
-struct Scratch {
-    hipStream_t stream;
-    std::vector<void *> p;
-    template <typename T>
-    hipError_t get(T **out, size_t bytes) {
-        void *v = nullptr;
-        const hipError_t e = hipMalloc(&v, bytes ? bytes : 4);
-        if (e == hipSuccess) p.push_back(v);
-        *out = (T *)v;
-        return e;
-    }
-    ~Scratch() {
-        (void)hipStreamSynchronize(stream);
-        for (void *v : p) (void)hipFree(v);
-    }
-};
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 }  // namespace
 
@@ -128,44 +113,78 @@ int pmk_mp_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uin
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;
     const int win = window_for(1024);
-    Scratch mem{s, {}};
-    uint32_t *d_err = nullptr;
-    hipError_t e = mem.get(&d_err, sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemsetAsync(d_err, 0, sizeof(uint32_t), s);
-    for (int c = 0; c < kMpClasses && e == hipSuccess; ++c) {
+    // one context-held device arena, grown when a call needs more (the call is
+    // synchronous, so nothing still uses the old one): error flag, then per class
+    // descriptors, tile keys, packed input, packed output, prime results, tables
+    struct Part {
+        uint64_t desc, tk, x32, y32, parts, table;
+        uint32_t grid;
+    } at[kMpClasses] = {};
+    uint64_t total = kAlign;  // the error flag
+    for (int c = 0; c < kMpClasses; ++c) {
         const uint64_t ntiles = tkeys[c].size();
         if (!ntiles) continue;
         const MpGeom g = make_mp_geom(c);
         const uint32_t units = (uint32_t)(ntiles * g.parts);
-        const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(mp_wave_slots(ctx->num_cus), units));
-        ChunkDesc *desc = nullptr;
-        uint32_t *tk = nullptr, *x32 = nullptr, *y32 = nullptr, *parts = nullptr, *table = nullptr;
-        e = mem.get(&desc, per[c].size() * sizeof(ChunkDesc));
-        if (e == hipSuccess) e = mem.get(&tk, ntiles * sizeof(uint32_t));
-        if (e == hipSuccess) e = mem.get(&x32, ntiles * g.S * kTile * sizeof(uint32_t));
-        if (e == hipSuccess) e = mem.get(&y32, ntiles * g.S * kTile * sizeof(uint32_t));
-        if (e == hipSuccess) e = mem.get(&parts, ntiles * g.parts * kMpNL * kTile * sizeof(uint32_t));
-        if (e == hipSuccess) e = mem.get(&table, (uint64_t)grid * mp_slot_words(win) * sizeof(uint32_t));
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(desc, per[c].data(), per[c].size() * sizeof(ChunkDesc), hipMemcpyHostToDevice, s);
+        Part &a = at[c];
+        a.grid = std::max<uint32_t>(1, std::min<uint32_t>(mp_wave_slots(ctx->num_cus), units));
+        a.desc = total;
+        total += align_up(per[c].size() * sizeof(ChunkDesc));
+        a.tk = total;
+        total += align_up(ntiles * sizeof(uint32_t));
+        a.x32 = total;
+        total += align_up(ntiles * g.S * kTile * sizeof(uint32_t));
+        a.y32 = total;
+        total += align_up(ntiles * g.S * kTile * sizeof(uint32_t));
+        a.parts = total;
+        total += align_up(ntiles * g.parts * kMpNL * kTile * sizeof(uint32_t));
+        a.table = total;
+        total += align_up((uint64_t)a.grid * mp_slot_words(win) * sizeof(uint32_t));
+    }
+    hipError_t e = hipSuccess;
+    if (total > ctx->mp_scratch_bytes) {
+        if (ctx->mp_scratch) (void)hipFree(ctx->mp_scratch);
+        ctx->mp_scratch = nullptr;
+        ctx->mp_scratch_bytes = 0;
+        e = hipMalloc(&ctx->mp_scratch, total);
+        if (e != hipSuccess) {
+            ctx->mp_scratch = nullptr;
+            return hip_err(ctx, e, "multi-prime scratch allocation");
+        }
+        ctx->mp_scratch_bytes = total;
+    }
+    uint8_t *base = (uint8_t *)ctx->mp_scratch;
+    uint32_t *d_err = (uint32_t *)base;
+    e = hipMemsetAsync(d_err, 0, sizeof(uint32_t), s);
+    for (int c = 0; c < kMpClasses && e == hipSuccess; ++c) {
+        const uint64_t ntiles = tkeys[c].size();
+        if (!ntiles) continue;
+        const Part &a = at[c];
+        ChunkDesc *desc = (ChunkDesc *)(base + a.desc);
+        uint32_t *tk = (uint32_t *)(base + a.tk), *x32 = (uint32_t *)(base + a.x32), *y32 = (uint32_t *)(base + a.y32);
+        uint32_t *parts = (uint32_t *)(base + a.parts), *table = (uint32_t *)(base + a.table);
+        e = hipMemcpyAsync(desc, per[c].data(), per[c].size() * sizeof(ChunkDesc), hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(tk, tkeys[c].data(), ntiles * sizeof(uint32_t), hipMemcpyHostToDevice, s);
         if (e != hipSuccess) break;
         const uint32_t *keys = ctx->d_mp_keys[c];
         int le = mp_launch_pack(c, d_ct, desc, keys, tk, (uint32_t)ntiles, x32, s);
         if (!le)
-            le = mp_launch_parts(c, keys, tk, desc, (uint32_t)ntiles, x32, parts, table, mp_slot_words(win), grid, win,
-                                 d_err, s);
+            le = mp_launch_parts(c, keys, tk, desc, (uint32_t)ntiles, x32, parts, table, mp_slot_words(win), a.grid,
+                                 win, d_err, s);
         if (!le) le = mp_launch_garner(c, keys, desc, (uint32_t)ntiles, parts, y32, s);
         if (!le) le = mp_launch_unpack(c, y32, desc, keys, tk, (uint32_t)ntiles, d_msg, s);
         if (le) e = (hipError_t)le;
-        // host vectors per[c] / tkeys[c] must outlive the asynchronous copies
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
+    // the host vectors per[c] / tkeys[c] must outlive the asynchronous copies
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     uint32_t flag = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, d_err, sizeof flag, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_err(ctx, e, "multi-prime decryption");
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        return hip_err(ctx, e, "multi-prime decryption");
+    }
     if (flag & 1u) return set_err(ctx, PMK_ERANGE, "a ciphertext block is not below its modulus");
     ctx->err.clear();
     return PMK_OK;

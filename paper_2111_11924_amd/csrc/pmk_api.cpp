@@ -142,6 +142,7 @@ void pmk_destroy(pmk_ctx *ctx) {
     if (ctx->mr_table) (void)hipFree(ctx->mr_table);
     for (auto &p : ctx->d_mp_keys)
         if (p) (void)hipFree(p);
+    if (ctx->mp_scratch) (void)hipFree(ctx->mp_scratch);
     delete ctx;
 }
 

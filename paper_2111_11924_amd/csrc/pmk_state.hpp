@@ -43,6 +43,8 @@ struct pmk_ctx {
     // multi-prime key table (pmk_mp_keys_load): records per class (3072 / 4096 bits)
     std::vector<KeySlot> mp_keys;
     uint32_t *d_mp_keys[2] = {};
+    void *mp_scratch = nullptr;  // device arena of pmk_mp_decrypt (grown on demand)
+    uint64_t mp_scratch_bytes = 0;
 };
 
 struct TimedLaunch {
