@@ -1,10 +1,12 @@
 """CPU oracle for the PMKRSA hot path -- TEST INFRASTRUCTURE ONLY.
 
 Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
-use this package.  It wraps ``oracle.c`` (plain C: schoolbook multiplication,
-Knuth Algorithm D remainders, the binary exponentiation of Algorithm 2, CRT-RSA
-decryption as in Sec. 2.1) through ctypes.  It shares no code with the GPU
-library.
+use this package.  It wraps ``oracle.c`` through ctypes: plain C with
+schoolbook multiplication, Knuth Algorithm D remainders, x^e mod N (the
+operation of Algorithm 2) by left-to-right square-and-multiply, and CRT-RSA
+decryption as in Sec. 2.1.  Operands beyond its fixed limb capacity (520
+limbs; moduli up to 260 limbs) raise instead of being cut.  It shares no code
+with the GPU library.
 
 Pins (tests/test_oracle_*.py) tie it to facts outside itself: Python's own
 integer arithmetic (an independent implementation), brute-force repeated
@@ -101,7 +103,9 @@ def _p(a: np.ndarray):
 def mul(a: int, b: int) -> int:
     A, B = to_limbs(a), to_limbs(b)
     R = np.zeros(len(A) + len(B), dtype=np.uint32)
-    assert lib().oracle_mul(_p(A), len(A), _p(B), len(B), _p(R), len(R)) == 0
+    rc = lib().oracle_mul(_p(A), len(A), _p(B), len(B), _p(R), len(R))
+    if rc != 0:
+        raise OverflowError("operands beyond the oracle's limb capacity")
     return from_limbs(R)
 
 
@@ -110,6 +114,8 @@ def divmod_(u: int, v: int) -> Tuple[int, int]:
     Q = np.zeros(len(U), dtype=np.uint32)
     R = np.zeros(len(V), dtype=np.uint32)
     rc = lib().oracle_divmod(_p(U), len(U), _p(V), len(V), _p(Q), len(Q), _p(R), len(R))
+    if rc == -2:
+        raise OverflowError("operands beyond the oracle's limb capacity")
     if rc != 0:
         raise ZeroDivisionError
     return from_limbs(Q), from_limbs(R)
@@ -119,6 +125,8 @@ def modexp(x: int, e: int, m: int) -> int:
     X, E, M = to_limbs(x), to_limbs(e), to_limbs(m)
     Y = np.zeros(len(M), dtype=np.uint32)
     rc = lib().oracle_modexp(_p(X), len(X), _p(E), len(E), _p(M), len(M), _p(Y), len(Y))
+    if rc == -2:
+        raise OverflowError("operands beyond the oracle's limb capacity")
     if rc != 0:
         raise ValueError("modulus 0")
     return from_limbs(Y)
@@ -197,7 +205,11 @@ def rsa_int(table: KeyTable, key_index: int, mode: str, x: int) -> int:
     out = np.zeros(nl, dtype=np.uint32)
     m = {"enc": 0, "dec": 1, "crt": 2}[mode]
     k = C.pointer(table.arr[key_index])
-    assert lib().oracle_rsa_int(k, m, _p(X), len(X), _p(out), nl) == 0
+    rc = lib().oracle_rsa_int(k, m, _p(X), len(X), _p(out), nl)
+    if rc == -2:
+        raise OverflowError("key or input beyond the oracle's limb capacity")
+    if rc != 0:
+        raise ValueError(f"oracle_rsa_int: {rc}")
     return from_limbs(out)
 
 

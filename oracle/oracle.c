@@ -19,10 +19,11 @@
  *     m = (c*)^d (c_R^d)^-1 mod N (Sec. 3.1, Eqs. 3-10, Algorithm 1).
  *
  * How: little-endian base-2^32 limbs; schoolbook multiplication; remainders by
- * Knuth's Algorithm D (TAOCP vol. 2, Sec. 4.3.1); modular exponentiation by the
- * binary multiply-and-square method of Algorithm 2 in the order the paper
- * prints it (bits scanned from e_0 upwards, last factor applied after the
- * loop).  No Montgomery arithmetic, no windows, no lane tricks.
+ * Knuth's Algorithm D (TAOCP vol. 2, Sec. 4.3.1); modular exponentiation
+ * y = x^e mod N (the operation Algorithm 2 computes) written from that
+ * definition as left-to-right square-and-multiply over the bits of e.  No
+ * Montgomery arithmetic, no windows, no lane tricks.  Inputs longer than the
+ * fixed limb capacity are refused with an error, never truncated.
  *
  * Readings of the paper taken here (each one listed in the design notes):
  *   - a chunk is the big-endian integer of (modulus bytes - 4) message bytes,
@@ -63,11 +64,16 @@ static void bn_copy(bn *dst, const bn *src) {
     memcpy(dst->v, src->v, sizeof(uint32_t) * (size_t)src->len);
 }
 
-static void bn_from_limbs(bn *a, const uint32_t *limbs, int n) {
-    if (n > OR_MAXL) n = OR_MAXL;
+/* returns -1 (and leaves a = 0) when the value needs more than OR_MAXL limbs */
+static int bn_from_limbs(bn *a, const uint32_t *limbs, int n) {
+    while (n > 0 && limbs[n - 1] == 0) n--;
+    if (n > OR_MAXL) {
+        bn_zero(a);
+        return -1;
+    }
     memcpy(a->v, limbs, sizeof(uint32_t) * (size_t)n);
     a->len = n;
-    bn_norm(a);
+    return 0;
 }
 
 /* writes exactly n limbs (zero-padded); returns -1 if the value does not fit */
@@ -87,6 +93,7 @@ static int bn_cmp(const bn *a, const bn *b) {
 /* r = a + b */
 static void bn_add(bn *r, const bn *a, const bn *b) {
     int n = a->len > b->len ? a->len : b->len;
+    if (n + 1 > OR_MAXL) abort(); /* callers stay within capacity; overflowing it is a bug */
     uint64_t carry = 0;
     for (int i = 0; i < n; i++) {
         uint64_t s = carry;
@@ -123,6 +130,7 @@ static void bn_mul(bn *r, const bn *a, const bn *b) {
         return;
     }
     int n = a->len + b->len;
+    if (n > OR_MAXL) abort(); /* entry points bound their operands; overflowing is a bug */
     for (int i = 0; i < n; i++) r->v[i] = 0;
     for (int i = 0; i < a->len; i++) {
         uint64_t carry = 0;
@@ -266,24 +274,22 @@ static int bn_bitlen(const bn *a) {
 }
 
 /*
- * y = x^e mod N by Algorithm 2 (binary multiply-and-square).  With
- * e = (e_l ... e_1 e_0)_2 and e_l = 1: start from y = 1, x = x mod N; for
- * i = 0 .. l-1 multiply y by x when e_i = 1, then square x; finally multiply y
- * by x once more for the top bit e_l.  e = 0 gives 1 mod N (the empty product).
- * N must be non-zero; N = 1 gives 0.
+ * y = x^e mod N, the operation of Algorithm 2 (binary exponentiation), written
+ * from its definition: with e = sum_i e_i 2^i, scan the bits from the top one
+ * down; before bit i is taken in, y = x^(e >> (i+1)) mod N, so squaring y and
+ * multiplying by x where e_i = 1 gives x^(e >> i) mod N.  After bit 0,
+ * y = x^e mod N.  e = 0 gives 1 mod N (the empty product); N must be non-zero,
+ * and N = 1 gives 0.
  */
 static void bn_modexp(bn *y, const bn *x_in, const bn *e, const bn *N) {
     bn one, x;
     bn_set_u32(&one, 1);
     bn_mod(y, &one, N);
-    if (e->len == 0) return;
     bn_mod(&x, x_in, N);
-    int l = bn_bitlen(e) - 1; /* index of the top bit e_l */
-    for (int i = 0; i < l; i++) {
+    for (int i = bn_bitlen(e) - 1; i >= 0; i--) {
+        bn_mulmod(y, y, y, N);
         if (bn_bit(e, i)) bn_mulmod(y, y, &x, N);
-        bn_mulmod(&x, &x, &x, N);
     }
-    bn_mulmod(y, y, &x, N);
 }
 
 /* ---------- byte <-> integer -------------------------------------------------------- */
@@ -359,6 +365,29 @@ long long oracle_plan(const oracle_key *keys, int nkeys, const uint32_t *key_map
 
 static void key_part(bn *out, const uint32_t *limbs, int len) { bn_from_limbs(out, limbs, len); }
 
+/* number of limbs of a limb array once its zero top limbs are dropped */
+static int used_limbs(const uint32_t *limbs, int n) {
+    while (n > 0 && limbs[n - 1] == 0) n--;
+    return n;
+}
+
+/* every field of a key fits half the limb capacity, so that a product of two
+ * residues (and every intermediate of the routines below) fits the capacity */
+static int key_ok(const oracle_key *k) {
+    const int half = OR_MAXL / 2;
+    return used_limbs(k->n, k->n_len) <= half && used_limbs(k->e, k->e_len) <= half &&
+           used_limbs(k->d, k->d_len) <= half && used_limbs(k->p, k->p_len) <= half &&
+           used_limbs(k->q, k->q_len) <= half && used_limbs(k->dp, k->dp_len) <= half &&
+           used_limbs(k->dq, k->dq_len) <= half && used_limbs(k->qinv, k->qinv_len) <= half &&
+           k->bits > 0 && k->bits <= 32 * half;
+}
+
+static int keys_ok(const oracle_key *keys, int nkeys) {
+    for (int i = 0; i < nkeys; i++)
+        if (!key_ok(&keys[i])) return 0;
+    return 1;
+}
+
 /* Sec. 1.1 step 2 / Algorithm 1 (Encryption without blinding): c = m^e mod N */
 static void rsa_encrypt_int(bn *c, const bn *m, const oracle_key *k) {
     bn N, e;
@@ -406,33 +435,34 @@ static void rsa_decrypt_crt_int(bn *m, const bn *c, const oracle_key *k) {
 
 /* ---------- exported primitives (for pinning the oracle against Python integers) ---- */
 
-/* r (rn limbs) = a * b; returns -1 if rn is too small */
+/* r (rn limbs) = a * b; returns -1 if rn is too small, -2 if the product exceeds the capacity */
 int oracle_mul(const uint32_t *a, int an, const uint32_t *b, int bn_, uint32_t *r, int rn) {
     bn A, Bv, R;
-    bn_from_limbs(&A, a, an);
-    bn_from_limbs(&Bv, b, bn_);
+    if (bn_from_limbs(&A, a, an) != 0 || bn_from_limbs(&Bv, b, bn_) != 0) return -2;
+    if (A.len + Bv.len > OR_MAXL) return -2;
     bn_mul(&R, &A, &Bv);
     return bn_to_limbs(&R, r, rn);
 }
 
-/* q (qn limbs) = u / v, r (rn limbs) = u mod v */
+/* q (qn limbs) = u / v, r (rn limbs) = u mod v; -1 for v = 0 or short outputs, -2 for an
+ * operand beyond the capacity */
 int oracle_divmod(const uint32_t *u, int un, const uint32_t *v, int vn, uint32_t *q, int qn,
                   uint32_t *r, int rn) {
     bn U, V, Q, R;
-    bn_from_limbs(&U, u, un);
-    bn_from_limbs(&V, v, vn);
+    if (bn_from_limbs(&U, u, un) != 0 || bn_from_limbs(&V, v, vn) != 0) return -2;
     if (bn_divmod(&Q, &R, &U, &V) != 0) return -1;
     if (bn_to_limbs(&Q, q, qn) != 0) return -1;
     return bn_to_limbs(&R, r, rn);
 }
 
-/* y (yn limbs) = x^e mod m by Algorithm 2 */
+/* y (yn limbs) = x^e mod m (the operation of Algorithm 2); -1 for m = 0 or a short output,
+ * -2 for operands beyond the capacity (m may have at most half of it) */
 int oracle_modexp(const uint32_t *x, int xn, const uint32_t *e, int en, const uint32_t *m, int mn,
                   uint32_t *y, int yn) {
     bn X, E, M, Y;
-    bn_from_limbs(&X, x, xn);
-    bn_from_limbs(&E, e, en);
-    bn_from_limbs(&M, m, mn);
+    if (bn_from_limbs(&X, x, xn) != 0 || bn_from_limbs(&E, e, en) != 0 || bn_from_limbs(&M, m, mn) != 0)
+        return -2;
+    if (M.len > OR_MAXL / 2) return -2;
     if (M.len == 0) return -1;
     bn_modexp(&Y, &X, &E, &M);
     return bn_to_limbs(&Y, y, yn);
@@ -443,14 +473,15 @@ int oracle_modexp(const uint32_t *x, int xn, const uint32_t *e, int en, const ui
 /*
  * Encrypt a message chunk by chunk (Algorithm 1, Encryption; the loop over
  * chunks is the one the paper marks as parallel).  ct must hold the ciphertext
- * length returned by oracle_plan.  Returns 0, or -1 on a bad plan.
+ * length returned by oracle_plan.  Returns 0, or -1 on a bad plan or a key
+ * beyond the capacity.
  */
 int oracle_encrypt(const oracle_key *keys, int nkeys, const uint8_t *msg, long long msg_len,
                    const uint32_t *key_map, long long nchunks, uint8_t *ct) {
     long long *off = malloc(sizeof(long long) * (size_t)(nchunks + 1));
     long long *len = malloc(sizeof(long long) * (size_t)(nchunks + 1));
     long long *cto = malloc(sizeof(long long) * (size_t)(nchunks + 1));
-    long long total = oracle_plan(keys, nkeys, key_map, nchunks, msg_len, off, len, cto);
+    long long total = keys_ok(keys, nkeys) ? oracle_plan(keys, nkeys, key_map, nchunks, msg_len, off, len, cto) : -1;
     int status = total < 0 ? -1 : 0;
     if (status == 0) {
 #pragma omp parallel for schedule(dynamic, 4)
@@ -479,7 +510,7 @@ int oracle_decrypt(const oracle_key *keys, int nkeys, const uint8_t *ct, long lo
     long long *off = malloc(sizeof(long long) * (size_t)(nchunks + 1));
     long long *len = malloc(sizeof(long long) * (size_t)(nchunks + 1));
     long long *cto = malloc(sizeof(long long) * (size_t)(nchunks + 1));
-    long long total = oracle_plan(keys, nkeys, key_map, nchunks, msg_len, off, len, cto);
+    long long total = keys_ok(keys, nkeys) ? oracle_plan(keys, nkeys, key_map, nchunks, msg_len, off, len, cto) : -1;
     int status = total < 0 ? -1 : 0;
     int range_err = 0;
     if (status == 0) {
@@ -515,12 +546,12 @@ int oracle_decrypt(const oracle_key *keys, int nkeys, const uint8_t *ct, long lo
 /*
  * Single-chunk forms on limb arrays, for tests that work on integers directly.
  * mode 0: c = m^e mod N; 1: m = c^d mod N; 2: CRT decryption.
- * out receives out_len limbs.
+ * out receives out_len limbs.  -2: a key field or x beyond the capacity.
  */
 int oracle_rsa_int(const oracle_key *k, int mode, const uint32_t *x, int xn, uint32_t *out,
                    int out_len) {
     bn X, Y;
-    bn_from_limbs(&X, x, xn);
+    if (!key_ok(k) || bn_from_limbs(&X, x, xn) != 0) return -2;
     if (mode == 0)
         rsa_encrypt_int(&Y, &X, k);
     else if (mode == 1)
@@ -540,20 +571,24 @@ int oracle_rsa_int(const oracle_key *k, int mode, const uint32_t *x, int xn, uin
  * The inverse r'^-1 is found by the extended Euclidean algorithm on integers.
  * mode 0 (encrypt): x = m, aux = r  ->  out = c*, out2 = c_R.
  * mode 1 (decrypt): x = c*, aux = c_R -> out = m, out2 = r'.
- * Returns -2 when r' is not invertible mod N.
+ * Returns -2 when r' is not invertible mod N, -3 for a key field or an input
+ * beyond the capacity.
  */
 static int bn_modinv(bn *inv, const bn *a, const bn *N);
 
 int oracle_blind_int(const oracle_key *k, int mode, const uint32_t *x, int xn, const uint32_t *aux,
                      int auxn, uint32_t *out, uint32_t *out2, int out_len) {
     bn X, A, N, e, d, t, y, y2;
-    bn_from_limbs(&X, x, xn);
-    bn_from_limbs(&A, aux, auxn);
+    if (!key_ok(k) || bn_from_limbs(&X, x, xn) != 0 || bn_from_limbs(&A, aux, auxn) != 0) return -3;
     key_part(&N, k->n, k->n_len);
     key_part(&e, k->e, k->e_len);
     key_part(&d, k->d, k->d_len);
+    if (N.len == 0) return -1;
     if (mode == 0) {
-        bn_mulmod(&t, &A, &X, &N);
+        bn ra, rx; /* r m mod N from the reduced factors */
+        bn_mod(&ra, &A, &N);
+        bn_mod(&rx, &X, &N);
+        bn_mulmod(&t, &ra, &rx, &N);
         bn_modexp(&y, &t, &e, &N);
         bn_modexp(&y2, &A, &e, &N);
     } else if (mode == 1) {
