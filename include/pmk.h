@@ -23,7 +23,7 @@
  *     CUDA tensor); "stream" is a hipStream_t passed as void* (NULL = the
  *     default stream).  Work on a stream is asynchronous: a zero return covers
  *     host-side validation and launch; errors the GPU detects (a ciphertext
- *     block not below its modulus) are reported by pmk_plan_check().
+ *     block out of range) are reported by pmk_plan_check().
  *   - One context per host thread; a context is not thread-safe.
  */
 #ifndef PMK_H
@@ -40,7 +40,8 @@ enum {
     PMK_OK = 0,
     PMK_EINVAL = -1,      /* bad argument or inconsistent key material */
     PMK_EKEY = -2,        /* a chunk names a key index >= number of loaded keys */
-    PMK_ERANGE = -3,      /* a ciphertext block is not below its modulus (C must lie in Z_N, Sec. 1.1) */
+    PMK_ERANGE = -3,      /* a ciphertext block is not below its modulus (C must lie in Z_N, Sec. 1.1),
+                             or decrypts to a plaintext wider than its chunk */
     PMK_ESIZE = -4,       /* chunk count / buffer sizes do not match the message */
     PMK_ENOMEM = -5,      /* device or host allocation failed */
     PMK_EDEVICE = -6,     /* HIP runtime error */
@@ -148,10 +149,29 @@ int pmk_encrypt_plan(pmk_plan *plan, const uint8_t *d_msg, uint8_t *d_ct, void *
  * Decrypt by CRT (Sec. 2.1): m_p = c^dp mod p, m_q = c^dq mod q,
  * h = qinv (m_p - m_q) mod p, m = m_q + h q; writes msg_len bytes.  d_ct: plan
  * ct_len bytes (device); d_msg: plan msg_len bytes (device).  A block that is
- * not below its modulus sets the plan's device error flag (PMK_ERANGE from
- * pmk_plan_check); that chunk's output bytes are then unspecified.
+ * not below its modulus (a ciphertext lies in Z_N, Sec. 1.1), or whose
+ * plaintext does not fit its chunk's length (no encryption of a chunk of that
+ * length produces it), sets the plan's device error flag (PMK_ERANGE from
+ * pmk_plan_check) and that chunk's output bytes are written as zeros.
  */
 int pmk_decrypt_plan(pmk_plan *plan, const uint8_t *d_ct, uint8_t *d_msg, void *stream);
+
+/*
+ * Output form of the plan's decryptions (pmk_decrypt_plan, the blinded and the
+ * batched forms):
+ *   PMK_DEC_CHUNKS  (default) msg_len bytes, chunk i as its own length, with
+ *                   the range rules above;
+ *   PMK_DEC_BLOCKS  every decrypted block in full, m_i = c_i^d mod N as kb_i
+ *                   big-endian bytes laid out like the ciphertext (the output
+ *                   buffer holds ct_len bytes): the private-key operation of
+ *                   Sec. 1.1 step 3 on any block of Z_N, without the chunk
+ *                   length check; a block not below N still sets PMK_ERANGE
+ *                   and is written as zeros.
+ * Host only; a change drops the plan's captured graphs (after waiting for the
+ * device).  PMK_EINVAL for another value.
+ */
+enum { PMK_DEC_CHUNKS = 0, PMK_DEC_BLOCKS = 1 };
+int pmk_plan_set_decrypt_output(pmk_plan *plan, int form);
 
 /*
  * Blinded PMKRSA (Sec. 3.1, Eqs. 3-10, Algorithm 1 with its blinding factor R).
@@ -162,9 +182,11 @@ int pmk_decrypt_plan(pmk_plan *plan, const uint8_t *d_ct, uint8_t *d_msg, void *
  * bytes each, same block layout).  Decryption computes
  * m_i = (c*_i)^d (c_R,i^d)^-1 mod N, i.e. r'_i = c_R,i^d = r_i is divided out,
  * through CRT: per prime, (c*)^(d_p) times c_R^(p-1-d_p) (Fermat's inverse;
- * both powers in one squaring chain), then Garner.  A c* or c_R block not below N sets PMK_ERANGE, a c_R divisible
- * by p or q sets PMK_EBLIND (both from pmk_plan_check).  Asynchronous on
- * `stream`; every buffer device memory, 4-byte aligned.
+ * both powers in one squaring chain), then Garner.  A c* or c_R block not
+ * below N, or a plaintext wider than its chunk, sets PMK_ERANGE and zeroes
+ * that chunk's output (as pmk_decrypt_plan); a c_R divisible by p or q sets
+ * PMK_EBLIND (both from pmk_plan_check).  Asynchronous on `stream`; every
+ * buffer device memory, 4-byte aligned.
  */
 int pmk_encrypt_blinded_plan(pmk_plan *plan, const uint8_t *d_msg, const uint8_t *d_r, uint8_t *d_ct_star,
                              uint8_t *d_ct_r, void *stream);
@@ -202,6 +224,18 @@ int pmk_set_window(pmk_ctx *ctx, uint32_t bits, int win);
 int pmk_get_window(const pmk_ctx *ctx, uint32_t bits);
 
 /*
+ * Upper bound on the resident waves (workgroups) of every persistent
+ * exponentiation launch of the context (the CRT halves, encryption, the
+ * batched work queue, multi-prime parts and primality tests); 0 (the default)
+ * leaves each launch at its kernel's occupancy on this device.  Each wave
+ * then walks more work units (the parallel loops of Algorithm 1 over fewer
+ * workers): a control for sharing the GPU with other work and for tuning;
+ * results never change.  Graphs are recaptured.  PMK_EBUSY while a server
+ * runs.
+ */
+int pmk_set_grid_limit(pmk_ctx *ctx, uint32_t waves);
+
+/*
  * Autotuner for the launch configuration: for every size class that has keys
  * in the loaded table, time the CRT decryption of one chip-filling batch of
  * full-size chunks (zero blocks: the fixed-window exponentiation costs the
@@ -221,7 +255,8 @@ int pmk_autotune(pmk_ctx *ctx, const char *cache_path, int flags);
 
 /*
  * Wait for `stream`, then return and clear the plan's device-detected error
- * (PMK_OK, PMK_ERANGE or PMK_EBLIND).
+ * (PMK_OK, PMK_ERANGE or PMK_EBLIND; PMK_EBLIND when both were seen, since a
+ * non-invertible blinding block also leaves its chunk's plaintext out of range).
  */
 int pmk_plan_check(pmk_plan *plan, void *stream);
 
@@ -240,8 +275,7 @@ enum {
     PMK_KERNEL_GARNER = 3,     /* CRT recombination */
     PMK_KERNEL_UNPACK = 4,     /* limbs -> bytes */
     PMK_KERNEL_BATCH = 5,      /* persistent work-queue encryption (3072/4096-bit classes) */
-    PMK_KERNEL_BLIND = 6,      /* blinded decryption: product of the two CRT half results */
-    PMK_KERNEL_KINDS = 7
+    PMK_KERNEL_KINDS = 6
 };
 int pmk_plan_profile(pmk_plan *plan, int enable);
 int pmk_plan_kernel_time(pmk_plan *plan, int kind, double *ms_total, uint64_t *launches);
@@ -255,6 +289,25 @@ int pmk_encrypt(pmk_ctx *ctx, const uint8_t *d_msg, uint64_t msg_len, const uint
                 uint64_t nchunks, uint8_t *d_ct, uint64_t ct_cap, void *stream);
 int pmk_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uint32_t *key_map,
                 uint64_t nchunks, uint8_t *d_msg, uint64_t msg_len, void *stream);
+
+/*
+ * Host-buffer forms (the paper's transfer / compute / merge pipeline of its
+ * CPU+GPU implementation, Sec. 3.3): msg and ct are HOST memory (pinned -- hipHostMalloc, or a torch
+ * tensor with pin_memory -- for asynchronous copies; pageable memory works,
+ * with copies the runtime stages itself).  The plan's chunk range is cut into
+ * `slices` runs of chunks of about equal bytes; slice s is copied to the
+ * device, encrypted or decrypted, and copied back on three streams, so the
+ * copies of one slice overlap the computation of the others.  slices = 0
+ * picks one slice for decryption (its copies are a tiny part of its time) and
+ * up to four, of at least 65,536 chunks each, for encryption.  Sizes as
+ * pmk_encrypt_plan / pmk_decrypt_plan (the decryption output form of the plan
+ * applies).  Synchronous: returns once the output is in host memory, with the
+ * device-detected status (PMK_ERANGE as pmk_plan_check).  The first call with
+ * a slice count plans its slices and allocates device copies of the whole
+ * input and output (kept with the plan); calls on one plan must not overlap.
+ */
+int pmk_encrypt_host(pmk_plan *plan, const uint8_t *msg, uint8_t *ct, uint32_t slices);
+int pmk_decrypt_host(pmk_plan *plan, const uint8_t *ct, uint8_t *msg, uint32_t slices);
 
 /*
  * Multi-prime keys (Sec. 2.1, the multi-prime variant: N is the product of b
@@ -304,8 +357,9 @@ uint32_t pmk_mp_key_count(const pmk_ctx *ctx);
  * `stream`; its device scratch is a context-held arena, grown when a call
  * needs more and freed by pmk_destroy (calls on one context must not overlap).
  * PMK_EKEY / PMK_ESIZE as
- * pmk_plan_create, PMK_ERANGE when a block is not below its modulus (the
- * output is then unspecified).
+ * pmk_plan_create, PMK_ERANGE when a block is not below its modulus or its
+ * plaintext is wider than its chunk (that chunk's bytes are then zeros, as in
+ * pmk_decrypt_plan).
  */
 int pmk_mp_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uint32_t *key_map,
                    uint64_t nchunks, uint8_t *d_msg, uint64_t msg_len, void *stream);
@@ -336,7 +390,7 @@ int pmk_miller_rabin(pmk_ctx *ctx, uint32_t bits, const uint32_t *d_cand, uint32
  * (chunks under one key share tiles across requests; each in-flight request
  * gets a fair share of a round, so small requests are not stuck behind large
  * ones), in the spirit of the paper's parallel chunk loops and transfer /
- * compute pipeline (Sec. 3.1, Algorithm 1; Sec. 4).  Requests are admitted in
+ * compute pipeline (Sec. 3.1, Algorithm 1; Sec. 3.3).  Requests are admitted in
  * arrival order while the device staging slab has room for their input and
  * output; their host buffers are copied in at admission and out at
  * completion.  Results are byte-identical to pmk_encrypt_plan /

@@ -34,8 +34,10 @@ PMK_KERNEL_CRT_HALVES = 2
 PMK_KERNEL_GARNER = 3
 PMK_KERNEL_UNPACK = 4
 PMK_KERNEL_BATCH = 5
-PMK_KERNEL_BLIND = 6
-KERNEL_NAMES = {0: "pack", 1: "encrypt", 2: "crt_halves", 3: "garner", 4: "unpack", 5: "batch", 6: "blind"}
+KERNEL_NAMES = {0: "pack", 1: "encrypt", 2: "crt_halves", 3: "garner", 4: "unpack", 5: "batch"}
+
+PMK_DEC_CHUNKS = 0
+PMK_DEC_BLOCKS = 1
 
 STATUS_NAMES = {0: "PMK_OK", -1: "PMK_EINVAL", -2: "PMK_EKEY", -3: "PMK_ERANGE", -4: "PMK_ESIZE",
                 -5: "PMK_ENOMEM", -6: "PMK_EDEVICE", -7: "PMK_EBUSY", -8: "PMK_EUNSUPPORTED",
@@ -119,6 +121,7 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "pmk_decrypt_batch": (C.c_int, [vp, vp, vp, vp]),
         "pmk_set_window": (C.c_int, [vp, u32, C.c_int]),
         "pmk_get_window": (C.c_int, [vp, u32]),
+        "pmk_set_grid_limit": (C.c_int, [vp, u32]),
         "pmk_autotune": (C.c_int, [vp, C.c_char_p, C.c_int]),
         "pmk_sieve": (C.c_int, [vp, u32, vp, u32, vp, vp]),
         "pmk_miller_rabin": (C.c_int, [vp, u32, vp, u32, vp, u32, vp, vp]),
@@ -129,10 +132,13 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "pmk_server_stats_get": (C.c_int, [vp, C.POINTER(pmk_server_stats)]),
         "pmk_server_stop": (C.c_int, [vp]),
         "pmk_plan_check": (C.c_int, [vp, vp]),
+        "pmk_plan_set_decrypt_output": (C.c_int, [vp, C.c_int]),
         "pmk_plan_profile": (C.c_int, [vp, C.c_int]),
         "pmk_plan_kernel_time": (C.c_int, [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(u64)]),
         "pmk_encrypt": (C.c_int, [vp, vp, u64, U32P, u64, vp, u64, vp]),
         "pmk_decrypt": (C.c_int, [vp, vp, u64, U32P, u64, vp, u64, vp]),
+        "pmk_encrypt_host": (C.c_int, [vp, vp, vp, u32]),
+        "pmk_decrypt_host": (C.c_int, [vp, vp, vp, u32]),
         "pmk_mp_key_check": (C.c_int, [C.POINTER(pmk_key_mp), C.c_char_p, C.c_size_t]),
         "pmk_mp_keys_load": (C.c_int, [vp, C.POINTER(pmk_key_mp), u32]),
         "pmk_mp_key_count": (u32, [vp]),
@@ -333,6 +339,10 @@ def pmk_get_window(ctx: int, bits: int) -> int:
     return load_library().pmk_get_window(ctx, int(bits))
 
 
+def pmk_set_grid_limit(ctx: int, waves: int) -> None:
+    _check(load_library().pmk_set_grid_limit(ctx, int(waves)), ctx)
+
+
 PMK_AUTOTUNE_FORCE = 1
 
 
@@ -343,6 +353,10 @@ def pmk_autotune(ctx: int, cache_path: Optional[str] = None, flags: int = 0) -> 
 
 def pmk_plan_check(plan: int, stream=None) -> int:
     return load_library().pmk_plan_check(plan, _stream(stream))
+
+
+def pmk_plan_set_decrypt_output(plan: int, form: int) -> None:
+    _check(load_library().pmk_plan_set_decrypt_output(plan, int(form)))
 
 
 def pmk_plan_profile(plan: int, enable: bool) -> None:
@@ -365,6 +379,23 @@ def pmk_decrypt(ctx: int, d_ct, ct_len: int, key_map, d_msg, msg_len: int, strea
     km = _map_array(key_map)
     return load_library().pmk_decrypt(ctx, _dev_ptr(d_ct), int(ct_len), km.ctypes.data_as(U32P), len(km),
                                       _dev_ptr(d_msg), int(msg_len), _stream(stream))
+
+
+def _host_ptr(x) -> Optional[int]:
+    """Address of a host buffer: a numpy array, a CPU torch tensor, or an int."""
+    if x is None or isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        return int(x.ctypes.data)
+    return int(x.data_ptr())
+
+
+def pmk_encrypt_host(plan: int, msg, ct, slices: int = 0) -> int:
+    return load_library().pmk_encrypt_host(plan, _host_ptr(msg), _host_ptr(ct), int(slices))
+
+
+def pmk_decrypt_host(plan: int, ct, msg, slices: int = 0) -> int:
+    return load_library().pmk_decrypt_host(plan, _host_ptr(ct), _host_ptr(msg), int(slices))
 
 
 def pmk_mp_key_check(key) -> Tuple[int, str]:
@@ -463,12 +494,20 @@ class Plan:
         fn(self.handle, msg, ct, stream, self.ctx.handle)
         return ct
 
+    def set_decrypt_output(self, form: int) -> None:
+        """PMK_DEC_CHUNKS (msg_len bytes) or PMK_DEC_BLOCKS (every m in full, ct_len bytes)."""
+        pmk_plan_set_decrypt_output(self.handle, form)
+        self.dec_blocks = form == PMK_DEC_BLOCKS
+
+    def _dec_len(self) -> int:
+        return self.ct_len if getattr(self, "dec_blocks", False) else self.msg_len
+
     def decrypt(self, ct, msg=None, stream=None, batch: bool = False):
         """CRT-decrypt `ct` into `msg`; batch=True uses pmk_decrypt_batch."""
         import torch
 
         if msg is None:
-            msg = torch.empty(max(self.msg_len, 4), dtype=torch.uint8, device=ct.device)
+            msg = torch.empty(max(self._dec_len(), 4), dtype=torch.uint8, device=ct.device)
         fn = pmk_decrypt_batch if batch else pmk_decrypt_plan
         fn(self.handle, ct, msg, stream, self.ctx.handle)
         return msg
@@ -487,9 +526,17 @@ class Plan:
         import torch
 
         if msg is None:
-            msg = torch.empty(max(self.msg_len, 4), dtype=torch.uint8, device=ct_star.device)
+            msg = torch.empty(max(self._dec_len(), 4), dtype=torch.uint8, device=ct_star.device)
         pmk_decrypt_blinded_plan(self.handle, ct_star, ct_r, msg, stream, self.ctx.handle)
         return msg
+
+    def encrypt_host(self, msg, ct, slices: int = 0) -> int:
+        """Host buffers in and out (pmk_encrypt_host); returns the status."""
+        return pmk_encrypt_host(self.handle, msg, ct, slices)
+
+    def decrypt_host(self, ct, msg, slices: int = 0) -> int:
+        """Host buffers in and out (pmk_decrypt_host); returns the status."""
+        return pmk_decrypt_host(self.handle, ct, msg, slices)
 
     def check(self, stream=None) -> int:
         return pmk_plan_check(self.handle, stream)
@@ -597,6 +644,10 @@ class Context:
 
     def window(self, bits: int) -> int:
         return pmk_get_window(self.handle, bits)
+
+    def set_grid_limit(self, waves: int) -> None:
+        """At most `waves` resident waves per persistent launch (0: the device's occupancy)."""
+        pmk_set_grid_limit(self.handle, waves)
 
     def autotune(self, cache_path: Optional[str] = None, force: bool = False) -> None:
         """Pick each loaded size class's CRT window width by timing (pmk_autotune)."""

@@ -11,7 +11,6 @@ namespace pmk {
     int launch_encrypt_##B(const ClassRun &, hipStream_t);                                 \
     int launch_halves_##B(const ClassRun &, hipStream_t);                                  \
     int launch_garner_##B(const ClassRun &, hipStream_t);                                  \
-    int launch_blind_combine_##B(const ClassRun &, const uint32_t *, hipStream_t);         \
     uint32_t wave_slots_##B(int, int);                                                     \
     uint64_t slot_words_##B(int, int);
 PMK_DECLARE(128)
@@ -42,9 +41,9 @@ int launch_pack(const ClassRun &r, const uint8_t *src, int decrypt, void *stream
     if (r.ntiles == 0) return 0;
     PMK_DISPATCH(r.cls, launch_pack, r, src, decrypt, (hipStream_t)stream);
 }
-int launch_unpack(const ClassRun &r, uint8_t *dst, int decrypt, void *stream) {
+int launch_unpack(const ClassRun &r, uint8_t *dst, int mode, void *stream) {
     if (r.ntiles == 0) return 0;
-    PMK_DISPATCH(r.cls, launch_unpack, r, dst, decrypt, (hipStream_t)stream);
+    PMK_DISPATCH(r.cls, launch_unpack, r, dst, mode, (hipStream_t)stream);
 }
 int launch_encrypt(const ClassRun &r, void *stream) {
     if (r.ntiles == 0) return 0;
@@ -58,11 +57,6 @@ int launch_garner(const ClassRun &r, void *stream) {
     if (r.ntiles == 0) return 0;
     PMK_DISPATCH(r.cls, launch_garner, r, (hipStream_t)stream);
 }
-int launch_blind_combine(const ClassRun &r, const uint32_t *half2, void *stream) {
-    if (r.ntiles == 0) return 0;
-    PMK_DISPATCH(r.cls, launch_blind_combine, r, half2, (hipStream_t)stream);
-}
-
 uint64_t table_words_per_slot(int cls, int decrypt, int win) {
     switch (cls) {
         case 0: return slot_words_128(decrypt, win);

@@ -94,26 +94,79 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint8_t *__restrict__ s
     }
 }
 
+// Output forms of unpack_kernel.
+enum UnpackMode {
+    kOutCipher = 0,    // encryption: kb-byte blocks at ct_off
+    kOutChunks = 1,    // decryption: msg_len bytes at msg_off, range-checked
+    kOutBlocks = 2     // decryption: the whole m as a kb-byte block at ct_off, range-checked
+};
+
+// x (word k at x[k * CPT]) < n (word k at n[k]), most significant word first
+template <int S, int CPT>
+PMK_DEV bool below(const uint32_t *x, const uint32_t *n) {
+    for (int k = S - 1; k >= 0; --k) {
+        const uint32_t a = x[(size_t)k * CPT], b = n[k];
+        if (a != b) return a < b;
+    }
+    return false;
+}
+
+// Decryption output keeps to the range of the scheme, as the oracle does: a
+// chunk whose ciphertext block is not below its modulus (a ciphertext lies in
+// Z_N, Sec. 1.1) -- checked against the packed input words chk and, for
+// blinded decryption, chk2 -- or whose plaintext does not fit its msg_len bytes
+// (no encryption of a chunk of that length has it) is written as zero bytes and
+// sets bit 0 of *err (PMK_ERANGE), and its byte of slot_err when given.  The
+// full-block form checks the range only.
 template <int S, int CPT>
 __global__ __launch_bounds__(256) void unpack_kernel(const uint32_t *__restrict__ y32,
                                                      const ChunkDesc *__restrict__ desc,
                                                      const uint32_t *__restrict__ keys,
                                                      const uint32_t *__restrict__ tile_key, int stride,
-                                                     int off_kbytes, uint8_t *__restrict__ dst, int decrypt) {
+                                                     int off_kbytes, int off_n32, uint8_t *__restrict__ dst, int mode,
+                                                     const uint32_t *__restrict__ chk,
+                                                     const uint32_t *__restrict__ chk2, uint32_t *err,
+                                                     uint8_t *slot_err) {
     __shared__ uint32_t tile[S * (CPT + 1)];
+    __shared__ uint32_t bad[CPT];
     const uint32_t t = blockIdx.x;
-    const int64_t kb = keys[(size_t)tile_key[t] * stride + off_kbytes];
+    const uint32_t *kr = keys + (size_t)tile_key[t] * stride;
+    const int64_t kb = kr[off_kbytes];
     for (int i = threadIdx.x; i < S * CPT; i += blockDim.x) {
         const int k = i / CPT, c = i % CPT;
         tile[k * (CPT + 1) + c] = y32[((size_t)t * S + k) * CPT + c];
+    }
+    __syncthreads();
+    if (mode != kOutCipher && threadIdx.x < CPT) {
+        const int c = threadIdx.x;
+        const uint32_t len = desc[(size_t)t * CPT + c].msg_len;
+        uint32_t out = 0;
+        if (len) {
+            if (mode == kOutChunks) {
+                // word len/4 keeps its low len%4 bytes; every byte above them must be 0
+                const int full = (int)(len / 4), rem = (int)(len % 4);
+                for (int k = full; k < S; ++k) {
+                    const uint32_t w = tile[k * (CPT + 1) + c];
+                    out |= (k == full && rem) ? w >> (8 * rem) : w;
+                }
+            }
+            const uint32_t *n32 = kr + off_n32;
+            if (chk && !below<S, CPT>(chk + (size_t)t * S * CPT + c, n32)) out = 1;
+            if (chk2 && !below<S, CPT>(chk2 + (size_t)t * S * CPT + c, n32)) out = 1;
+            if (out) {
+                atomicOr(err, 1u);
+                if (slot_err) slot_err[(size_t)t * CPT + c] = 1;  // names the chunk (request server)
+            }
+        }
+        bad[c] = out;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < S * CPT; i += blockDim.x) {
         const int c = i / S, k = i % S;
         const ChunkDesc d = desc[(size_t)t * CPT + c];
         if (!d.msg_len) continue;
-        const uint32_t w = tile[k * (CPT + 1) + c];
-        if (decrypt)
+        const uint32_t w = mode != kOutCipher && bad[c] ? 0u : tile[k * (CPT + 1) + c];
+        if (mode == kOutChunks)
             be_store(dst, d.msg_off, d.msg_len, k, w);
         else
             be_store(dst, d.ct_off, kb, k, w);
@@ -412,7 +465,7 @@ PMK_DEV void halves_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uint32_t 
     uint32_t n[NL];
     load_uniform(n, hr + G.h_m);
     const uint32_t n0 = uni(hr[G.h_m0]);
-    const uint32_t *dexp = hr + (r.exp_sel ? G.h_d2 : G.h_d);
+    const uint32_t *dexp = hr + G.h_d;
     const uint32_t *one_h = hr + G.h_one;
 
     uint32_t acc[NL], b[NL];
@@ -962,7 +1015,7 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
     uint32_t n[K];
     load_limbs(n, fresh_v(hr + G.h_m + pos * K));
     const uint32_t n0 = uni(hr[G.h_m0]);
-    const uint32_t *dexp = hr + (r.exp_sel ? G.h_d2 : G.h_d);
+    const uint32_t *dexp = hr + G.h_d;
 
     uint32_t acc[K];
     for (int k = pos; k < S; k += L) col[k * NG] = r.x32[((size_t)tile * S + k) * kTile + c];
@@ -1455,79 +1508,6 @@ __global__ __launch_bounds__(64) void garner_rolled_kernel(const uint32_t *__res
     for (; k32 < S; ++k32) {  // (not reached: 2 NL LB >= 32 S)
         if (slot0 < nslots) y32[((size_t)tile * S + k32) * CPT + c] = (uint32_t)wacc;
         wacc >>= 32;
-    }
-}
-
-// blinded decryption, rolled form of blind_combine_kernel (6144/8192-bit classes)
-template <int CB>
-__global__ __launch_bounds__(64) void blind_combine_rolled_kernel(const uint32_t *__restrict__ keys,
-                                                                  const ChunkDesc *__restrict__ desc,
-                                                                  uint32_t nslots, uint32_t *__restrict__ half,
-                                                                  const uint32_t *__restrict__ half2,
-                                                                  uint32_t *err) {
-    constexpr Geom G = make_geom(CB);
-    constexpr int NL = G.nlh, LB = G.lbh, CPT = chunks_per_tile(CB);
-    const uint32_t slot0 = blockIdx.x * 64 + threadIdx.x;
-    const uint32_t slot = slot0 < nslots ? slot0 : nslots - 1;
-    const int h = blockIdx.y;
-    const uint32_t tile = slot / CPT, c = slot % CPT;
-    const uint32_t *hr = keys + (size_t)desc[slot].key * G.stride + G.off_half[h];
-    const size_t base = ((size_t)(2 * tile + h) * NL) * CPT + c;
-    uint32_t x[NL], y[NL];
-    uint32_t any = 0;
-#pragma unroll 1
-    for (int j = 0; j < NL; ++j) {
-        x[j] = half[base + (size_t)j * CPT];
-        y[j] = half2[base + (size_t)j * CPT];
-        any |= y[j];
-    }
-    mont_mul_rolled<NL, LB>(x, x, y, hr + G.h_m, hr[G.h_m0]);
-    mont_mul_rolled<NL, LB>(x, x, hr + G.h_rr, hr + G.h_m, hr[G.h_m0]);
-    canonicalize_rolled<NL, LB>(x, hr + G.h_m);
-    if (slot0 < nslots && desc[slot].msg_len) {
-        if (!any) atomicOr(err, 2u);
-#pragma unroll 1
-        for (int j = 0; j < NL; ++j) half[base + (size_t)j * CPT] = x[j];
-    }
-}
-
-// ------------------------------------------------------------------ blinding
-// Blinded decryption (Sec. 3.1, Algorithm 1): with a = c* mod p_h and
-// b = c_R mod p_h, m mod p_h = a^d * (b^d)^-1 = a^d * b^(p_h - 1 - d).  The two
-// exponentiations land in half (a^d) and half2 (b^(p_h-1-d)); this kernel
-// multiplies them: half[h] = MM(MM(x, y), R^2) mod p_h, canonical.  y = 0 means
-// b is divisible by p_h (the blinding factor shares a prime with N): flagged.
-// Grid: (slots / 64, 2), one lane per slot of prime h = blockIdx.y.
-template <int CB>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(make_geom(CB).nlh > 40 ? 1 : 2))) void blind_combine_kernel(
-    const uint32_t *__restrict__ keys, const ChunkDesc *__restrict__ desc, uint32_t nslots,
-    uint32_t *__restrict__ half, const uint32_t *__restrict__ half2, uint32_t *err) {
-    constexpr Geom G = make_geom(CB);
-    constexpr int NL = G.nlh, LB = G.lbh, CPT = chunks_per_tile(CB);
-    const uint32_t slot0 = blockIdx.x * 64 + threadIdx.x;
-    const uint32_t slot = slot0 < nslots ? slot0 : nslots - 1;
-    const int h = blockIdx.y;
-    const uint32_t tile = slot / CPT, c = slot % CPT;
-    const uint32_t *hr = keys + (size_t)desc[slot].key * G.stride + G.off_half[h];
-    const size_t base = ((size_t)(2 * tile + h) * NL) * CPT + c;
-    uint32_t m[NL], x[NL], y[NL];
-    load_limbs(m, hr + G.h_m);
-    uint32_t any = 0;
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-        x[j] = half[base + (size_t)j * CPT];
-        y[j] = half2[base + (size_t)j * CPT];
-        any |= y[j];
-    }
-    const uint32_t n0 = hr[G.h_m0];
-    mont_mul<NL, LB>(x, x, y, m, n0);
-    load_limbs(y, hr + G.h_rr);
-    mont_mul<NL, LB>(x, x, y, m, n0);
-    canonicalize<NL, LB>(x, m);
-    if (slot0 < nslots && desc[slot].msg_len) {
-        if (!any) atomicOr(err, 2u);
-#pragma unroll
-        for (int j = 0; j < NL; ++j) half[base + (size_t)j * CPT] = x[j];
     }
 }
 

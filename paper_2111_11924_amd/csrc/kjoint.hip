@@ -26,16 +26,14 @@ int launch_joint_class(const ClassRun &r, hipStream_t s) {
         ncu = 1;
     const uint64_t resident = (uint64_t)oj * (uint64_t)ncu;
     const uint32_t units = 2 * r.ntiles * lanes_half(CB);
-    uint64_t grid = units < resident ? units : resident;
-    if (grid > r.slots_dec) grid = r.slots_dec;
+    uint64_t grid = persistent_grid(units, r.slots_dec, r.grid_cap);
+    if (grid > resident) grid = resident;
     const uint64_t slot = 2 * table_words_per_slot(r.cls, 1, r.win);  // two odd-power tables
     hipLaunchKernelGGL(halves_joint_kernel<CB>, dim3((uint32_t)grid), dim3(64), 0, s, r, slot);
     return (int)hipGetLastError();
 }
 
 }  // namespace
-
-bool joint_class(int cls) { return cls >= 0 && cls < kNumClasses; }
 
 int launch_decrypt_joint(const ClassRun &r, void *stream) {
     if (r.ntiles == 0) return 0;

@@ -222,12 +222,14 @@ int launch_pack_k(const uint8_t *src, const ChunkDesc *desc, const uint32_t *key
     return (int)hipGetLastError();
 }
 
+// plaintext chunks, range-checked against the packed ciphertext x32 (as the
+// two-prime decryption)
 template <int K>
 int launch_unpack_k(const uint32_t *y32, const ChunkDesc *desc, const uint32_t *keys, const uint32_t *tile_key,
-                    uint32_t ntiles, uint8_t *dst, hipStream_t s) {
+                    uint32_t ntiles, const uint32_t *x32, uint8_t *dst, uint32_t *err, hipStream_t s) {
     constexpr MpGeom G = make_mp_geom(K);
     hipLaunchKernelGGL((unpack_kernel<G.S, kTile>), dim3(ntiles), dim3(256), 0, s, y32, desc, keys, tile_key,
-                       G.stride, G.off_kbytes, dst, 1);
+                       G.stride, G.off_kbytes, G.off_n32, dst, (int)kOutChunks, x32, nullptr, err, nullptr);
     return (int)hipGetLastError();
 }
 
@@ -241,10 +243,11 @@ int mp_launch_pack(int k, const uint8_t *src, const ChunkDesc *desc, const uint3
 }
 
 int mp_launch_unpack(int k, const uint32_t *y32, const ChunkDesc *desc, const uint32_t *keys,
-                     const uint32_t *tile_key, uint32_t ntiles, uint8_t *dst, void *stream) {
+                     const uint32_t *tile_key, uint32_t ntiles, const uint32_t *x32, uint8_t *dst, uint32_t *err,
+                     void *stream) {
     hipStream_t s = (hipStream_t)stream;
-    return k == 0 ? launch_unpack_k<0>(y32, desc, keys, tile_key, ntiles, dst, s)
-                  : launch_unpack_k<1>(y32, desc, keys, tile_key, ntiles, dst, s);
+    return k == 0 ? launch_unpack_k<0>(y32, desc, keys, tile_key, ntiles, x32, dst, err, s)
+                  : launch_unpack_k<1>(y32, desc, keys, tile_key, ntiles, x32, dst, err, s);
 }
 
 int mp_launch_parts(int k, const uint32_t *keys, const uint32_t *tile_key, const ChunkDesc *desc, uint32_t ntiles,

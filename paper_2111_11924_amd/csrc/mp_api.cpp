@@ -127,7 +127,7 @@ int pmk_mp_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uin
         const MpGeom g = make_mp_geom(c);
         const uint32_t units = (uint32_t)(ntiles * g.parts);
         Part &a = at[c];
-        a.grid = std::max<uint32_t>(1, std::min<uint32_t>(mp_wave_slots(ctx->num_cus), units));
+        a.grid = std::max<uint32_t>(1, persistent_grid(units, mp_wave_slots(ctx->num_cus), ctx->grid_limit));
         a.desc = total;
         total += align_up(per[c].size() * sizeof(ChunkDesc));
         a.tk = total;
@@ -173,7 +173,7 @@ int pmk_mp_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uin
             le = mp_launch_parts(c, keys, tk, desc, (uint32_t)ntiles, x32, parts, table, mp_slot_words(win), a.grid,
                                  win, d_err, s);
         if (!le) le = mp_launch_garner(c, keys, desc, (uint32_t)ntiles, parts, y32, s);
-        if (!le) le = mp_launch_unpack(c, y32, desc, keys, tk, (uint32_t)ntiles, d_msg, s);
+        if (!le) le = mp_launch_unpack(c, y32, desc, keys, tk, (uint32_t)ntiles, x32, d_msg, d_err, s);
         if (le) e = (hipError_t)le;
     }
     // the host vectors per[c] / tkeys[c] must outlive the asynchronous copies
@@ -185,7 +185,8 @@ int pmk_mp_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uin
         (void)hipStreamSynchronize(s);
         return hip_err(ctx, e, "multi-prime decryption");
     }
-    if (flag & 1u) return set_err(ctx, PMK_ERANGE, "a ciphertext block is not below its modulus");
+    if (flag & 1u)
+        return set_err(ctx, PMK_ERANGE, "a ciphertext block is not below its modulus or decrypts wider than its chunk");
     ctx->err.clear();
     return PMK_OK;
 }

@@ -64,8 +64,11 @@ int mp_launch_parts(int k, const uint32_t *keys, const uint32_t *tile_key, const
                     int win, uint32_t *err, void *stream);
 int mp_launch_garner(int k, const uint32_t *keys, const ChunkDesc *desc, uint32_t ntiles, uint32_t *parts,
                      uint32_t *y32, void *stream);
+// plaintext chunks; a block not below N (checked against x32) or a plaintext
+// wider than its chunk is written as zeros and sets bit 0 of *err
 int mp_launch_unpack(int k, const uint32_t *y32, const ChunkDesc *desc, const uint32_t *keys,
-                     const uint32_t *tile_key, uint32_t ntiles, uint8_t *dst, void *stream);
+                     const uint32_t *tile_key, uint32_t ntiles, const uint32_t *x32, uint8_t *dst, uint32_t *err,
+                     void *stream);
 uint64_t mp_slot_words(int win);
 uint32_t mp_wave_slots(int num_cus);
 

@@ -56,6 +56,14 @@ void drop_graphs(pmk_plan *pl) {
 void free_plan_memory(pmk_plan *pl) {
     drop_timings(pl);
     drop_graphs(pl);
+    for (pmk_plan *s : pl->hp_sub) pmk_plan_destroy(s);
+    pl->hp_sub.clear();
+    for (int i = 0; i < pmk_plan::kPipe; ++i) {
+        if (pl->hp_stream[i]) (void)hipStreamDestroy(pl->hp_stream[i]);
+        pl->hp_stream[i] = nullptr;
+    }
+    for (hipEvent_t ev : pl->hp_ev) (void)hipEventDestroy(ev);
+    pl->hp_ev.clear();
     if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
     for (int i = 0; i < pmk_plan::kSide; ++i) {
         if (pl->side_stream[i]) (void)hipStreamDestroy(pl->side_stream[i]);
@@ -98,6 +106,7 @@ hipError_t ensure_tables(pmk_plan *pl) {
         ClassRun &r = pl->runs[c];
         if (!r.ntiles) continue;
         r.win = pl->ctx->win[c];
+        r.grid_cap = pl->ctx->grid_limit;
         const uint64_t need = std::max(r.slots_enc * table_words_per_slot(c, 0, 0),
                                        r.slots_dec * table_words_per_slot(c, 1, r.win));
         const hipError_t e = regrow(pl, &r.table, pl->table_cap[c], need);
@@ -262,6 +271,7 @@ int pmk_plan_create(pmk_ctx *ctx, const uint32_t *key_map, uint64_t nchunks, uin
     pl->msg_len = msg_len;
     pl->nchunks = nchunks;
     pl->ct_len = total;
+    if (nchunks) pl->key_map.assign(key_map, key_map + nchunks);
     hipError_t e = dev_alloc(pl, &pl->d_err, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(pl->d_err, 0, sizeof(uint32_t));
     for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
@@ -357,7 +367,8 @@ int pmk_decrypt_plan(pmk_plan *pl, const uint8_t *d_ct, uint8_t *d_msg, void *st
         int e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(r, d_ct, 1, stream); });
         if (!e) e = timed_launch(pl, PMK_KERNEL_CRT_HALVES, stream, [&] { return launch_decrypt_halves(r, stream); });
         if (!e) e = timed_launch(pl, PMK_KERNEL_GARNER, stream, [&] { return launch_garner(r, stream); });
-        if (!e) e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, d_msg, 1, stream); });
+        if (!e)
+            e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, d_msg, pl->dec_mode, stream); });
         if (e) return hip_err(ctx, (hipError_t)e, "decrypt launch");
     }
     return PMK_OK;
@@ -370,8 +381,7 @@ static int blind_prepare(pmk_plan *pl) {
         if (!r.ntiles) continue;
         const Geom g = make_geom(kClassBits[c]);
         const uint64_t tiles = r.ntiles, cpt = (uint64_t)chunks_per_tile(kClassBits[c]);
-        hipError_t e = dev_alloc(pl, &pl->x32b[c], tiles * g.S * cpt * sizeof(uint32_t));
-        if (e == hipSuccess) e = dev_alloc(pl, &pl->half2[c], tiles * 2 * g.nlh * cpt * sizeof(uint32_t));
+        const hipError_t e = dev_alloc(pl, &pl->x32b[c], tiles * g.S * cpt * sizeof(uint32_t));
         if (e != hipSuccess) return hip_err(pl->ctx, e, "blinding buffers");
     }
     pl->blind_ready = true;
@@ -422,7 +432,7 @@ int pmk_decrypt_blinded_plan(pmk_plan *pl, const uint8_t *d_ct_star, const uint8
     if (rc != PMK_OK) return rc;
     for (int c = 0; c < kNumClasses; ++c) {
         ClassRun &r = pl->runs[c];
-        if (!r.ntiles || !joint_class(c)) continue;
+        if (!r.ntiles) continue;
         // the one-pass form keeps two odd-power tables per slot
         const hipError_t te = regrow(pl, &r.table, pl->table_cap[c], 2 * r.slots_dec * table_words_per_slot(c, 1, r.win));
         if (te != hipSuccess) return hip_err(ctx, te, "window table allocation");
@@ -430,34 +440,33 @@ int pmk_decrypt_blinded_plan(pmk_plan *pl, const uint8_t *d_ct_star, const uint8
     for (int c = 0; c < kNumClasses; ++c) {
         const ClassRun &r = pl->runs[c];
         if (!r.ntiles) continue;
-        if (joint_class(c)) {  // (c*)^d_p c_R^(p-1-d_p) in one chain per prime
-            ClassRun rj = r;
-            rj.fin32 = pl->x32b[c];
-            int e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(r, d_ct_star, 1, stream); });
-            if (!e) {
-                ClassRun rr = r;
-                rr.x32 = pl->x32b[c];
-                e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(rr, d_ct_r, 1, stream); });
-            }
-            if (!e) e = timed_launch(pl, PMK_KERNEL_CRT_HALVES, stream, [&] { return launch_decrypt_joint(rj, stream); });
-            if (!e) e = timed_launch(pl, PMK_KERNEL_GARNER, stream, [&] { return launch_garner(r, stream); });
-            if (!e) e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, d_msg, 1, stream); });
-            if (e) return hip_err(ctx, (hipError_t)e, "blinded decrypt launch");
-            continue;
-        }
-        ClassRun rr = r;  // c_R^(p-1-d_p), c_R^(q-1-d_q) into half2
+        // (c*)^d_p c_R^(p-1-d_p) in one chain per prime; c* packed at x32, c_R at x32b
+        ClassRun rj = r;
+        rj.fin32 = pl->x32b[c];
+        ClassRun rr = r;
         rr.x32 = pl->x32b[c];
-        rr.half = pl->half2[c];
-        rr.exp_sel = 1;
         int e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(r, d_ct_star, 1, stream); });
         if (!e) e = timed_launch(pl, PMK_KERNEL_PACK, stream, [&] { return launch_pack(rr, d_ct_r, 1, stream); });
-        if (!e) e = timed_launch(pl, PMK_KERNEL_CRT_HALVES, stream, [&] { return launch_decrypt_halves(r, stream); });
-        if (!e) e = timed_launch(pl, PMK_KERNEL_CRT_HALVES, stream, [&] { return launch_decrypt_halves(rr, stream); });
-        if (!e)
-            e = timed_launch(pl, PMK_KERNEL_BLIND, stream, [&] { return launch_blind_combine(r, pl->half2[c], stream); });
+        if (!e) e = timed_launch(pl, PMK_KERNEL_CRT_HALVES, stream, [&] { return launch_decrypt_joint(rj, stream); });
         if (!e) e = timed_launch(pl, PMK_KERNEL_GARNER, stream, [&] { return launch_garner(r, stream); });
-        if (!e) e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, d_msg, 1, stream); });
+        // both blocks are range-checked while unpacking
+        if (!e)
+            e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(rj, d_msg, pl->dec_mode, stream); });
         if (e) return hip_err(ctx, (hipError_t)e, "blinded decrypt launch");
+    }
+    return PMK_OK;
+}
+
+int pmk_plan_set_decrypt_output(pmk_plan *pl, int form) {
+    if (!pl) return PMK_EINVAL;
+    if (form != PMK_DEC_CHUNKS && form != PMK_DEC_BLOCKS)
+        return set_err(pl->ctx, PMK_EINVAL, "decryption output form must be PMK_DEC_CHUNKS or PMK_DEC_BLOCKS");
+    const int mode = form == PMK_DEC_BLOCKS ? 2 : 1;
+    if (mode != pl->dec_mode) {
+        (void)hipSetDevice(pl->ctx->device);
+        (void)hipDeviceSynchronize();  // a replay in flight still uses its graph
+        drop_graphs(pl);               // captured sequences hold the old unpack form
+        pl->dec_mode = mode;
     }
     return PMK_OK;
 }
@@ -542,7 +551,7 @@ int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, v
     auto stream_of = [&](int lane) { return lane == 0 ? stream : (void *)pl->side_stream[lane - 1]; };
     if (!e && !decrypt && total) {
         void *s = stream_of(lanes - 1);
-        const uint32_t grid = std::min(total, pl->batch_slots);
+        const uint32_t grid = persistent_grid(total, pl->batch_slots, ctx->grid_limit);
         e = timed_launch(pl, PMK_KERNEL_BATCH, s, [&] { return launch_batch(a, grid, s); });
     }
     for (int i = 0; i < nl && !e; ++i) {
@@ -561,7 +570,10 @@ int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, v
         const ClassRun &r = pl->runs[c];
         if (!r.ntiles) continue;
         if (decrypt) e = timed_launch(pl, PMK_KERNEL_GARNER, stream, [&] { return launch_garner(r, stream); });
-        if (!e) e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, out, decrypt, stream); });
+        if (!e) {
+            const int mode = decrypt ? pl->dec_mode : 0;
+            e = timed_launch(pl, PMK_KERNEL_UNPACK, stream, [&] { return launch_unpack(r, out, mode, stream); });
+        }
     }
     return e;
 }
@@ -671,6 +683,16 @@ int pmk_get_window(const pmk_ctx *ctx, uint32_t bits) {
     if (!ctx) return PMK_EINVAL;
     const int c = class_for_bits(bits);
     return c < 0 ? PMK_EUNSUPPORTED : ctx->win[c];
+}
+
+int pmk_set_grid_limit(pmk_ctx *ctx, uint32_t waves) {
+    if (!ctx) return PMK_EINVAL;
+    if (ctx->server) return set_err(ctx, PMK_EBUSY, "the grid limit is fixed while a server runs");
+    if (ctx->grid_limit != waves) {
+        ctx->grid_limit = waves;
+        ctx->epoch++;  // captured graphs hold the old grids
+    }
+    return PMK_OK;
 }
 
 }  // extern "C"
@@ -837,7 +859,7 @@ int pmk_miller_rabin(pmk_ctx *ctx, uint32_t bits, const uint32_t *d_cand, uint32
     if (!d_bases || rounds == 0 || rounds > 256) return set_err(ctx, PMK_EINVAL, "need 1..256 bases per candidate");
     const int win = ctx->win[c];
     const uint32_t units = (count + kTile - 1) / kTile;
-    const uint32_t grid = std::max<uint32_t>(1, std::min(units, mr_wave_slots(c, ctx->num_cus)));
+    const uint32_t grid = std::max<uint32_t>(1, persistent_grid(units, mr_wave_slots(c, ctx->num_cus), ctx->grid_limit));
     const uint64_t slot = mr_slot_words(c, win);
     const uint64_t need = (uint64_t)grid * slot;
     if (need > ctx->mr_cap) {
@@ -869,8 +891,11 @@ int pmk_plan_check(pmk_plan *pl, void *stream) {
         e = hipMemcpy(pl->d_err, &zero, sizeof zero, hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) return hip_err(ctx, e, "error flag read");
-    if (flag & 1u) return set_err(ctx, PMK_ERANGE, "a ciphertext block is not below its modulus");
+    // a non-invertible blinding block also leaves its chunk's plaintext out of
+    // range: the more specific status wins
     if (flag & 2u) return set_err(ctx, PMK_EBLIND, "a blinding block is not invertible modulo N");
+    if (flag & 1u)
+        return set_err(ctx, PMK_ERANGE, "a ciphertext block is not below its modulus or decrypts wider than its chunk");
     return PMK_OK;
 }
 
@@ -900,6 +925,128 @@ int pmk_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uint32
     if (rc == PMK_OK) rc = pmk_plan_check(pl, stream);
     pmk_plan_destroy(pl);
     return rc;
+}
+
+
+}  // extern "C"
+
+namespace {
+
+// Slices of a plan's chunk range for the host-buffer forms: `n` contiguous
+// runs of chunks of about equal message bytes, each planned on its own (its
+// offsets relative to the slice), device copies of the whole input and output,
+// and the pipeline's streams and events.
+int host_prepare(pmk_plan *pl, uint32_t n) {
+    pmk_ctx *ctx = pl->ctx;
+    if (!pl->hp_in) {
+        hipError_t e = dev_alloc(pl, &pl->hp_in, pl->ct_len);  // ct_len >= msg_len
+        if (e == hipSuccess) e = dev_alloc(pl, &pl->hp_out, pl->ct_len);
+        for (int i = 0; i < pmk_plan::kPipe && e == hipSuccess; ++i)
+            e = hipStreamCreateWithFlags(&pl->hp_stream[i], hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_err(ctx, e, "host pipeline setup");
+    }
+    if (pl->hp_n == n) return PMK_OK;
+    (void)hipDeviceSynchronize();
+    for (pmk_plan *s : pl->hp_sub) pmk_plan_destroy(s);
+    pl->hp_sub.clear();
+    for (hipEvent_t ev : pl->hp_ev) (void)hipEventDestroy(ev);
+    pl->hp_ev.clear();
+    pl->hp_chunk.assign(1, 0);
+    pl->hp_msg.assign(1, 0);
+    pl->hp_ct.assign(1, 0);
+    uint64_t off = 0, ct = 0;
+    for (uint64_t i = 0; i < pl->nchunks; ++i) {
+        const uint32_t kb = ctx->keys[pl->key_map[i]].bits / 8;
+        off += std::min<uint64_t>(kb - 4, pl->msg_len - off);
+        ct += kb;
+        const uint64_t s = pl->hp_chunk.size();  // next cut: s / n of the message
+        if (s < n && off * n >= s * pl->msg_len) {
+            pl->hp_chunk.push_back(i + 1);
+            pl->hp_msg.push_back(off);
+            pl->hp_ct.push_back(ct);
+        }
+    }
+    if (pl->hp_chunk.back() != pl->nchunks) {
+        pl->hp_chunk.push_back(pl->nchunks);
+        pl->hp_msg.push_back(off);
+        pl->hp_ct.push_back(ct);
+    }
+    const size_t ns = pl->hp_chunk.size() - 1;
+    pl->hp_n = 0;
+    for (size_t s = 0; s < ns; ++s) {
+        pmk_plan *sub = nullptr;
+        const int rc = pmk_plan_create(ctx, pl->key_map.data() + pl->hp_chunk[s], pl->hp_chunk[s + 1] - pl->hp_chunk[s],
+                                       pl->hp_msg[s + 1] - pl->hp_msg[s], &sub, nullptr);
+        if (rc != PMK_OK) return rc;
+        pl->hp_sub.push_back(sub);
+        for (int k = 0; k < 2; ++k) {
+            hipEvent_t ev = nullptr;
+            const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_err(ctx, e, "host pipeline events");
+            pl->hp_ev.push_back(ev);
+        }
+    }
+    pl->hp_n = n;
+    return PMK_OK;
+}
+
+// The paper's transfer / compute pipeline over host buffers: slice s is copied
+// to the device, computed, and copied back, on three streams, so copies of one
+// slice overlap the computation of another.
+int host_run(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, uint32_t slices) {
+    if (!pl) return PMK_EINVAL;
+    pmk_ctx *ctx = pl->ctx;
+    if (pl->msg_len == 0) return PMK_OK;
+    if (!in || !out) return set_err(ctx, PMK_EINVAL, "NULL buffer");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
+    // default: one slice for decryption (its copies are a tiny share of its
+    // time), up to four for encryption, each large enough to fill the chip
+    uint32_t n = slices ? slices : (decrypt ? 1u : (uint32_t)std::min<uint64_t>(4, std::max<uint64_t>(1, pl->nchunks / 65536)));
+    n = (uint32_t)std::min<uint64_t>(n, pl->nchunks);
+    int rc = host_prepare(pl, n);
+    if (rc != PMK_OK) return rc;
+    const bool blocks = decrypt && pl->dec_mode == 2;
+    const std::vector<uint64_t> &in_off = decrypt ? pl->hp_ct : pl->hp_msg;
+    const std::vector<uint64_t> &out_off = (decrypt && !blocks) ? pl->hp_msg : pl->hp_ct;
+    hipStream_t cin = pl->hp_stream[0], comp = pl->hp_stream[1], cout = pl->hp_stream[2];
+    hipError_t e = hipSuccess;
+    for (size_t s = 0; s < pl->hp_sub.size() && rc == PMK_OK && e == hipSuccess; ++s) {
+        pmk_plan *sub = pl->hp_sub[s];
+        sub->dec_mode = pl->dec_mode;
+        const uint64_t ib = in_off[s], il = in_off[s + 1] - ib, ob = out_off[s], ol = out_off[s + 1] - ob;
+        e = hipMemcpyAsync(pl->hp_in + ib, in + ib, il, hipMemcpyHostToDevice, cin);
+        if (e == hipSuccess) e = hipEventRecord(pl->hp_ev[2 * s], cin);
+        if (e == hipSuccess) e = hipStreamWaitEvent(comp, pl->hp_ev[2 * s], 0);
+        if (e != hipSuccess) break;
+        rc = decrypt ? pmk_decrypt_plan(sub, pl->hp_in + ib, pl->hp_out + ob, comp)
+                     : pmk_encrypt_plan(sub, pl->hp_in + ib, pl->hp_out + ob, comp);
+        if (rc != PMK_OK) break;
+        e = hipEventRecord(pl->hp_ev[2 * s + 1], comp);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cout, pl->hp_ev[2 * s + 1], 0);
+        if (e == hipSuccess) e = hipMemcpyAsync(out + ob, pl->hp_out + ob, ol, hipMemcpyDeviceToHost, cout);
+    }
+    const hipError_t e1 = hipStreamSynchronize(cin), e2 = hipStreamSynchronize(comp), e3 = hipStreamSynchronize(cout);
+    if (rc != PMK_OK) return rc;
+    if (e == hipSuccess) e = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
+    if (e != hipSuccess) return hip_err(ctx, e, "host pipeline");
+    // device-detected errors of every slice (PMK_EBLIND cannot occur here)
+    for (pmk_plan *sub : pl->hp_sub) {
+        const int c = pmk_plan_check(sub, comp);
+        if (c != PMK_OK) rc = rc == PMK_OK ? c : rc;
+    }
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pmk_encrypt_host(pmk_plan *plan, const uint8_t *msg, uint8_t *ct, uint32_t slices) {
+    return host_run(plan, 0, msg, ct, slices);
+}
+
+int pmk_decrypt_host(pmk_plan *plan, const uint8_t *ct, uint8_t *msg, uint32_t slices) {
+    return host_run(plan, 1, ct, msg, slices);
 }
 
 }  // extern "C"

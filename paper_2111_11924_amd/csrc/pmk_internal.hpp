@@ -34,6 +34,12 @@ PMK_HD constexpr int lanes_half(int bits) { return bits >= 6144 ? 4 : 1; }
 // number a tile's exponentiation takes L wavefronts of 64/L chunks each
 PMK_HD constexpr int chunks_per_tile(int) { return 64; }
 PMK_HD constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
+// grid of a persistent launch: one wave per unit, at most `slots` (the table
+// slots) and at most `cap` when a cap is set
+PMK_HD constexpr uint32_t persistent_grid(uint32_t units, uint32_t slots, uint32_t cap) {
+    const uint32_t g = units < slots ? units : slots;
+    return cap && cap < g ? cap : g;
+}
 
 // Default window width of the fixed-window exponentiation of the CRT halves
 // (the autotuner may pick another one up to kMaxWin).
@@ -122,12 +128,14 @@ struct ClassRun {
     uint32_t *table;           // per resident wave: window table scratch
     uint32_t slots_enc;        // wave slots in `table` for the encryption kernel
     uint32_t slots_dec;        // wave slots in `table` for the CRT-halves kernel
-    uint32_t *err;             // device error word: bit 0 block >= N, bit 1 blinding factor not invertible
+    uint32_t *err;             // device error word: bit 0 block out of range, bit 1 blinding factor not invertible
+    uint8_t *slot_err;         // optional, per descriptor slot: 1 where unpacking rejected the chunk
+    uint32_t grid_cap;         // 0, or the most resident waves a persistent launch may use
     int win;                   // window width of the CRT-halves exponentiation (3..6)
     // blinded PMKRSA (Sec. 3.1, Algorithm 1)
     const uint32_t *fin32;     // encryption: words of a factor v < N the result is multiplied by
-                               // (x^e v mod N; tile layout of y32), nullptr = 1
-    int exp_sel;               // CRT halves: 0 exponents d_p, d_q; 1 exponents p-1-d_p, q-1-d_q
+                               // (x^e v mod N; tile layout of y32), nullptr = 1; blinded decryption:
+                               // the packed c_R blocks
 };
 
 constexpr int kMaxWin = 6;
@@ -156,14 +164,13 @@ int launch_pack(const ClassRun &r, const uint8_t *src, int decrypt, void *stream
 int launch_encrypt(const ClassRun &r, void *stream);
 int launch_decrypt_halves(const ClassRun &r, void *stream);
 int launch_garner(const ClassRun &r, void *stream);
-// blinded decryption: half[h] = half[h] * half2[h] mod p_h for both primes
-int launch_blind_combine(const ClassRun &r, const uint32_t *half2, void *stream);
 // blinded decryption in one pass per prime: half[h] = (c*)^d_h c_R^(p_h-1-d_h) mod p_h
 // with c* at r.x32 and c_R at r.fin32; tables need 2 table_words_per_slot(cls, 1, win)
-// words per slot.  Only where joint_class(cls) holds.
-bool joint_class(int cls);
+// words per slot
 int launch_decrypt_joint(const ClassRun &r, void *stream);
-int launch_unpack(const ClassRun &r, uint8_t *dst, int decrypt, void *stream);
+// mode: 0 ciphertext blocks, 1 plaintext chunks (range-checked), 2 whole plaintext
+// blocks (range-checked); the checks read the packed input at r.x32 (and r.fin32)
+int launch_unpack(const ClassRun &r, uint8_t *dst, int mode, void *stream);
 // table words needed per wave slot for a class (decryption: at window width win)
 uint64_t table_words_per_slot(int cls, int decrypt, int win);
 // resident wave slots the persistent kernels of a class use

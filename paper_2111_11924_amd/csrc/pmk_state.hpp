@@ -36,6 +36,7 @@ struct pmk_ctx {
     std::set<pmk_plan *> plans;
     int win[kNumClasses] = {};  // CRT-halves window width per class
     uint32_t epoch = 0;         // bumped when a tuning choice changes (captured graphs go stale)
+    uint32_t grid_limit = 0;    // pmk_set_grid_limit: most resident waves per persistent launch (0: none)
     std::string device_name;
     pmk::Server *server = nullptr;  // request server (pmk_server_start), if running
     uint32_t *mr_table = nullptr;   // window tables of the primality tests
@@ -78,10 +79,19 @@ struct pmk_plan {
     static constexpr int kSide = 3;  // side streams of the batched sequence
     hipStream_t capture_stream = nullptr, side_stream[kSide] = {};
     hipEvent_t fork_event = nullptr, join_event[kSide] = {};
-    // blinded PMKRSA: second input tiles and second CRT halves (allocated on first use)
+    // blinded PMKRSA: tiles of the c_R blocks (allocated on first use)
     uint32_t *x32b[kNumClasses] = {};
-    uint32_t *half2[kNumClasses] = {};
     bool blind_ready = false;
+    int dec_mode = 1;  // unpack mode of decryptions: 1 plaintext chunks, 2 whole blocks
+    // host-buffer forms (pmk_encrypt_host / pmk_decrypt_host), made on first use
+    std::vector<uint32_t> key_map;      // the chunk-to-key map the plan was made from
+    uint8_t *hp_in = nullptr, *hp_out = nullptr;  // device copies of the whole input / output
+    std::vector<pmk_plan *> hp_sub;     // one plan per slice of the chunk range
+    uint32_t hp_n = 0;                  // slice count hp_sub was made for
+    std::vector<uint64_t> hp_chunk, hp_msg, hp_ct;  // slice boundaries: chunk, message and ciphertext offsets
+    static constexpr int kPipe = 3;     // streams: host-to-device copies, compute, device-to-host copies
+    hipStream_t hp_stream[kPipe] = {};
+    std::vector<hipEvent_t> hp_ev;      // per slice: input copied, slice computed
 };
 
 namespace pmk {

@@ -2,7 +2,7 @@
 // requests of any size against the context's device-resident key table, with
 // continuous tile-level batching.  The paper runs its chunk loops in parallel
 // and streams data through a transfer/compute pipeline (Sec. 3.1, Algorithm 1,
-// and the implementation notes of Sec. 4); here each request's chunks join
+// and the implementation steps of Sec. 3.3); here each request's chunks join
 // batching rounds as soon as the request is admitted, and a round mixes the
 // chunks of every in-flight request (chunks under one key share tiles).
 //
@@ -110,8 +110,10 @@ struct RoundPlan {
     uint64_t cap_tiles[kNumClasses] = {};
     ChunkDesc *desc[kNumClasses] = {};
     uint32_t *tkey[kNumClasses] = {};
+    uint8_t *slot_err[kNumClasses] = {};  // decryption: chunks rejected by unpacking, per slot
     std::vector<ChunkDesc> h_desc[kNumClasses];
     std::vector<uint32_t> h_tkey[kNumClasses];
+    std::vector<Request *> h_req[kNumClasses];  // request of each descriptor slot (nullptr: padding)
 };
 
 // Per-round bookkeeping: which chunks of which request went into the round.
@@ -190,6 +192,8 @@ hipError_t ensure_class(Server *sv, RoundPlan &R, int c, uint64_t tiles) {
     if (e == hipSuccess) e = grow_buffer(&R.pl, (void **)&r.y32, cap, t * g.S * cpt * sizeof(uint32_t));
     cap = 0;
     if (e == hipSuccess) e = grow_buffer(&R.pl, (void **)&r.half, cap, t * 2 * g.nlh * cpt * sizeof(uint32_t));
+    cap = 0;
+    if (e == hipSuccess) e = grow_buffer(&R.pl, (void **)&R.slot_err[c], cap, t * cpt);
     if (e == hipSuccess) R.cap_tiles[c] = t;
     r.desc = R.desc[c];
     r.tile_key = R.tkey[c];
@@ -200,11 +204,11 @@ hipError_t ensure_class(Server *sv, RoundPlan &R, int c, uint64_t tiles) {
 // Returns a hipError_t.
 int launch_round(Server *sv, RoundPlan &R, int decrypt, const std::vector<Taken> &taken) {
     pmk_ctx *ctx = sv->ctx;
-    // chunks grouped per key, in request order
-    std::unordered_map<uint32_t, std::vector<ChunkDesc>> per_key;
+    // chunks grouped per key, in request order (with the request of each)
+    std::unordered_map<uint32_t, std::vector<std::pair<ChunkDesc, Request *>>> per_key;
     std::vector<uint32_t> key_order;
     for (const Taken &t : taken) {
-        const Request *q = t.req;
+        Request *q = t.req;
         for (uint64_t i = t.first; i < t.first + t.count; ++i) {
             const Chunk &ch = q->chunks[i];
             ChunkDesc d;
@@ -216,14 +220,15 @@ int launch_round(Server *sv, RoundPlan &R, int decrypt, const std::vector<Taken>
             auto it = per_key.find(ch.key);
             if (it == per_key.end()) {
                 key_order.push_back(ch.key);
-                it = per_key.emplace(ch.key, std::vector<ChunkDesc>()).first;
+                it = per_key.emplace(ch.key, std::vector<std::pair<ChunkDesc, Request *>>()).first;
             }
-            it->second.push_back(d);
+            it->second.emplace_back(d, q);
         }
     }
     for (int c = 0; c < kNumClasses; ++c) {
         R.h_desc[c].clear();
         R.h_tkey[c].clear();
+        R.h_req[c].clear();
         R.pl.runs[c].ntiles = 0;
         R.pl.runs[c].count = 0;
     }
@@ -235,8 +240,11 @@ int launch_round(Server *sv, RoundPlan &R, int decrypt, const std::vector<Taken>
         R.pl.runs[c].count += (uint32_t)list.size();
         for (size_t i = 0; i < list.size(); i += cpt) {
             R.h_tkey[c].push_back(slot);
-            for (size_t l = 0; l < cpt; ++l)
-                R.h_desc[c].push_back(i + l < list.size() ? list[i + l] : ChunkDesc{0, 0, slot, 0});
+            for (size_t l = 0; l < cpt; ++l) {
+                const bool real = i + l < list.size();
+                R.h_desc[c].push_back(real ? list[i + l].first : ChunkDesc{0, 0, slot, 0});
+                R.h_req[c].push_back(real ? list[i + l].second : nullptr);
+            }
         }
     }
     uint32_t units = 0;  // work units of the wide encryption kernel
@@ -249,6 +257,11 @@ int launch_round(Server *sv, RoundPlan &R, int decrypt, const std::vector<Taken>
         r.ntiles = (uint32_t)tiles;
         r.keys = ctx->d_keys[c];
         r.err = R.pl.d_err;
+        r.slot_err = decrypt ? R.slot_err[c] : nullptr;
+        if (decrypt) {
+            e = hipMemsetAsync(R.slot_err[c], 0, R.h_desc[c].size(), sv->stream);
+            if (e != hipSuccess) return (int)e;
+        }
         r.slots_enc = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 0, ctx->num_cus), exp_units(c, 0, r.ntiles)));
         r.slots_dec = std::max<uint32_t>(1, std::min<uint64_t>(wave_slots(c, 1, ctx->num_cus), exp_units(c, 1, r.ntiles)));
         if (is_wide_class(c)) units += exp_units(c, 0, r.ntiles);
@@ -268,15 +281,20 @@ int launch_round(Server *sv, RoundPlan &R, int decrypt, const std::vector<Taken>
     return batch_sequence(&R.pl, decrypt, sv->d_slab, sv->d_slab, sv->stream);
 }
 
-// Host check of a decryption request's blocks against their moduli (used to
-// name the request when a round's device flag reports a block >= N).
-bool blocks_below_moduli(const pmk_ctx *ctx, const Request *q, const std::vector<std::vector<uint8_t>> &nbe) {
-    for (const Chunk &ch : q->chunks) {
-        const std::vector<uint8_t> &n = nbe[ch.key];
-        if (std::memcmp(q->in + ch.ct_off, n.data(), n.size()) >= 0) return false;
+// After a round whose device flag is set: the requests of the decryption
+// chunks that unpacking rejected (block out of range) get PMK_ERANGE.
+hipError_t name_rejected(RoundPlan &R) {
+    std::vector<uint8_t> h;
+    for (int c = 0; c < kNumClasses; ++c) {
+        const size_t n = R.h_req[c].size();
+        if (!n || !R.pl.runs[c].ntiles) continue;
+        h.resize(n);
+        const hipError_t e = hipMemcpy(h.data(), R.slot_err[c], n, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return e;
+        for (size_t i = 0; i < n; ++i)
+            if (h[i] && R.h_req[c][i]) R.h_req[c][i]->status = PMK_ERANGE;
     }
-    (void)ctx;
-    return true;
+    return hipSuccess;
 }
 
 void finish(Server *sv, Request *q, int status) {
@@ -372,8 +390,7 @@ void fail_all(Server *sv, int status) {
 
 // Waits for the oldest launched round and completes what it finished.
 // Returns a hipError_t.
-int complete_round(Server *sv, std::vector<std::vector<uint8_t>> &nbe) {
-    pmk_ctx *ctx = sv->ctx;
+int complete_round(Server *sv) {
     Round r = std::move(sv->flight.front());
     sv->flight.pop_front();
     int e = (int)hipEventSynchronize(sv->round_done[r.slot]);
@@ -382,6 +399,7 @@ int complete_round(Server *sv, std::vector<std::vector<uint8_t>> &nbe) {
     if (!e && !r.taken[1].empty()) {
         e = (int)hipMemcpy(&flag, sv->rp[r.slot][1].pl.d_err, sizeof flag, hipMemcpyDeviceToHost);
         if (!e && flag) e = (int)hipMemset(sv->rp[r.slot][1].pl.d_err, 0, sizeof flag);
+        if (!e && flag) e = (int)name_rejected(sv->rp[r.slot][1]);
     }
     if (e) return e;
     uint64_t chunks = 0;
@@ -395,17 +413,6 @@ int complete_round(Server *sv, std::vector<std::vector<uint8_t>> &nbe) {
         sv->stats.rounds++;
         sv->stats.chunks += chunks;
         sv->stats.busy_ns += now_ns() - r.t0;
-    }
-    if (flag) {
-        for (const Taken &t : r.taken[1]) {
-            for (const Chunk &ch : t.req->chunks)
-                if (nbe[ch.key].empty()) {
-                    const std::vector<uint32_t> &n = ctx->keys[ch.key].n;
-                    for (size_t w = n.size(); w-- > 0;)
-                        for (int b = 3; b >= 0; --b) nbe[ch.key].push_back((uint8_t)(n[w] >> (8 * b)));
-                }
-            if (!blocks_below_moduli(ctx, t.req, nbe)) t.req->status = PMK_ERANGE;
-        }
     }
     // completed requests: results to the host, staging released
     std::vector<Request *> still;
@@ -427,8 +434,6 @@ int complete_round(Server *sv, std::vector<std::vector<uint8_t>> &nbe) {
 void run(Server *sv) {
     pmk_ctx *ctx = sv->ctx;
     (void)hipSetDevice(ctx->device);
-    // big-endian moduli for the host-side range check
-    std::vector<std::vector<uint8_t>> nbe(ctx->keys.size());
     std::vector<Taken> round[2];
     for (;;) {
         {
@@ -475,7 +480,7 @@ void run(Server *sv) {
             continue;
         }
         if (launched && sv->flight.size() < depth) continue;  // queue a second round first if there is work
-        if (complete_round(sv, nbe)) fail_all(sv, PMK_EDEVICE);
+        if (complete_round(sv)) fail_all(sv, PMK_EDEVICE);
     }
 }
 

@@ -5,6 +5,11 @@ several 64-chunk tiles per size class plus a ragged last tile; the 100 MiB
 workload is checked on sampled chunks against the oracle and in full through
 the decrypt(encrypt(m)) = m identity (Sec. 1.1 correctness of RSA).
 """
+import json
+import os
+from concurrent.futures import ThreadPoolExecutor
+from functools import lru_cache
+
 import numpy as np
 import pytest
 
@@ -12,6 +17,15 @@ import oracle
 from paper_2111_11924_amd import binding, inputs
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@lru_cache(maxsize=1)
+def fixture_keys():
+    """The seeded 2048-8192-bit key pairs stored in tests/golden/large_keys.json."""
+    with open(os.path.join(GOLDEN, "large_keys.json")) as f:
+        return {k["bits"]: inputs.RsaKey.from_json(k) for k in json.load(f)["keys"]}
 
 
 @pytest.fixture(scope="module")
@@ -158,6 +172,9 @@ def test_block_not_below_modulus_is_reported(torch, ctx):
     finally:
         plan.close()
     assert (pt[:60] == msg[:60]).all() and (pt[120:] == msg[120:]).all()
+    assert not pt[60:120].any()  # the rejected chunk is written as zeros
+    ref, rc = oracle.decrypt(T, bad, len(msg), km)
+    assert rc == -3 and (pt == ref).all()
 
 
 def test_empty_message(torch, ctx):
@@ -428,9 +445,10 @@ def test_large_and_small_classes_mixed_batch_and_blinded(torch, ctx):
 # The window schedule is read from the private exponents themselves.  Key
 # material with CRT exponents of unusual shape -- zero, one, a single bit, zero
 # runs longer than the 64 exponent bits a step reads ahead, a set bit only at
-# the top -- is still a valid input to the CRT route (m = C^d' mod N with
-# d' = dp mod p-1, dq mod q-1), so the GPU must match the oracle's CRT route
-# bit for bit on every block, and the blinded form (exponent p-1-dp) likewise.
+# the top -- is still a valid input to the CRT route (the unique m < N with
+# m = C^dp mod p and m = C^dq mod q), so the GPU must match the oracle's CRT
+# route bit for bit on every block.  Such blocks decrypt to values as wide as N,
+# so the plan writes whole blocks (PMK_DEC_BLOCKS) and every bit is compared.
 
 def _special_exponents(h):
     return [
@@ -443,9 +461,23 @@ def _special_exponents(h):
     ]
 
 
-@pytest.mark.parametrize("bits", [1024, 2048, 3072, 6144])
+def base_key(bits):
+    """One key pair of the given size: the stored seeded keys for 2048 bits and
+    up (large primes take minutes to find), generated below that."""
+    if bits >= 2048:
+        return fixture_keys()[bits]
+    return inputs.make_keys([bits], 850 + bits // 64)[0]
+
+
+def oracle_many(fn, jobs):
+    """fn over jobs on the host cores (the oracle's calls release the GIL)."""
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(fn, jobs))
+
+
+@pytest.mark.parametrize("bits", [1024, 2048, 3072, 4096, 6144, 8192])
 def test_unusual_crt_exponents(torch, ctx, bits):
-    base = inputs.make_keys([bits], 850 + bits // 64)[0]
+    base = base_key(bits)
     h = bits // 2
     keys = []
     for dp, dq in _special_exponents(h):
@@ -464,29 +496,29 @@ def test_unusual_crt_exponents(torch, ctx, bits):
     plan = ctx.plan(km, msg_len)
     T = oracle.KeyTable(keys)
     try:
-        d_pt = plan.decrypt(dev(torch, ct))
+        plan.set_decrypt_output(binding.PMK_DEC_BLOCKS)
+        d_m = plan.decrypt(dev(torch, ct))
         assert plan.check() == binding.PMK_OK
-        pt = host(d_pt, msg_len)
-        # every block up to 2048 bits; above, sampled blocks of every key
-        # (first, second, last of the full tile, the ragged tile's first and last)
-        rows = range(len(km)) if bits <= 2048 else \
-            [k * per_key + j for k in range(len(keys)) for j in (0, 1, 63, 64, per_key - 1)]
-        for i in rows:
-            c = int.from_bytes(bytes(ct[i * kb:(i + 1) * kb]), "big")
-            m = oracle.rsa_int(T, int(km[i]), "crt", c) % (1 << (8 * (kb - 4)))
-            got = int.from_bytes(bytes(pt[i * (kb - 4):(i + 1) * (kb - 4)]), "big")
-            assert got == m, f"block {i} (key {km[i]})"
+        got = host(d_m, plan.ct_len)
     finally:
         plan.close()
+    # every block up to 2048 bits; above, sampled blocks of every key
+    # (first, second, last of the full tile, the ragged tile's first and last)
+    rows = list(range(len(km))) if bits <= 2048 else \
+        [k * per_key + j for k in range(len(keys)) for j in (0, 1, 63, 64, per_key - 1)]
+    ref = oracle_many(lambda i: oracle.rsa_int(T, int(km[i]), "crt",
+                                               int.from_bytes(bytes(ct[i * kb:(i + 1) * kb]), "big")), rows)
+    for i, m in zip(rows, ref):
+        assert bytes(got[i * kb:(i + 1) * kb]) == m.to_bytes(kb, "big"), f"block {i} (key {km[i]})"
 
 
-@pytest.mark.parametrize("bits", [1024, 2048, 3072])
+@pytest.mark.parametrize("bits", [1024, 2048, 3072, 4096, 6144, 8192])
 def test_blinded_decryption_with_unusual_exponents(torch, ctx, bits):
-    """Blinded decryption (one chain for c* and c_R up to 2048 bits, two passes
-    above) with private exponents of unusual shape: d below both primes, so
-    dp = dq = d keeps the shape, and the second exponent p-1-d is dense.
-    Against the oracle's blinded route m = (c*)^d (c_R^d)^-1 mod N."""
-    base = inputs.make_keys([bits], 850 + bits // 64)[0]
+    """Blinded decryption (c* and c_R in one squaring chain per prime) with
+    private exponents of unusual shape: d below both primes, so dp = dq = d
+    keeps the shape, and the second exponent p-1-d is dense.  Whole blocks
+    against the oracle's blinded route m = (c*)^d (c_R^d)^-1 mod N."""
+    base = base_key(bits)
     h = bits // 2
     exps = [1, 3, (1 << 70) + 5, (1 << (h - 3)) - 1, (1 << (h - 2)) | 1, (1 << 100) | (1 << 37)]
     keys = []
@@ -509,15 +541,18 @@ def test_blinded_decryption_with_unusual_exponents(torch, ctx, bits):
     plan = ctx.plan(km, msg_len)
     T = oracle.KeyTable(keys)
     try:
-        d_pt = plan.decrypt_blinded(dev(torch, cs), dev(torch, cr))
+        plan.set_decrypt_output(binding.PMK_DEC_BLOCKS)
+        d_m = plan.decrypt_blinded(dev(torch, cs), dev(torch, cr))
         assert plan.check() == binding.PMK_OK
-        pt = host(d_pt, msg_len)
-        rows = [k * per_key + j for k in range(len(keys)) for j in (0, 1, 63, 64, per_key - 1)]
-        for i in rows:
-            c1 = int.from_bytes(bytes(cs[i * kb:(i + 1) * kb]), "big")
-            c2 = int.from_bytes(bytes(cr[i * kb:(i + 1) * kb]), "big")
-            m, _ = oracle.blind_int(T, int(km[i]), "dec", c1, c2)
-            got = int.from_bytes(bytes(pt[i * (kb - 4):(i + 1) * (kb - 4)]), "big")
-            assert got == m % (1 << (8 * (kb - 4))), f"block {i} (key {km[i]})"
+        got = host(d_m, plan.ct_len)
     finally:
         plan.close()
+    rows = [k * per_key + j for k in range(len(keys)) for j in (0, 1, 63, 64, per_key - 1)]
+
+    def ref(i):
+        c1 = int.from_bytes(bytes(cs[i * kb:(i + 1) * kb]), "big")
+        c2 = int.from_bytes(bytes(cr[i * kb:(i + 1) * kb]), "big")
+        return oracle.blind_int(T, int(km[i]), "dec", c1, c2)[0]
+
+    for i, m in zip(rows, oracle_many(ref, rows)):
+        assert bytes(got[i * kb:(i + 1) * kb]) == m.to_bytes(kb, "big"), f"block {i} (key {km[i]})"

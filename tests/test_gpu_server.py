@@ -151,11 +151,23 @@ def test_errors_are_per_request(ctx, keys, table):
         broken = ct.copy()
         nb = keys[1].bits // 8
         broken[:nb] = np.frombuffer(keys[1].n.to_bytes(nb, "big"), np.uint8)
-        t_bad, _ = srv.submit(binding.PMK_OP_DECRYPT, broken, len(msg), km)
+        t_bad, out_bad = srv.submit(binding.PMK_OP_DECRYPT, broken, len(msg), km)
+        # a block below its modulus whose plaintext is wider than the chunk
+        # (N - 1 decrypts to itself) fails its request too, in the same round
+        wide = ct.copy()
+        nb2 = keys[int(km[1])].bits // 8
+        off2 = nb
+        wide[off2:off2 + nb2] = np.frombuffer((keys[int(km[1])].n - 1).to_bytes(nb2, "big"), np.uint8)
+        t_wide, out_wide = srv.submit(binding.PMK_OP_DECRYPT, wide, len(msg), km)
         t_ok, out_ok = srv.submit(binding.PMK_OP_DECRYPT, ct, len(msg), km)
         assert srv.wait(t_bad)["status"] == binding.PMK_ERANGE
+        assert srv.wait(t_wide)["status"] == binding.PMK_ERANGE
         assert srv.wait(t_ok)["status"] == binding.PMK_OK
         assert (out_ok == msg).all()
+        # the rejected chunks are zeros, the rest decrypted: the oracle's bytes
+        for data, out in ((broken, out_bad), (wide, out_wide)):
+            ref, rc = oracle.decrypt(table, data, len(msg), km)
+            assert rc == -3 and (out == ref).all()
         # an empty request completes at once
         t_e, out_e = srv.submit(binding.PMK_OP_ENCRYPT, np.zeros(0, np.uint8), 0, np.zeros(0, np.uint32))
         assert srv.wait(t_e)["status"] == binding.PMK_OK and len(out_e) == 0
