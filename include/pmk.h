@@ -310,6 +310,26 @@ int pmk_encrypt_host(pmk_plan *plan, const uint8_t *msg, uint8_t *ct, uint32_t s
 int pmk_decrypt_host(pmk_plan *plan, const uint8_t *ct, uint8_t *msg, uint32_t slices);
 
 /*
+ * For callers that cannot allocate while they run (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pmk_decrypt
+ * with the same arguments, results and errors, but calling no hipMalloc,
+ * hipFree or other allocating routine.  Every device buffer its kernels use
+ * (chunk descriptors, packed words, CRT half results, window tables, the
+ * error word) lives in one fixed device array of 64 MiB that the library
+ * holds on each GPU it runs on until the process ends; the host-side planning
+ * uses buffers made at pmk_create / pmk_keys_load.  Limits: at most 65,536
+ * chunks, and the chunk data plus at least one window table per size class
+ * must fit the 64 MiB (PMK_ESIZE, before anything is launched, otherwise);
+ * fewer table slots than pmk_decrypt's may run the exponentiation in more
+ * rounds.  d_ct / d_msg are device memory, key_map host memory.  Synchronous
+ * on `stream`.  Every call on one GPU, from any context or thread, shares that
+ * GPU's array and keeps nothing from the previous call: calls that overlap on
+ * one GPU race.
+ */
+int pmk_decrypt_noalloc(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uint32_t *key_map,
+                        uint64_t nchunks, uint8_t *d_msg, uint64_t msg_len, void *stream);
+
+/*
  * Multi-prime keys (Sec. 2.1, the multi-prime variant: N is the product of b
  * distinct primes of bits/b bits, and decryption runs b exponentiations modulo
  * the primes, on numbers of bits/b bits, then one recombination; against two

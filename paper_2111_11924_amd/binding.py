@@ -138,6 +138,7 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "pmk_encrypt": (C.c_int, [vp, vp, u64, U32P, u64, vp, u64, vp]),
         "pmk_decrypt": (C.c_int, [vp, vp, u64, U32P, u64, vp, u64, vp]),
         "pmk_encrypt_host": (C.c_int, [vp, vp, vp, u32]),
+        "pmk_decrypt_noalloc": (C.c_int, [vp, vp, u64, U32P, u64, vp, u64, vp]),
         "pmk_decrypt_host": (C.c_int, [vp, vp, vp, u32]),
         "pmk_mp_key_check": (C.c_int, [C.POINTER(pmk_key_mp), C.c_char_p, C.c_size_t]),
         "pmk_mp_keys_load": (C.c_int, [vp, C.POINTER(pmk_key_mp), u32]),
@@ -379,6 +380,12 @@ def pmk_decrypt(ctx: int, d_ct, ct_len: int, key_map, d_msg, msg_len: int, strea
     km = _map_array(key_map)
     return load_library().pmk_decrypt(ctx, _dev_ptr(d_ct), int(ct_len), km.ctypes.data_as(U32P), len(km),
                                       _dev_ptr(d_msg), int(msg_len), _stream(stream))
+
+
+def pmk_decrypt_noalloc(ctx: int, d_ct, ct_len: int, key_map, d_msg, msg_len: int, stream=None) -> int:
+    km = _map_array(key_map)
+    return load_library().pmk_decrypt_noalloc(ctx, _dev_ptr(d_ct), int(ct_len), km.ctypes.data_as(U32P), len(km),
+                                              _dev_ptr(d_msg), int(msg_len), _stream(stream))
 
 
 def _host_ptr(x) -> Optional[int]:

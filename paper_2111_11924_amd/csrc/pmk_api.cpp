@@ -137,6 +137,9 @@ int pmk_create(int device, pmk_ctx **out) {
     ctx->num_cus = prop.multiProcessorCount;
     ctx->device_name = prop.gcnArchName;
     for (int c = 0; c < kNumClasses; ++c) ctx->win[c] = window_for(kClassBits[c] / 2);
+    ctx->err.reserve(600);  // messages (below 512 bytes) are then stored without allocating
+    // the allocation-free entry point reports it if its scratch is unavailable
+    (void)noalloc_setup(ctx);
     *out = ctx;
     return PMK_OK;
 }
@@ -152,6 +155,7 @@ void pmk_destroy(pmk_ctx *ctx) {
     for (auto &p : ctx->d_mp_keys)
         if (p) (void)hipFree(p);
     if (ctx->mp_scratch) (void)hipFree(ctx->mp_scratch);
+    if (ctx->na_host) (void)hipHostFree(ctx->na_host);
     delete ctx;
 }
 
@@ -212,6 +216,7 @@ int pmk_keys_load(pmk_ctx *ctx, const pmk_key *keys, uint32_t nkeys) {
     }
     ctx->keys.swap(slots);
     ctx->err.clear();
+    if (noalloc_keys(ctx) != PMK_OK) return set_err(ctx, PMK_ENOMEM, "host planning buffers");
     return PMK_OK;
 }
 

@@ -13,6 +13,10 @@
 
 namespace pmk {
 struct Server;
+// pmk_decrypt_noalloc: size of the fixed device array holding all its scratch
+// (one per GPU, for the life of the process), and its chunk limit
+constexpr uint64_t kNoAllocScratchBytes = 64ull << 20;
+constexpr uint64_t kNoAllocMaxChunks = 65536;
 }
 using pmk::ClassRun;
 using pmk::kNumClasses;
@@ -46,6 +50,12 @@ struct pmk_ctx {
     uint32_t *d_mp_keys[2] = {};
     void *mp_scratch = nullptr;  // device arena of pmk_mp_decrypt (grown on demand)
     uint64_t mp_scratch_bytes = 0;
+    // pmk_decrypt_noalloc: the device address of this GPU's static scratch
+    // (taken at pmk_create) and host planning buffers sized at pmk_keys_load
+    uint8_t *na_scratch = nullptr;
+    std::vector<uint32_t> na_bits, na_count, na_tile;  // per key: modulus bits, chunks, first tile
+    uint8_t *na_host = nullptr;  // pinned mirror of the scratch's descriptor region
+    uint64_t na_host_bytes = 0;
 };
 
 struct TimedLaunch {
@@ -125,6 +135,11 @@ hipError_t ensure_batch_table(pmk_plan *pl);
 int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, void *stream);
 // Stops and frees the request server of a context (server.cpp).
 void server_shutdown(pmk_ctx *ctx);
+// pmk_decrypt_noalloc set-up (noalloc.hip): the device address of the static
+// scratch on ctx->device (current), once per device; and the host planning
+// buffers for the loaded key table.  Return a status.
+int noalloc_setup(pmk_ctx *ctx);
+int noalloc_keys(pmk_ctx *ctx);
 
 // Runs one launcher; with profiling on, brackets it with events on `stream`.
 template <typename F>
