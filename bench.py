@@ -47,6 +47,17 @@ def enc_products(bits: int, e: int = 65537) -> int:
     return ((e.bit_length() - 1) + (bin(e).count("1") - 1) + 2) * mm_products(bits // 32)
 
 
+def joint_products(bits: int) -> int:
+    """Canonical products of one prime's blinded decryption in one chain,
+    (c*)^dp c_R^(p-1-dp) mod p, counted like half_products at window 5: both
+    inputs reduced into Montgomery form and tabled (2 x 30 products), one
+    squaring chain of 5 (W - 1) squarings with a window product for each of the
+    two exponents per 5 bits, the c_R mod p check and the final conversion."""
+    s_h = bits // 64
+    W = -(-(bits // 2) // 5)
+    return (2 * 30 + 4 + 5 * (W - 1) + 2 * (W - 1) + 1) * mm_products(s_h)
+
+
 # Peak of the VALU 32x32->64 multiply-add (v_mad_u64_u32): one per lane per
 # clock, 64 lanes per compute unit, 256 compute units, 2.4 GHz.
 PEAK_MAD_PER_S = 256 * 64 * 2.4e9
@@ -116,6 +127,102 @@ def cpu_baseline(keys, msg, km, sample_chunks: int):
         "single_thread": {"dec_modexp_per_s": n1 / td1, "enc_modexp_per_s": n1 / te1,
                           "dec_MiBps": nbytes1 / td1 / 2**20, "enc_MiBps": nbytes1 / te1 / 2**20},
     }
+
+
+def blinding_blocks(keys, km, seed: int):
+    """Blinding blocks for a throughput pass: per chunk kb random bytes with the
+    top byte zero, so r < 2^(bits-8) < N; r shares a prime with N with
+    probability below 2^-1000 (the GPU would report PMK_EBLIND).  Vectorised
+    stand-in for inputs.make_blinding, whose per-chunk gcd is too slow for
+    400,000 chunks; the timing does not depend on the values."""
+    import numpy as np
+
+    kb = np.array([k.bits // 8 for k in keys])[km]
+    g = np.random.Generator(np.random.PCG64(seed * 1000 + 5))
+    blk = g.integers(0, 256, size=int(kb.sum()), dtype=np.uint8)
+    starts = np.concatenate([[0], np.cumsum(kb)[:-1]])
+    blk[starts] = 0
+    return blk
+
+
+def blinded_measure(plan, d_msg, keys, km, seed: int, steps: int, warmup: int):
+    """Blinded PMKRSA (Sec. 3.1) over the whole workload: c* = (r m)^e and
+    c_R = r^e, then m = (c*)^d (c_R^d)^-1 through one squaring chain per prime;
+    event-timed per call on the current stream, the one-chain kernel timed per
+    launch in one extra profiled step."""
+    import numpy as np
+    import torch
+
+    from paper_2111_11924_amd import binding
+
+    stream = torch.cuda.current_stream()
+    d_r = torch.from_numpy(blinding_blocks(keys, km, seed)).to("cuda")
+    n = plan.ct_len
+    d_cs = torch.empty(n, dtype=torch.uint8, device="cuda")
+    d_cr = torch.empty(n, dtype=torch.uint8, device="cuda")
+    d_pt = torch.empty(plan.msg_len, dtype=torch.uint8, device="cuda")
+    enc = lambda: binding.pmk_encrypt_blinded_plan(plan.handle, d_msg, d_r, d_cs, d_cr, stream, plan.ctx.handle)
+    dec = lambda: binding.pmk_decrypt_blinded_plan(plan.handle, d_cs, d_cr, d_pt, stream, plan.ctx.handle)
+    for _ in range(warmup):
+        enc()
+        dec()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        enc()
+        ev[k][1].record(stream)
+        dec()
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    enc_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    dec_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    ok = plan.check(stream) == binding.PMK_OK and torch.equal(d_pt, d_msg)
+    plan.profile(True)
+    dec()
+    torch.cuda.synchronize()
+    joint_ms, joint_n = plan.kernel_time(binding.PMK_KERNEL_CRT_HALVES)
+    plan.profile(False)
+    bits_of = np.array([k.bits for k in keys])[km]
+    ub, uc = np.unique(bits_of, return_counts=True)
+    work = sum(2 * joint_products(int(b)) * int(c) for b, c in zip(ub, uc))
+    mib = plan.msg_len / 2**20
+    return {
+        "enc_ms": enc_ms, "dec_ms": dec_ms, "enc_MiBps": mib / (enc_ms / 1e3), "dec_MiBps": mib / (dec_ms / 1e3),
+        "dec_modexp_per_s": len(km) / (dec_ms / 1e3), "roundtrip_ok": bool(ok),
+        "roofline": {"bound": "alu", "kernel": "crt_halves_joint (one chain per prime)",
+                     "achieved": work / (joint_ms / max(joint_n, 1) / 1e3) / 1e12, "peak": PEAK_MAD_PER_S / 1e12,
+                     "unit": "Tmad/s", "frac": work / (joint_ms / max(joint_n, 1) / 1e3) / PEAK_MAD_PER_S,
+                     "work_per_launch": work, "avg_launch_ms": joint_ms / max(joint_n, 1)},
+    }
+
+
+def host_measure(plan, msg, reps: int = 3):
+    """End-to-end rates through the host-buffer forms (pmk_encrypt_host /
+    pmk_decrypt_host, default slicing): pinned host message in, pinned host
+    ciphertext out, and back; wall-clocked per call."""
+    import numpy as np
+    import torch
+
+    from paper_2111_11924_amd import binding
+
+    h_msg = torch.from_numpy(msg).pin_memory()
+    h_ct = torch.empty(plan.ct_len, dtype=torch.uint8).pin_memory()
+    h_pt = torch.empty(len(msg), dtype=torch.uint8).pin_memory()
+    ok = plan.encrypt_host(h_msg, h_ct) == binding.PMK_OK and plan.decrypt_host(h_ct, h_pt) == binding.PMK_OK
+    te = td = 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        ok = ok and plan.encrypt_host(h_msg, h_ct) == binding.PMK_OK
+        t1 = time.perf_counter()
+        ok = ok and plan.decrypt_host(h_ct, h_pt) == binding.PMK_OK
+        t2 = time.perf_counter()
+        te += t1 - t0
+        td += t2 - t1
+    ok = ok and bool(np.array_equal(h_pt.numpy(), msg))
+    mib = len(msg) / 2**20
+    return {"enc_MiBps_e2e": mib * reps / te, "dec_MiBps_e2e": mib * reps / td, "enc_ms_e2e": te / reps * 1e3,
+            "dec_ms_e2e": td / reps * 1e3, "reps": reps, "host_buffers": "pinned", "ok": ok}
 
 
 def serve_measure(nreq: int, loads, seed: int = 5, staging_mib: int = 2048, round_chunks: int = 0,
@@ -361,6 +468,7 @@ def main() -> int:
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-blinded", action="store_true", help="skip the blinded PMKRSA pass after the timed steps")
     ap.add_argument("--config", type=int, default=4,
                     help="workload recipe (1-4; the JSON line's headline workload is 4)")
     ap.add_argument("--mode", choices=["plain", "batch"], default="plain",
@@ -551,6 +659,17 @@ def main() -> int:
     if args.config != 4:
         out["metric"] = f"CRT decrypt modexp/s, workload {w.name}"
         out["unit"] = "CRT decrypt modexp/s (whole encrypt+decrypt steps)"
+    # after the timed region: end-to-end rates from pinned host memory, and
+    # blinded PMKRSA over the same workload
+    e2e = host_measure(plan, msg)
+    out.update({k: v for k, v in e2e.items() if k.endswith("_e2e")})
+    out["e2e"] = {"reps": e2e["reps"], "host_buffers": e2e["host_buffers"], "ok": e2e["ok"],
+                  "form": "pmk_encrypt_host / pmk_decrypt_host (H2D, compute, D2H over slices)"}
+    ok = ok and e2e["ok"]
+    if not args.no_blinded and not batch:
+        bl = blinded_measure(plan, d_msg, keys, km, w.seed, max(2, min(args.steps, 5)), 1)
+        out["blinded"] = bl
+        ok = ok and bl["roundtrip_ok"]
     plan.close()
     ctx.close()
     if not args.no_serve and args.config == 4:
