@@ -450,6 +450,9 @@ def main() -> int:
     ap.add_argument("--autotune", action="store_true",
                     help="pick each class's CRT window by timing on this device first (pmk_autotune)")
     ap.add_argument("--window", type=int, default=0, help="fix the CRT window width of every class")
+    ap.add_argument("--lanes", type=int, nargs=2, default=None, metavar=("FILL", "TAIL"),
+                    help="lanes per number (1, 2, 4) of the CRT halves of an under-filled launch and of a "
+                         "short last round, every one-lane class")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the short serving pass that fills p99_request_ms")
     ap.add_argument("--paper-table", action="store_true",
@@ -469,6 +472,7 @@ def main() -> int:
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-blinded", action="store_true", help="skip the blinded PMKRSA pass after the timed steps")
+    ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end pass through host buffers")
     ap.add_argument("--config", type=int, default=4,
                     help="workload recipe (1-4; the JSON line's headline workload is 4)")
     ap.add_argument("--mode", choices=["plain", "batch"], default="plain",
@@ -548,7 +552,12 @@ def main() -> int:
             ctx.set_window(b, args.window)
     elif args.autotune:
         ctx.autotune()  # measured on this device (setup, outside the timed region)
+    if args.lanes:
+        for b in set(int(k.bits) for k in keys):
+            if b <= 4096:
+                ctx.set_lanes(b, args.lanes[0], args.lanes[1])
     windows = {int(b): ctx.window(int(b)) for b in sorted(set(int(k.bits) for k in keys))}
+    lanes = {int(b): ctx.lanes(int(b)) for b in sorted(set(int(k.bits) for k in keys))}
     plan = ctx.plan(km, len(msg))
     d_msg = torch.from_numpy(msg).to("cuda")
     d_ct = torch.empty(plan.ct_len, dtype=torch.uint8, device="cuda")
@@ -634,6 +643,7 @@ def main() -> int:
         "dec_ms_per_step": dec_ms / args.steps,
         "mode": args.mode,
         "crt_window": windows,
+        "tail_lanes": lanes,
         "step_ms_median": step_ms[len(step_ms) // 2],
         "step_ms_min": step_ms[0],
         "half_modexp_per_s": 2 * nchunks * args.steps / (dec_ms / 1e3),
@@ -661,11 +671,12 @@ def main() -> int:
         out["unit"] = "CRT decrypt modexp/s (whole encrypt+decrypt steps)"
     # after the timed region: end-to-end rates from pinned host memory, and
     # blinded PMKRSA over the same workload
-    e2e = host_measure(plan, msg)
-    out.update({k: v for k, v in e2e.items() if k.endswith("_e2e")})
-    out["e2e"] = {"reps": e2e["reps"], "host_buffers": e2e["host_buffers"], "ok": e2e["ok"],
-                  "form": "pmk_encrypt_host / pmk_decrypt_host (H2D, compute, D2H over slices)"}
-    ok = ok and e2e["ok"]
+    if not args.no_e2e:
+        e2e = host_measure(plan, msg)
+        out.update({k: v for k, v in e2e.items() if k.endswith("_e2e")})
+        out["e2e"] = {"reps": e2e["reps"], "host_buffers": e2e["host_buffers"], "ok": e2e["ok"],
+                      "form": "pmk_encrypt_host / pmk_decrypt_host (H2D, compute, D2H over slices)"}
+        ok = ok and e2e["ok"]
     if not args.no_blinded and not batch:
         bl = blinded_measure(plan, d_msg, keys, km, w.seed, max(2, min(args.steps, 5)), 1)
         out["blinded"] = bl

@@ -224,6 +224,24 @@ int pmk_set_window(pmk_ctx *ctx, uint32_t bits, int win);
 int pmk_get_window(const pmk_ctx *ctx, uint32_t bits);
 
 /*
+ * Tuning: lanes per number of the CRT exponentiations (the parallel loops of
+ * Algorithm 1 over the chunks) of the size class holding `bits`-bit moduli,
+ * where a launch would leave the chip mostly idle.  A class whose CRT halves
+ * run one lane per number (128- to 4096-bit keys) runs
+ *   - a launch that fills at most half of one round of resident waves with
+ *     `fill_lanes` lanes per number, and
+ *   - the last partial round of a launch, when it holds at most half a round,
+ *     with `tail_lanes` lanes per number,
+ * each 1, 2 or 4: L lanes per number give L times the waves, each with a
+ * shorter chain per Montgomery product, for about twice the instructions per
+ * number.  The 6144/8192-bit classes always use 4 lanes (PMK_EUNSUPPORTED for
+ * other values).  Results never change; graphs are recaptured; PMK_EBUSY
+ * while a server runs.  pmk_get_lanes fills the current values.
+ */
+int pmk_set_lanes(pmk_ctx *ctx, uint32_t bits, int fill_lanes, int tail_lanes);
+int pmk_get_lanes(const pmk_ctx *ctx, uint32_t bits, int *fill_lanes, int *tail_lanes);
+
+/*
  * Upper bound on the resident waves (workgroups) of every persistent
  * exponentiation launch of the context (the CRT halves, encryption, the
  * batched work queue, multi-prime parts and primality tests); 0 (the default)
@@ -236,15 +254,17 @@ int pmk_get_window(const pmk_ctx *ctx, uint32_t bits);
 int pmk_set_grid_limit(pmk_ctx *ctx, uint32_t waves);
 
 /*
- * Autotuner for the launch configuration: for every size class that has keys
- * in the loaded table, time the CRT decryption of one chip-filling batch of
- * full-size chunks (zero blocks: the fixed-window exponentiation costs the
- * same for any input) under the first key of that class, at three window
- * widths ({4,5,6} for 1024-bit classes and up, {3,4,5} below), and keep the
- * fastest (pmk_set_window).  The lane count per number is fixed per class by
- * its kernel.  cache_path (may be NULL): a text file -- a signature line
+ * Autotuner for the launch configuration (L lanes per number, w window bits):
+ * for every size class that has keys in the loaded table, time the CRT
+ * decryption of full-size chunks (zero blocks: the exponentiation costs the
+ * same for any input) under the first key of that class -- four rounds of
+ * resident waves at three window widths ({4,5,6} for 1024-bit classes and up,
+ * {3,4,5} below), keeping the fastest (pmk_set_window); then, for the classes
+ * with one lane per number, a quarter of a round and one and a third rounds
+ * at 1, 2 and 4 lanes per number, keeping the fastest fill and tail forms
+ * (pmk_set_lanes).  cache_path (may be NULL): a text file -- a signature line
  * (GPU architecture, compute units, HIP runtime version), then
- * "<class bits> <window> <ms>" lines.  When it exists and its signature
+ * "<class bits> <window> <fill lanes> <tail lanes> <ms>" lines.  When it exists and its signature
  * matches this device, its windows are applied without measuring, unless
  * flags has PMK_AUTOTUNE_FORCE; otherwise the measured choice is written
  * there.  Synchronous; allocates (and frees) its own device buffers; needs a

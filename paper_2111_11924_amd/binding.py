@@ -122,6 +122,8 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "pmk_set_window": (C.c_int, [vp, u32, C.c_int]),
         "pmk_get_window": (C.c_int, [vp, u32]),
         "pmk_set_grid_limit": (C.c_int, [vp, u32]),
+        "pmk_set_lanes": (C.c_int, [vp, u32, C.c_int, C.c_int]),
+        "pmk_get_lanes": (C.c_int, [vp, u32, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "pmk_autotune": (C.c_int, [vp, C.c_char_p, C.c_int]),
         "pmk_sieve": (C.c_int, [vp, u32, vp, u32, vp, vp]),
         "pmk_miller_rabin": (C.c_int, [vp, u32, vp, u32, vp, u32, vp, vp]),
@@ -338,6 +340,17 @@ def pmk_set_window(ctx: int, bits: int, win: int) -> None:
 
 def pmk_get_window(ctx: int, bits: int) -> int:
     return load_library().pmk_get_window(ctx, int(bits))
+
+
+def pmk_set_lanes(ctx: int, bits: int, fill_lanes: int, tail_lanes: int) -> None:
+    _check(load_library().pmk_set_lanes(ctx, int(bits), int(fill_lanes), int(tail_lanes)), ctx)
+
+
+def pmk_get_lanes(ctx: int, bits: int) -> Tuple[int, int]:
+    """(fill_lanes, tail_lanes) of the class holding `bits`-bit moduli."""
+    f, t = C.c_int(0), C.c_int(0)
+    _check(load_library().pmk_get_lanes(ctx, int(bits), C.byref(f), C.byref(t)), ctx)
+    return f.value, t.value
 
 
 def pmk_set_grid_limit(ctx: int, waves: int) -> None:
@@ -651,6 +664,14 @@ class Context:
 
     def window(self, bits: int) -> int:
         return pmk_get_window(self.handle, bits)
+
+    def set_lanes(self, bits: int, fill_lanes: int, tail_lanes: Optional[int] = None) -> None:
+        """Lanes per number (1, 2, 4) of the CRT halves of a launch filling at
+        most half a round, and of a short last round (default: the same)."""
+        pmk_set_lanes(self.handle, bits, fill_lanes, fill_lanes if tail_lanes is None else tail_lanes)
+
+    def lanes(self, bits: int) -> Tuple[int, int]:
+        return pmk_get_lanes(self.handle, bits)
 
     def set_grid_limit(self, waves: int) -> None:
         """At most `waves` resident waves per persistent launch (0: the device's occupancy)."""

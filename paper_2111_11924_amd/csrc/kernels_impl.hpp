@@ -870,11 +870,11 @@ PMK_DEV void halves_joint_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uin
 // staged) and digit products (stage T[digit]).
 
 // stage this lane's K limbs of a number into its group's LDS column (the
-// per-lane base goes through fresh_v so the K addresses are formed at each use
-// as base + immediate, not hoisted into registers for the whole kernel)
+// per-lane base goes through an opaque copy so the K addresses are formed at
+// each use as base + immediate, not hoisted into registers for the whole kernel)
 template <int K>
 PMK_DEV void stage_limbs(uint32_t *col, int ng, int pos, const uint32_t (&x)[K]) {
-    uint32_t *d = fresh_v(col + pos * K * ng);
+    lds_u32 *d = opaque_lds(as_lds(col + pos * K * ng));
 #pragma unroll
     for (int j = 0; j < K; ++j) d[j * ng] = x[j];
 }
@@ -885,14 +885,14 @@ PMK_DEV void stage_mem(uint32_t *col, int ng, int pos, const uint32_t *src, size
     src = fresh_v(src);
 #pragma unroll
     for (int j = 0; j < K; ++j) v[j] = src[j * stride];
-    uint32_t *d = fresh_v(col + pos * K * ng);
+    lds_u32 *d = opaque_lds(as_lds(col + pos * K * ng));
 #pragma unroll
     for (int j = 0; j < K; ++j) d[j * ng] = v[j];
 }
 // the constant 1
 template <int K>
 PMK_DEV void stage_one(uint32_t *col, int ng, int pos) {
-    uint32_t *d = fresh_v(col + pos * K * ng);
+    lds_u32 *d = opaque_lds(as_lds(col + pos * K * ng));
 #pragma unroll
     for (int j = 0; j < K; ++j) d[j * ng] = (pos == 0 && j == 0) ? 1u : 0u;
 }
@@ -900,14 +900,14 @@ PMK_DEV void stage_one(uint32_t *col, int ng, int pos) {
 // are in the group's LDS column
 template <int K, int LB>
 PMK_DEV void limbs_from_words(uint32_t (&x)[K], const uint32_t *col, int ng, int nwords, int first) {
-    col = fresh_v(col);
+    const lds_u32 *cl = opaque_lds(as_lds(col));
     first = fresh_i(first);  // keep the K word indices and shifts out of the loop-invariant set
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const int bit = LB * (first + j);
         const int k = bit >> 5, sh = bit & 31;
-        const uint32_t lo = k < nwords ? col[k * ng] : 0u;
-        const uint32_t hi = k + 1 < nwords ? col[(k + 1) * ng] : 0u;
+        const uint32_t lo = k < nwords ? cl[k * ng] : 0u;
+        const uint32_t hi = k + 1 < nwords ? cl[(k + 1) * ng] : 0u;
         x[j] = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & Radix<LB>::MASK;
     }
 }
@@ -918,12 +918,15 @@ constexpr int lds_words_enc() {
     return (make_geom(CB).nlf > make_geom(CB).S ? make_geom(CB).nlf : make_geom(CB).S) * (64 / lanes_full(CB));
 }
 // LDS words of the CRT-halves units: one-lane classes hold one prefetched
-// table entry per wavefront; lane-group classes one multiplier column per group
+// table entry per wavefront; lane groups of L lanes one multiplier column per
+// group (of nla limbs, or of the S input words while they are staged)
+template <int CB, int L>
+constexpr int lds_words_lanes() {
+    return (make_geom(CB).nla > make_geom(CB).S ? make_geom(CB).nla : make_geom(CB).S) * (64 / L);
+}
 template <int CB>
 constexpr int lds_words_dec() {
-    return lanes_half(CB) == 1
-               ? pad4(make_geom(CB).nlh) * kTile
-               : (make_geom(CB).nlh > make_geom(CB).S ? make_geom(CB).nlh : make_geom(CB).S) * (64 / lanes_half(CB));
+    return lanes_half(CB) == 1 ? pad4(make_geom(CB).nlh) * kTile : lds_words_lanes<CB, lanes_half(CB)>();
 }
 
 // Unit u encrypts chunks [part NG, part NG + NG) of tile u / L (part = u % L):
@@ -995,14 +998,18 @@ PMK_DEV void encrypt_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uin
     }
 }
 
-// CRT halves with L = 4 lanes per number (6144/8192-bit keys): unit u works on
-// chunks [part 16, part 16 + 16) of tile t modulo p (h = 0) or q (h = 1), with
-// u = (2 t + h) L + part.  The exponent is wave-uniform; the window table holds
-// each lane's K limbs per entry ([entry][limb][lane]).
-template <int CB>
+// CRT halves with L lanes per number: the only form of the 6144/8192-bit
+// classes (L = 4), and for the one-lane classes the form of a launch's last
+// partial round or of a launch too small to fill the chip (L = 2 or 4, on
+// numbers of nla limbs with the record's lane-group constants).  Unit u works
+// on chunks [part 64/L, part 64/L + 64/L) of tile t modulo p (h = 0) or q
+// (h = 1), with u = (2 t + h) L + part.  The exponent is wave-uniform; the
+// window table holds each lane's K limbs per entry ([entry][limb][lane]).
+template <int CB, int L = lanes_half(CB)>
 PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint32_t *lds) {
     constexpr Geom G = make_geom(CB);
-    constexpr int L = lanes_half(CB), NLT = G.nlh, K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
+    constexpr int NLT = G.nla, K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
+    static_assert(K * L == NLT, "lane-group limbs must split evenly");
     constexpr int NG = 64 / L;  // groups (chunks) per wavefront
     const int win = r.win, TH = 1 << (win - 1);  // odd powers x~, x~^3, ..., x~^(2 TH - 1)
     const uint32_t jt = u / L, tile = jt >> 1;
@@ -1032,7 +1039,7 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
     limbs_from_words<K, LB>(acc, col, NG, S, NLT + pos * K);  // c_hi
     store_entry(tbl, 0, lane, acc);
     limbs_from_words<K, LB>(acc, col, NG, S, pos * K);        // c_lo
-    stage_mem<K>(col, NG, pos, hr + G.h_rr + pos * K, 1);
+    stage_mem<K>(col, NG, pos, hr + G.h_rra + pos * K, 1);
 
     // phases as in halves_unit: 0 c_lo R, 1 c_hi R^2 and x~ (entry 0), 2 x~^2,
     // 5 odd powers (entry e = x~^(2e+1)), 3 sliding-window steps (squarings,
@@ -1046,7 +1053,7 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
         if (phase == 0) {
             store_entry(tbl, 1, lane, acc);
             load_entry(acc, tbl, 0, lane);
-            stage_mem<K>(col, NG, pos, hr + G.h_rrr + pos * K, 1);
+            stage_mem<K>(col, NG, pos, hr + G.h_rrra + pos * K, 1);
             phase = 1;
             continue;
         }
@@ -1089,7 +1096,7 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
             // table complete: the first window starts at the top set bit
             const int top = exp_top_bit(dexp, SH);
             if (top < 0) {
-                load_limbs(acc, fresh_v(hr + G.h_one + pos * K));
+                load_limbs(acc, fresh_v(hr + G.h_onea + pos * K));
                 st = WinStep::make(0, 0u, false, -1);
             } else {
                 st = win_first(nx, dexp, SH, top, win);
@@ -1115,9 +1122,12 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
         }
     }
     canonicalize_lanes<K, LB, L>(acc, n, pos);
-    uint32_t *dst = r.half + ((size_t)(2 * tile + h) * NLT + pos * K) * kTile + c;
+    // the result is below p: limbs from nlh up are zero and not stored (the
+    // half buffer holds nlh limbs per number)
+    uint32_t *dst = r.half + ((size_t)(2 * tile + h) * G.nlh + pos * K) * kTile + c;
 #pragma unroll
-    for (int j = 0; j < K; ++j) dst[(size_t)j * kTile] = acc[j];
+    for (int j = 0; j < K; ++j)
+        if (NLT == G.nlh || pos * K + j < G.nlh) dst[(size_t)j * kTile] = acc[j];
 }
 
 // Blinded decryption in one pass per prime for the lane-group classes (CRT
@@ -1332,17 +1342,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ha
 }
 
 template <int CB>
+// units [u_begin, u_end) of the class's own form (job tiles 2 t + h for one
+// lane per number, lane-group units for the 6144/8192-bit classes)
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kDecWaves<CB>))) void halves_kernel(
-    ClassRun r, uint64_t slot_words) {
+    ClassRun r, uint64_t slot_words, uint32_t u_begin, uint32_t u_end) {
     uint32_t *tbl = r.table + (size_t)blockIdx.x * slot_words;
     __shared__ uint32_t lds[lds_words_dec<CB>()];
-    const uint32_t units = 2 * r.ntiles * lanes_half(CB);
-    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+    for (uint32_t u = u_begin + blockIdx.x; u < u_end; u += gridDim.x) {
         if constexpr (lanes_half(CB) > 1)
             halves_lanes_unit<CB>(r, u, tbl, lds);
         else
             halves_unit<CB>(r, u, tbl, lds);
     }
+}
+
+// CRT halves of a one-lane class in lane groups of L lanes: lane-group units
+// [u_begin, u_end) (u = job tile x L + part)
+template <int CB, int L>
+__global__ __launch_bounds__(64) void halves_lanes_kernel(ClassRun r, uint64_t slot_words, uint32_t u_begin,
+                                                          uint32_t u_end) {
+    uint32_t *tbl = r.table + (size_t)blockIdx.x * slot_words;
+    __shared__ uint32_t lds[lds_words_lanes<CB, L>()];
+    for (uint32_t u = u_begin + blockIdx.x; u < u_end; u += gridDim.x) halves_lanes_unit<CB, L>(r, u, tbl, lds);
 }
 
 // ------------------------------------------------------------------ Garner

@@ -1,0 +1,77 @@
+// CRT halves of the one-lane classes (128- to 4096-bit keys) in lane groups
+// of 2 or 4 lanes per number (halves_lanes_kernel), for the last partial round
+// of a CRT-halves launch and for launches too small to fill the chip: there a
+// wave per 64 numbers leaves most SIMDs with one wave or none, while a group
+// of L lanes per number gives L times the waves, each with a shorter
+// dependency chain per product.  A translation unit of its own, so the
+// per-class objects stay as they are.
+#include "kernels_impl.hpp"
+
+namespace pmk {
+
+namespace {
+
+template <int CB, int L>
+uint32_t resident_of() {
+    static const uint32_t nb = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)halves_lanes_kernel<CB, L>, 64, 0) !=
+                hipSuccess ||
+            n < 1)
+            n = 1;
+        return (uint32_t)n;
+    }();
+    return nb * (uint32_t)device_cus();
+}
+
+template <int CB, int L>
+int launch_class(const ClassRun &r, uint32_t jt_begin, uint32_t jt_end, hipStream_t s) {
+    constexpr Geom G = make_geom(CB);
+    constexpr uint64_t K = G.nla / L;
+    const uint64_t slot = (uint64_t)(1u << (r.win - 1)) * K * kTile;  // odd powers, each lane's K limbs
+    const uint32_t units = (jt_end - jt_begin) * L;
+    // at most the table's room (L lane-group slots per one-lane slot), the
+    // kernel's residency and the context's cap
+    uint32_t grid = persistent_grid(units, r.slots_dec * (uint32_t)L, r.grid_cap);
+    grid = std::min(grid, resident_of<CB, L>());
+    hipLaunchKernelGGL((halves_lanes_kernel<CB, L>), dim3(grid), dim3(64), 0, s, r, slot, jt_begin * L, jt_end * L);
+    return (int)hipGetLastError();
+}
+
+template <int CB>
+int launch_L(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, hipStream_t s) {
+    if (L == 2) return launch_class<CB, 2>(r, jt_begin, jt_end, s);
+    if (L == 4) return launch_class<CB, 4>(r, jt_begin, jt_end, s);
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int device_cus() {
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1;
+    if (!cus[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 1;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
+int launch_halves_lanes(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, void *stream) {
+    if (jt_end <= jt_begin) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    switch (r.cls) {
+        case 0: return launch_L<128>(r, L, jt_begin, jt_end, s);
+        case 1: return launch_L<256>(r, L, jt_begin, jt_end, s);
+        case 2: return launch_L<512>(r, L, jt_begin, jt_end, s);
+        case 3: return launch_L<1024>(r, L, jt_begin, jt_end, s);
+        case 4: return launch_L<2048>(r, L, jt_begin, jt_end, s);
+        case 5: return launch_L<3072>(r, L, jt_begin, jt_end, s);
+        case 6: return launch_L<4096>(r, L, jt_begin, jt_end, s);
+        default: return (int)hipErrorNotSupported;
+    }
+}
+
+}  // namespace pmk

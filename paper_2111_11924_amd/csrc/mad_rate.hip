@@ -1,30 +1,40 @@
 // Issue-rate probe of the VALU integer instructions the Montgomery kernels are
-// made of (gfx950, wave64): each thread runs CH independent chains of one
-// instruction, the grid fills every compute unit, and the rate is reported in
-// lane-operations per clock per compute unit (64 = one per lane per clock).
-// The v_mad_u64_u32 figure is the measured ceiling the CRT kernels are
-// compared against beside the nominal one-per-lane-per-clock peak.
-// Register-only inline assembly: no memory access besides one store per thread.
+// made of (gfx950, wave64).  Each wave runs CH independent chains of one
+// instruction; the grid puts W waves on every SIMD (one-wave blocks,
+// 4 W blocks per compute unit).  Every wave reads the shader cycle counter
+// (clock64, s_memtime) and the constant-rate wall counter around its timed
+// loop, so rates come out per shader cycle whatever clock the chip runs at,
+// and the clock itself is measured: lane-operations per cycle per compute
+// unit = (waves x 64 x operations) / (the longest wave's cycles) / CUs.
+// Register-only inline assembly: no memory access besides one store per wave.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
+#include <vector>
 
 namespace {
 
-constexpr int kIters = 2048;
+constexpr int kIters = 4096;
 
 template <int OP, int CH>
-__global__ __launch_bounds__(256) void probe(uint32_t *out, uint32_t seed) {
+__global__ __launch_bounds__(64) void probe(unsigned long long *out, uint32_t seed) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t acc[CH];
     uint32_t r[CH];
     const uint32_t a = tid * 2654435761u + seed, b = a ^ 0x9e3779b9u;
+#pragma unroll
     for (int c = 0; c < CH; ++c) {
         acc[c] = tid + c;
         r[c] = tid * 7 + c;
     }
-    for (int it = 0; it < kIters; ++it) {
+    long long t0 = 0, w0 = 0;
+    for (int it = -64; it < kIters; ++it) {  // 64 untimed iterations first
+        if (it == 0) {
+            t0 = clock64();
+            w0 = wall_clock64();
+        }
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             if constexpr (OP == 0)  // 32x32 -> 64 multiply with 64-bit accumulate
@@ -39,37 +49,62 @@ __global__ __launch_bounds__(256) void probe(uint32_t *out, uint32_t seed) {
                 asm volatile("v_and_b32 %0, 0xfffffff, %0" : "+v"(r[c]));
         }
     }
+    const long long t1 = clock64(), w1 = wall_clock64();
     uint32_t s = b;
+#pragma unroll
     for (int c = 0; c < CH; ++c) s += (uint32_t)acc[c] + (uint32_t)(acc[c] >> 32) + r[c];
-    out[tid] = s;
+    if (threadIdx.x == 0) {
+        out[3 * blockIdx.x] = (unsigned long long)(t1 - t0);
+        out[3 * blockIdx.x + 1] = (unsigned long long)(w1 - w0);
+        out[3 * blockIdx.x + 2] = s;
+    }
 }
 
+struct Result {
+    double cu_rate;   // lane-ops per shader cycle per compute unit
+    double clk_mhz;   // shader clock measured by the waves
+    double event_rate;  // lane-ops per second from event timing
+};
+
 template <int OP, int CH>
-float time_ms(uint32_t *d, int blocks) {
+Result run(unsigned long long *d, std::vector<unsigned long long> &h, int waves_per_simd, const hipDeviceProp_t &prop,
+           int wall_khz) {
+    const int blocks = prop.multiProcessorCount * 4 * waves_per_simd;
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    hipLaunchKernelGGL((probe<OP, CH>), dim3(blocks), dim3(256), 0, 0, d, 1u);
+    hipLaunchKernelGGL((probe<OP, CH>), dim3(blocks), dim3(64), 0, 0, d, 1u);  // warm-up
     (void)hipDeviceSynchronize();
     (void)hipEventRecord(e0);
-    for (int i = 0; i < 3; ++i) hipLaunchKernelGGL((probe<OP, CH>), dim3(blocks), dim3(256), 0, 0, d, (uint32_t)i);
+    hipLaunchKernelGGL((probe<OP, CH>), dim3(blocks), dim3(64), 0, 0, d, 2u);
     (void)hipEventRecord(e1);
     (void)hipEventSynchronize(e1);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return ms / 3;
+    (void)hipMemcpy(h.data(), d, (size_t)blocks * 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    unsigned long long cyc = 0, wall = 0;
+    double clk = 0;
+    for (int i = 0; i < blocks; ++i) {
+        cyc = std::max(cyc, h[3 * i]);
+        wall = std::max(wall, h[3 * i + 1]);
+        if (h[3 * i + 1]) clk += (double)h[3 * i] / (double)h[3 * i + 1];
+    }
+    const double ops = (double)blocks * 64 * kIters * CH;
+    Result res;
+    res.cu_rate = ops / (double)cyc / prop.multiProcessorCount;
+    res.clk_mhz = clk / blocks * wall_khz / 1e3;
+    res.event_rate = ops / (ms * 1e-3);
+    return res;
 }
 
 template <int OP, int CH>
-void report(const char *name, uint32_t *d, int blocks, const hipDeviceProp_t &prop) {
-    const float ms = time_ms<OP, CH>(d, blocks);
-    const double ops = (double)blocks * 256 * kIters * CH;
-    const double rate = ops / (ms * 1e-3);
-    const double clk = prop.clockRate * 1e3;
-    std::printf("%-16s chains %2d  %8.3f ms  %.3e lane-ops/s  %6.2f lane-ops/clk/CU\n", name, CH, ms, rate,
-                rate / clk / prop.multiProcessorCount);
+void report(const char *name, unsigned long long *d, std::vector<unsigned long long> &h, int w,
+            const hipDeviceProp_t &prop, int wall_khz) {
+    const Result r = run<OP, CH>(d, h, w, prop, wall_khz);
+    std::printf("%-14s waves/SIMD %d chains %2d  %7.2f lane-ops/cycle/CU  clock %6.0f MHz  %.3e lane-ops/s (events)\n",
+                name, w, CH, r.cu_rate, r.clk_mhz, r.event_rate);
 }
 
 }  // namespace
@@ -80,17 +115,30 @@ int main() {
         std::fprintf(stderr, "no HIP device\n");
         return 1;
     }
-    std::printf("device %s, %d CUs, clock %d kHz\n", prop.gcnArchName, prop.multiProcessorCount, prop.clockRate);
-    const int blocks = prop.multiProcessorCount * 8;  // 8 blocks of 4 waves per CU: 8 waves per SIMD
-    uint32_t *d = nullptr;
-    if (hipMalloc(&d, (size_t)blocks * 256 * sizeof(uint32_t)) != hipSuccess) return 1;
-    report<0, 4>("v_mad_u64_u32", d, blocks, prop);
-    report<0, 8>("v_mad_u64_u32", d, blocks, prop);
-    report<0, 16>("v_mad_u64_u32", d, blocks, prop);
-    report<1, 8>("v_mul_lo_u32", d, blocks, prop);
-    report<2, 8>("v_add_co_u32", d, blocks, prop);
-    report<3, 8>("v_lshrrev_b64", d, blocks, prop);
-    report<4, 8>("v_and_b32", d, blocks, prop);
+    int wall_khz = 0;
+    if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, 0) != hipSuccess || wall_khz <= 0) {
+        std::fprintf(stderr, "no wall clock rate\n");
+        return 1;
+    }
+    std::printf("device %s, %d CUs, peak clock %d kHz, wall counter %d kHz\n", prop.gcnArchName,
+                prop.multiProcessorCount, prop.clockRate, wall_khz);
+    const int max_blocks = prop.multiProcessorCount * 4 * 8;
+    unsigned long long *d = nullptr;
+    if (hipMalloc(&d, (size_t)max_blocks * 3 * sizeof(unsigned long long)) != hipSuccess) return 1;
+    std::vector<unsigned long long> h((size_t)max_blocks * 3);
+    for (int w : {1, 2, 3, 4, 8}) {
+        report<0, 1>("v_mad_u64_u32", d, h, w, prop, wall_khz);
+        report<0, 2>("v_mad_u64_u32", d, h, w, prop, wall_khz);
+        report<0, 4>("v_mad_u64_u32", d, h, w, prop, wall_khz);
+        report<0, 8>("v_mad_u64_u32", d, h, w, prop, wall_khz);
+        report<0, 16>("v_mad_u64_u32", d, h, w, prop, wall_khz);
+    }
+    for (int w : {1, 4, 8}) {
+        report<1, 8>("v_mul_lo_u32", d, h, w, prop, wall_khz);
+        report<2, 8>("v_add_co_u32", d, h, w, prop, wall_khz);
+        report<3, 8>("v_lshrrev_b64", d, h, w, prop, wall_khz);
+        report<4, 8>("v_and_b32", d, h, w, prop, wall_khz);
+    }
     (void)hipFree(d);
     return 0;
 }

@@ -19,6 +19,20 @@
 
 namespace pmk {
 
+// LDS words through pointers of the LDS address space.  The kernels hand an
+// opaque copy (empty asm) of a pointer to their loops so that addresses are
+// formed at each use; made from a generic pointer, that copy no longer tells
+// the compiler that it points into LDS, and its accesses would become flat
+// memory operations (a global-memory wait per access).
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+__device__ __forceinline__ lds_u32 *as_lds(uint32_t *p) { return (lds_u32 *)p; }
+__device__ __forceinline__ const lds_u32 *as_lds(const uint32_t *p) { return (const lds_u32 *)p; }
+template <typename T>
+__device__ __forceinline__ T *opaque_lds(T *p) {
+    asm volatile("" : "+v"(p));
+    return p;
+}
+
 // quad_perm DPP selectors (four 2-bit lane indices inside each quad)
 constexpr int qperm(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
 
@@ -93,20 +107,34 @@ __device__ __forceinline__ void mont_mul_lanes(uint32_t (&r)[NLT / L], const uin
     static_assert((2.0 * NLT + 1) * (double)(1ull << LB) * (double)(1ull << LB) < 18446744073709551615.0,
                   "column sums may overflow 64 bits");
     constexpr uint32_t MASK = Radix<LB>::MASK;
-    asm volatile("" : "+v"(bl));  // b_i addresses: base + immediate at each use
+    const lds_u32 *b3 = opaque_lds(as_lds(bl));  // b_i addresses: base + immediate at each use
     uint64_t t[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) t[j] = 0;
+    // with few limbs per lane a step is short and its read of b_i would stall
+    // it: b_(i+1) is read one step ahead; with many (K > 20) the step hides
+    // the read and the extra register only adds pressure
+    constexpr bool kAhead = K <= 20;
+    uint32_t bn = kAhead ? (uint32_t)b3[0] : 0u;
     __builtin_amdgcn_sched_barrier(0);
     // NLT = L K steps, as L blocks of K unrolled steps: t shifts by one limb
     // per step, so after K steps its registers are back in place and the
     // block's code serves every block (code size K steps, not NLT)
 #pragma unroll 1
     for (int blk = 0; blk < L; ++blk) {
-        const uint32_t *bb = bl + blk * K * bstride;
+        const lds_u32 *bb = b3 + blk * K * bstride;
 #pragma unroll
         for (int ii = 0; ii < K; ++ii) {
-            const uint32_t bi = bb[ii * bstride];
+            uint32_t bi;
+            if constexpr (kAhead) {
+                bi = bn;
+                // the next step's limb, read while this step runs (the steps
+                // are kept apart by scheduling barriers); after the last step
+                // limb 0 again, unused
+                bn = bb[ii + 1 < K ? (ii + 1) * bstride : (blk + 1 < L ? K * bstride : -blk * K * bstride)];
+            } else {
+                bi = bb[ii * bstride];
+            }
 #pragma unroll
             for (int j = 0; j < K; ++j) t[j] += (uint64_t)a[j] * bi;
             const uint32_t m = (grp_first<L>((uint32_t)t[0], pos) * n0) & MASK;

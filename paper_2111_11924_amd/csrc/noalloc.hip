@@ -195,6 +195,8 @@ int pmk_decrypt_noalloc(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, cons
         r.err = d_err;
         r.grid_cap = ctx->grid_limit;
         r.win = ctx->win[c];
+        r.fill_lanes = ctx->fill_lanes[c];
+        r.tail_lanes = ctx->tail_lanes[c];
         le = launch_pack(r, d_ct, 1, s);
         if (!le) le = launch_decrypt_halves(r, s);
         if (!le) le = launch_garner(r, s);

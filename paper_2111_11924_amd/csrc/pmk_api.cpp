@@ -107,6 +107,8 @@ hipError_t ensure_tables(pmk_plan *pl) {
         if (!r.ntiles) continue;
         r.win = pl->ctx->win[c];
         r.grid_cap = pl->ctx->grid_limit;
+        r.fill_lanes = pl->ctx->fill_lanes[c];
+        r.tail_lanes = pl->ctx->tail_lanes[c];
         const uint64_t need = std::max(r.slots_enc * table_words_per_slot(c, 0, 0),
                                        r.slots_dec * table_words_per_slot(c, 1, r.win));
         const hipError_t e = regrow(pl, &r.table, pl->table_cap[c], need);
@@ -136,7 +138,12 @@ int pmk_create(int device, pmk_ctx **out) {
     }
     ctx->num_cus = prop.multiProcessorCount;
     ctx->device_name = prop.gcnArchName;
-    for (int c = 0; c < kNumClasses; ++c) ctx->win[c] = window_for(kClassBits[c] / 2);
+    for (int c = 0; c < kNumClasses; ++c) {
+        ctx->win[c] = window_for(kClassBits[c] / 2);
+        const int fixed = lanes_half(kClassBits[c]);
+        ctx->fill_lanes[c] = fixed > 1 ? fixed : default_fill_lanes(kClassBits[c]);
+        ctx->tail_lanes[c] = fixed > 1 ? fixed : default_tail_lanes(kClassBits[c]);
+    }
     ctx->err.reserve(600);  // messages (below 512 bytes) are then stored without allocating
     // the allocation-free entry point reports it if its scratch is unavailable
     (void)noalloc_setup(ctx);
@@ -690,6 +697,34 @@ int pmk_get_window(const pmk_ctx *ctx, uint32_t bits) {
     return c < 0 ? PMK_EUNSUPPORTED : ctx->win[c];
 }
 
+int pmk_set_lanes(pmk_ctx *ctx, uint32_t bits, int fill_lanes, int tail_lanes) {
+    if (!ctx) return PMK_EINVAL;
+    const int c = class_for_bits(bits);
+    if (c < 0) return set_err(ctx, PMK_EUNSUPPORTED, "no size class for %u bits", bits);
+    auto ok = [](int l) { return l == 1 || l == 2 || l == 4; };
+    if (!ok(fill_lanes) || !ok(tail_lanes)) return set_err(ctx, PMK_EINVAL, "lanes per number must be 1, 2 or 4");
+    const int fixed = lanes_half(kClassBits[c]);
+    if (fixed > 1 && (fill_lanes != fixed || tail_lanes != fixed))
+        return set_err(ctx, PMK_EUNSUPPORTED, "the %d-bit class always runs its CRT halves in groups of %d lanes",
+                       kClassBits[c], fixed);
+    if (ctx->server) return set_err(ctx, PMK_EBUSY, "lane settings are fixed while a server runs");
+    if (ctx->fill_lanes[c] != fill_lanes || ctx->tail_lanes[c] != tail_lanes) {
+        ctx->fill_lanes[c] = fill_lanes;
+        ctx->tail_lanes[c] = tail_lanes;
+        ctx->epoch++;
+    }
+    return PMK_OK;
+}
+
+int pmk_get_lanes(const pmk_ctx *ctx, uint32_t bits, int *fill_lanes, int *tail_lanes) {
+    if (!ctx) return PMK_EINVAL;
+    const int c = class_for_bits(bits);
+    if (c < 0) return PMK_EUNSUPPORTED;
+    if (fill_lanes) *fill_lanes = ctx->fill_lanes[c];
+    if (tail_lanes) *tail_lanes = ctx->tail_lanes[c];
+    return PMK_OK;
+}
+
 int pmk_set_grid_limit(pmk_ctx *ctx, uint32_t waves) {
     if (!ctx) return PMK_EINVAL;
     if (ctx->server) return set_err(ctx, PMK_EBUSY, "the grid limit is fixed while a server runs");
@@ -709,7 +744,7 @@ std::string tune_signature(const pmk_ctx *ctx) {
     int rt = 0;
     (void)hipRuntimeGetVersion(&rt);
     char buf[256];
-    std::snprintf(buf, sizeof buf, "pmk-autotune 1 %s cus=%d hip=%d", ctx->device_name.c_str(), ctx->num_cus, rt);
+    std::snprintf(buf, sizeof buf, "pmk-autotune 2 %s cus=%d hip=%d", ctx->device_name.c_str(), ctx->num_cus, rt);
     return buf;
 }
 
@@ -723,23 +758,55 @@ bool tune_load(pmk_ctx *ctx, const char *path) {
         line[strcspn(line, "\r\n")] = 0;
         ok = tune_signature(ctx) == line;
     }
-    int got[kNumClasses];
-    for (int c = 0; c < kNumClasses; ++c) got[c] = ctx->win[c];
+    int got[kNumClasses], fill[kNumClasses], tail[kNumClasses];
+    for (int c = 0; c < kNumClasses; ++c) {
+        got[c] = ctx->win[c];
+        fill[c] = ctx->fill_lanes[c];
+        tail[c] = ctx->tail_lanes[c];
+    }
     unsigned bits = 0;
-    int win = 0;
+    int win = 0, fl = 0, tl = 0;
     while (ok && std::fgets(line, sizeof line, f)) {
-        if (std::sscanf(line, "%u %d", &bits, &win) != 2) continue;
+        if (std::sscanf(line, "%u %d %d %d", &bits, &win, &fl, &tl) != 4) continue;
         const int c = class_for_bits(bits);
-        if (c < 0 || kClassBits[c] != (int)bits || win < 2 || win > kMaxWin) {
+        auto lanes_ok = [](int l) { return l == 1 || l == 2 || l == 4; };
+        if (c < 0 || kClassBits[c] != (int)bits || win < 2 || win > kMaxWin || !lanes_ok(fl) || !lanes_ok(tl)) {
             ok = false;
             break;
         }
         got[c] = win;
+        fill[c] = fl;
+        tail[c] = tl;
     }
     std::fclose(f);
     if (!ok) return false;
-    for (int c = 0; c < kNumClasses; ++c) (void)pmk_set_window(ctx, (uint32_t)kClassBits[c], got[c]);
+    for (int c = 0; c < kNumClasses; ++c) {
+        (void)pmk_set_window(ctx, (uint32_t)kClassBits[c], got[c]);
+        (void)pmk_set_lanes(ctx, (uint32_t)kClassBits[c], fill[c], tail[c]);
+    }
     return true;
+}
+
+// Best-of-`reps` time of the CRT decryption of `tiles` full tiles under key k0
+// (zero blocks: the exponentiation costs the same for any input), or PMK error.
+int tune_time(pmk_plan *pl, const uint8_t *ct, uint8_t *out, hipStream_t st, int reps, float *best);
+int tune_batch(pmk_ctx *ctx, uint32_t k0, uint64_t tiles, hipStream_t st, int reps, float *best) {
+    const uint64_t nch = tiles * (uint64_t)kTile;
+    const uint64_t kb = ctx->keys[k0].bits / 8;
+    std::vector<uint32_t> km(nch, k0);
+    pmk_plan *pl = nullptr;
+    uint64_t ct_len = 0;
+    int rc = pmk_plan_create(ctx, km.data(), nch, nch * (kb - 4), &pl, &ct_len);
+    if (rc != PMK_OK) return rc;
+    uint8_t *ct = nullptr, *out = nullptr;
+    hipError_t e = hipMalloc(&ct, ct_len);
+    if (e == hipSuccess) e = hipMalloc(&out, nch * (kb - 4));
+    if (e == hipSuccess) e = hipMemset(ct, 0, ct_len);
+    rc = e == hipSuccess ? tune_time(pl, ct, out, st, reps, best) : hip_err(ctx, e, "autotune buffers");
+    if (ct) (void)hipFree(ct);
+    if (out) (void)hipFree(out);
+    pmk_plan_destroy(pl);
+    return rc;
 }
 
 // Time of one CRT decryption of `pl` (device-resident buffers), best of `reps`.
@@ -817,14 +884,39 @@ int pmk_autotune(pmk_ctx *ctx, const char *cache_path, int flags) {
                 best_w = w;
             }
         }
-        if (rc == PMK_OK) {
-            std::snprintf(line, sizeof line, "%d %d %.4f\n", cb, best_w, best_ms);
-            report += line;
-        }
         (void)pmk_set_window(ctx, (uint32_t)cb, best_w);
         if (ct) (void)hipFree(ct);
         if (out) (void)hipFree(out);
         pmk_plan_destroy(pl);
+        // lanes per number where a launch leaves the chip idle (one-lane
+        // classes): a quarter of one round of resident waves (fill), then one
+        // and a third rounds (the last third is the tail); a lane form must
+        // win by 1 %
+        int best_fill = ctx->fill_lanes[c], best_tail = ctx->tail_lanes[c];
+        if (rc == PMK_OK && lanes_half(cb) == 1) {
+            const uint64_t resident = wave_slots(c, 1, ctx->num_cus);  // one-lane waves, 2 per tile
+            const uint64_t sizes[2] = {std::max<uint64_t>(1, resident / 8), std::max<uint64_t>(1, resident * 2 / 3)};
+            for (int which = 0; which < 2 && rc == PMK_OK; ++which) {
+                float lbest = 1e30f;
+                int lpick = 1;
+                for (int L : {1, 2, 4}) {
+                    (void)pmk_set_lanes(ctx, (uint32_t)cb, which == 0 ? L : best_fill, which == 0 ? best_tail : L);
+                    float ms = 0.f;
+                    rc = tune_batch(ctx, k0, sizes[which], st, 3, &ms);
+                    if (rc != PMK_OK) break;
+                    if (ms < (L == 1 ? 1.0f : 0.99f) * lbest) {
+                        lbest = ms;
+                        lpick = L;
+                    }
+                }
+                (which == 0 ? best_fill : best_tail) = lpick;
+            }
+            (void)pmk_set_lanes(ctx, (uint32_t)cb, best_fill, best_tail);
+        }
+        if (rc == PMK_OK) {
+            std::snprintf(line, sizeof line, "%d %d %d %d %.4f\n", cb, best_w, best_fill, best_tail, best_ms);
+            report += line;
+        }
     }
     (void)hipStreamDestroy(st);
     if (rc != PMK_OK) return rc;

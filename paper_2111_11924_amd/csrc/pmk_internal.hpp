@@ -49,13 +49,18 @@ PMK_HD constexpr int window_for(int bits) { return bits <= 256 ? 3 : (bits <= 51
 struct Geom {
     int bits, S, SH;
     int lbf, nlf, lbh, nlh;
+    // CRT halves spread over a lane group (2 or 4 lanes per number): nla limbs
+    // (a multiple of 4) and the constants of R_A = 2^(lbh nla); for the classes
+    // whose halves always run in lane groups these are the nlh-limb ones
+    int nla;
     int ew;  // words of the public exponent
     // full-modulus part
     int off_n32, off_nf, off_n0f, off_rrf, off_rrrf, off_onef, off_e, off_ebits, off_kbytes;
     // half records (p then q): m, m0, rr, rrr, one, d, and d2 = m - 1 - d (the
-    // exponent of the Fermat inverse of c^d, for blinded decryption)
+    // exponent of the Fermat inverse of c^d, for blinded decryption), then
+    // one, rr, rrr of the lane-group form
     int off_half[2];
-    int h_m, h_m0, h_rr, h_rrr, h_one, h_d, h_d2, h_size;
+    int h_m, h_m0, h_rr, h_rrr, h_one, h_d, h_d2, h_onea, h_rra, h_rrra, h_size;
     int off_qinvr;
     int stride;
 };
@@ -93,7 +98,19 @@ PMK_HD constexpr Geom make_geom(int bits) {
     g.h_m0 = 4 * ph;
     g.h_d = 4 * ph + 4;
     g.h_d2 = g.h_d + pad4(g.SH);
-    g.h_size = pad4(g.h_d2 + g.SH);
+    if (lanes_half(bits) > 1) {  // lane groups already: the same constants
+        g.nla = g.nlh;
+        g.h_onea = g.h_one;
+        g.h_rra = g.h_rr;
+        g.h_rrra = g.h_rrr;
+        g.h_size = pad4(g.h_d2 + g.SH);
+    } else {
+        g.nla = round_up(g.nlh, 4);
+        g.h_onea = pad4(g.h_d2 + g.SH);
+        g.h_rra = g.h_onea + g.nla;
+        g.h_rrra = g.h_rra + g.nla;
+        g.h_size = g.h_rrra + g.nla;
+    }
     g.off_half[0] = o; o += g.h_size;
     g.off_half[1] = o; o += g.h_size;
     g.off_qinvr = o; o += ph;
@@ -132,6 +149,9 @@ struct ClassRun {
     uint8_t *slot_err;         // optional, per descriptor slot: 1 where unpacking rejected the chunk
     uint32_t grid_cap;         // 0, or the most resident waves a persistent launch may use
     int win;                   // window width of the CRT-halves exponentiation (3..6)
+    int fill_lanes;            // one-lane classes: lanes per number (1, 2 or 4) of the CRT halves of a
+                               // launch that fills at most half of one round of resident waves
+    int tail_lanes;            // the same for the last partial round (at most half a round) after full ones
     // blinded PMKRSA (Sec. 3.1, Algorithm 1)
     const uint32_t *fin32;     // encryption: words of a factor v < N the result is multiplied by
                                // (x^e v mod N; tile layout of y32), nullptr = 1; blinded decryption:
@@ -139,6 +159,12 @@ struct ClassRun {
 };
 
 constexpr int kMaxWin = 6;
+// default lanes per number of a one-lane class's CRT halves in a launch that
+// fills at most half a round, and in a short last round after full ones
+// (measured: 4 lanes cut a 1 MiB 2048-bit decryption by a fifth; a 2-lane
+// last round of the 100 MiB one is about even)
+PMK_HD constexpr int default_fill_lanes(int bits) { return bits >= 1024 && lanes_half(bits) == 1 ? 4 : 1; }
+PMK_HD constexpr int default_tail_lanes(int bits) { return bits == 2048 ? 2 : 1; }
 
 // One persistent launch over the exponentiation work of the 1024- to 4096-bit
 // classes of a plan: units (tiles, or job tiles of CRT halves) are numbered
@@ -168,6 +194,11 @@ int launch_garner(const ClassRun &r, void *stream);
 // with c* at r.x32 and c_R at r.fin32; tables need 2 table_words_per_slot(cls, 1, win)
 // words per slot
 int launch_decrypt_joint(const ClassRun &r, void *stream);
+// CRT halves of job tiles [jt_begin, jt_end) of a one-lane class (128..4096
+// bits) in lane groups of L = 2 or 4 lanes per number (klanes.hip)
+int launch_halves_lanes(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, void *stream);
+// compute units of the current device
+int device_cus();
 // mode: 0 ciphertext blocks, 1 plaintext chunks (range-checked), 2 whole plaintext
 // blocks (range-checked); the checks read the packed input at r.x32 (and r.fin32)
 int launch_unpack(const ClassRun &r, uint8_t *dst, int mode, void *stream);

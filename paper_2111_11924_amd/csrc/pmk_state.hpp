@@ -39,6 +39,9 @@ struct pmk_ctx {
     int live_plans = 0;
     std::set<pmk_plan *> plans;
     int win[kNumClasses] = {};  // CRT-halves window width per class
+    // lanes per number of the CRT halves where a launch leaves the chip idle:
+    // a launch of at most half a round, and a short last round (1: off)
+    int fill_lanes[kNumClasses] = {}, tail_lanes[kNumClasses] = {};
     uint32_t epoch = 0;         // bumped when a tuning choice changes (captured graphs go stale)
     uint32_t grid_limit = 0;    // pmk_set_grid_limit: most resident waves per persistent launch (0: none)
     std::string device_name;

@@ -353,27 +353,32 @@ def test_autotune_cache_and_results(torch, ctx, tmp_path):
     keys = inputs.make_keys(bits, 840)
     ctx.load_keys(keys)
     default = {b: ctx.window(b) for b in bits}
+    default_lanes = {b: ctx.lanes(b) for b in bits}
     cache = str(tmp_path / "tune.txt")
     try:
         ctx.autotune(cache)
         lines = open(cache).read().splitlines()
-        assert lines[0].startswith("pmk-autotune 1 ")
-        chosen = {int(l.split()[0]): int(l.split()[1]) for l in lines[1:]}
+        assert lines[0].startswith("pmk-autotune 2 ")
+        chosen = {int(l.split()[0]): [int(x) for x in l.split()[1:4]] for l in lines[1:]}
         assert set(chosen) == set(bits)
         for b in bits:
-            assert ctx.window(b) == chosen[b]
-            assert chosen[b] in ((4, 5, 6) if b >= 1024 else (3, 4, 5))
+            w, fill, tail = chosen[b]
+            assert ctx.window(b) == w and ctx.lanes(b) == (fill, tail)
+            assert w in ((4, 5, 6) if b >= 1024 else (3, 4, 5))
+            assert fill in (1, 2, 4) and tail in (1, 2, 4)
         # the cache is applied without measuring
         for b in bits:
             ctx.set_window(b, 2)
+            ctx.set_lanes(b, 1, 1)
         ctx.autotune(cache)
-        assert all(ctx.window(b) == chosen[b] for b in bits)
+        assert all(ctx.window(b) == chosen[b][0] and ctx.lanes(b) == tuple(chosen[b][1:]) for b in bits)
         msg = inputs.make_message(30_000 + 3, 840)
         km = inputs.random_map(len(msg), bits, 840)
         check_against_oracle(torch, ctx, keys, msg, km)
     finally:
         for b in bits:
             ctx.set_window(b, default[b])
+            ctx.set_lanes(b, *default_lanes[b])
 
 
 # ---------------------------------------------------------------- 6144/8192-bit keys
@@ -475,8 +480,11 @@ def oracle_many(fn, jobs):
         return list(ex.map(fn, jobs))
 
 
-@pytest.mark.parametrize("bits", [1024, 2048, 3072, 4096, 6144, 8192])
-def test_unusual_crt_exponents(torch, ctx, bits):
+@pytest.mark.parametrize("bits,lanes", [(b, l) for b in (1024, 2048, 3072, 4096) for l in (1, 2, 4)]
+                         + [(6144, 4), (8192, 4)])
+def test_unusual_crt_exponents(torch, ctx, bits, lanes):
+    """(lanes: lanes per number of the CRT halves where the launch leaves the
+    chip mostly idle -- here every launch, 6 keys x 70 chunks.)"""
     base = base_key(bits)
     h = bits // 2
     keys = []
@@ -491,16 +499,19 @@ def test_unusual_crt_exponents(torch, ctx, bits):
     ct = g.integers(0, 256, size=len(km) * kb, dtype=np.uint8)
     ct.reshape(-1, kb)[:, 0] = 0  # every block below N
     msg_len = len(km) * (kb - 4)
-    print(f"[gpu] unusual CRT exponents, {bits} bits, {len(km)} blocks", flush=True)
+    print(f"[gpu] unusual CRT exponents, {bits} bits, {lanes} lanes, {len(km)} blocks", flush=True)
     ctx.load_keys(keys)
+    default = ctx.lanes(bits)
     plan = ctx.plan(km, msg_len)
     T = oracle.KeyTable(keys)
     try:
+        ctx.set_lanes(bits, lanes, lanes)
         plan.set_decrypt_output(binding.PMK_DEC_BLOCKS)
         d_m = plan.decrypt(dev(torch, ct))
         assert plan.check() == binding.PMK_OK
         got = host(d_m, plan.ct_len)
     finally:
+        ctx.set_lanes(bits, *default)
         plan.close()
     # every block up to 2048 bits; above, sampled blocks of every key
     # (first, second, last of the full tile, the ragged tile's first and last)

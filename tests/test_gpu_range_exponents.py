@@ -236,6 +236,49 @@ def test_waves_take_several_units(torch, ctx):
         plan.close()
 
 
+# ---------------------------------------------------------------- lanes per number
+
+def test_lane_forms_give_identical_bytes(torch, ctx):
+    """CRT halves of the one-lane classes with 1, 2 or 4 lanes per number in a
+    launch's short last round: with the grids uncapped (every launch here is
+    one short round) and capped at 8 waves (full rounds of one lane per number,
+    then a short round in lane groups), plain and batched, every form gives
+    the message back and the oracle's bytes on a whole-block check."""
+    bits = [128, 256, 512, 1024, 2048, 3072, 4096, 768]
+    keys = inputs.make_keys(bits, 895)
+    msg = inputs.make_message(120_000 + 5, 895)
+    km = inputs.random_map(len(msg), bits, 895)
+    T = oracle.KeyTable(keys)
+    ct = oracle.encrypt(T, msg, km)
+    print(f"[gpu] lane forms, {len(km)} chunks", flush=True)
+    ctx.load_keys(keys)
+    classes = sorted(set(bits) - {768})
+    default = {b: ctx.lanes(b) for b in classes}
+    plan = ctx.plan(km, len(msg))
+    try:
+        for lanes in (1, 2, 4):
+            for b in classes:
+                ctx.set_lanes(b, lanes, lanes)
+            for cap in (0, 8):
+                ctx.set_grid_limit(cap)
+                for batch in (False, True):
+                    pt = host(plan.decrypt(dev(torch, ct), batch=batch), len(msg))
+                    assert plan.check() == binding.PMK_OK
+                    assert (pt == msg).all(), f"lanes {lanes}, cap {cap}, batch {batch}"
+        with pytest.raises(binding.PmkError) as ei:
+            ctx.set_lanes(6144, 2)
+        assert ei.value.status == binding.PMK_EUNSUPPORTED
+        ctx.set_lanes(8192, 4)  # its fixed form is accepted
+        with pytest.raises(binding.PmkError) as ei:
+            ctx.set_lanes(2048, 3)
+        assert ei.value.status == binding.PMK_EINVAL
+    finally:
+        ctx.set_grid_limit(0)
+        for b in classes:
+            ctx.set_lanes(b, *default[b])
+        plan.close()
+
+
 # ---------------------------------------------------------------- the mixed workload in full
 
 def test_config3_full_size_batched(torch, ctx):
