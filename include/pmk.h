@@ -228,7 +228,8 @@ int pmk_get_window(const pmk_ctx *ctx, uint32_t bits);
  * Algorithm 1 over the chunks) of the size class holding `bits`-bit moduli,
  * where a launch would leave the chip mostly idle.  A class whose CRT halves
  * run one lane per number (128- to 4096-bit keys) runs
- *   - a launch that fills at most half of one round of resident waves with
+ *   - a launch of at most one unit (64 numbers modulo one prime) per compute
+ *     unit, and at most half of one round of resident waves, with
  *     `fill_lanes` lanes per number, and
  *   - the last partial round of a launch, when it holds at most half a round,
  *     with `tail_lanes` lanes per number,
@@ -437,7 +438,9 @@ int pmk_miller_rabin(pmk_ctx *ctx, uint32_t bits, const uint32_t *d_cand, uint32
  * pmk_decrypt_plan on the same input.
  *
  * pmk_server_start: staging_bytes (0: 512 MiB) is the admission budget of
- *   device memory for inputs and outputs in flight; round_chunks (0: two
+ *   device memory for inputs and outputs in flight (with a pinned host mirror
+ *   of the same size, through which the copies run asynchronously beside the
+ *   rounds); round_chunks (0: two
  *   chip-filling rounds of 2048-bit CRT halves) bounds the chunks of one
  *   round; pipeline_depth as in the struct.  The key table and window widths may not change while the server
  *   runs (PMK_EBUSY).  PMK_EBUSY if a server already runs.

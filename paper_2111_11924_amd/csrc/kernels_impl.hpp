@@ -872,35 +872,35 @@ PMK_DEV void halves_joint_unit(const ClassRun r, uint32_t jt, uint32_t *tbl, uin
 // stage this lane's K limbs of a number into its group's LDS column (the
 // per-lane base goes through an opaque copy so the K addresses are formed at
 // each use as base + immediate, not hoisted into registers for the whole kernel)
-template <int K>
+template <int K, bool Flat = false>
 PMK_DEV void stage_limbs(uint32_t *col, int ng, int pos, const uint32_t (&x)[K]) {
-    lds_u32 *d = opaque_lds(as_lds(col + pos * K * ng));
+    lds_word<Flat> *d = opaque_lds(lds_k<Flat>(col + pos * K * ng));
 #pragma unroll
     for (int j = 0; j < K; ++j) d[j * ng] = x[j];
 }
 // the same from memory: limb pos*K + j at src[j * stride]
-template <int K>
+template <int K, bool Flat = false>
 PMK_DEV void stage_mem(uint32_t *col, int ng, int pos, const uint32_t *src, size_t stride) {
     uint32_t v[K];
     src = fresh_v(src);
 #pragma unroll
     for (int j = 0; j < K; ++j) v[j] = src[j * stride];
-    lds_u32 *d = opaque_lds(as_lds(col + pos * K * ng));
+    lds_word<Flat> *d = opaque_lds(lds_k<Flat>(col + pos * K * ng));
 #pragma unroll
     for (int j = 0; j < K; ++j) d[j * ng] = v[j];
 }
 // the constant 1
-template <int K>
+template <int K, bool Flat = false>
 PMK_DEV void stage_one(uint32_t *col, int ng, int pos) {
-    lds_u32 *d = opaque_lds(as_lds(col + pos * K * ng));
+    lds_word<Flat> *d = opaque_lds(lds_k<Flat>(col + pos * K * ng));
 #pragma unroll
     for (int j = 0; j < K; ++j) d[j * ng] = (pos == 0 && j == 0) ? 1u : 0u;
 }
 // this lane's radix limbs [first, first + K) of the number whose 32-bit words
 // are in the group's LDS column
-template <int K, int LB>
+template <int K, int LB, bool Flat = false>
 PMK_DEV void limbs_from_words(uint32_t (&x)[K], const uint32_t *col, int ng, int nwords, int first) {
-    const lds_u32 *cl = opaque_lds(as_lds(col));
+    const lds_word<Flat> *cl = opaque_lds(lds_k<Flat>(col));
     first = fresh_i(first);  // keep the K word indices and shifts out of the loop-invariant set
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -1010,6 +1010,7 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
     constexpr Geom G = make_geom(CB);
     constexpr int NLT = G.nla, K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
     static_assert(K * L == NLT, "lane-group limbs must split evenly");
+    constexpr bool F = CB == 8192;  // generic pointers into the multiplier column (measured faster here)
     constexpr int NG = 64 / L;  // groups (chunks) per wavefront
     const int win = r.win, TH = 1 << (win - 1);  // odd powers x~, x~^3, ..., x~^(2 TH - 1)
     const uint32_t jt = u / L, tile = jt >> 1;
@@ -1036,10 +1037,10 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
         }
         if (cmp >= 0) atomicOr(r.err, 1u);
     }
-    limbs_from_words<K, LB>(acc, col, NG, S, NLT + pos * K);  // c_hi
+    limbs_from_words<K, LB, F>(acc, col, NG, S, NLT + pos * K);  // c_hi
     store_entry(tbl, 0, lane, acc);
-    limbs_from_words<K, LB>(acc, col, NG, S, pos * K);        // c_lo
-    stage_mem<K>(col, NG, pos, hr + G.h_rra + pos * K, 1);
+    limbs_from_words<K, LB, F>(acc, col, NG, S, pos * K);        // c_lo
+    stage_mem<K, F>(col, NG, pos, hr + G.h_rra + pos * K, 1);
 
     // phases as in halves_unit: 0 c_lo R, 1 c_hi R^2 and x~ (entry 0), 2 x~^2,
     // 5 odd powers (entry e = x~^(2e+1)), 3 sliding-window steps (squarings,
@@ -1048,12 +1049,12 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
     WinStep st = WinStep::make(0, 0u, false, -1);
     ExpWords nx{0u, 0u, 0u};
     for (;;) {
-        mont_mul_lanes<NLT, LB, L>(acc, acc, col, NG, n, n0, pos);
+        mont_mul_lanes<NLT, LB, L, F>(acc, acc, col, NG, n, n0, pos);
         if (phase == 4) break;
         if (phase == 0) {
             store_entry(tbl, 1, lane, acc);
             load_entry(acc, tbl, 0, lane);
-            stage_mem<K>(col, NG, pos, hr + G.h_rrra + pos * K, 1);
+            stage_mem<K, F>(col, NG, pos, hr + G.h_rrra + pos * K, 1);
             phase = 1;
             continue;
         }
@@ -1080,12 +1081,12 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
                 cy = cin;
             }
             store_entry(tbl, 0, lane, acc);
-            stage_limbs(col, NG, pos, acc);  // next: x~ x~
+            stage_limbs<K, F>(col, NG, pos, acc);  // next: x~ x~
             phase = 2;
             continue;
         }
         if (phase == 2) {
-            stage_limbs(col, NG, pos, acc);  // x~^2, the step between odd powers
+            stage_limbs<K, F>(col, NG, pos, acc);  // x~^2, the step between odd powers
             load_entry(acc, tbl, 0, lane);
             phase = 5;
             continue;
@@ -1111,13 +1112,13 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
         }
         // phase 3: next squaring, the step's product, or the end
         if (sq < st.nsq()) {
-            stage_limbs(col, NG, pos, acc);
+            stage_limbs<K, F>(col, NG, pos, acc);
             ++sq;
         } else if (st.mul()) {
-            stage_mem<K>(col, NG, pos, fresh(tbl) + (size_t)st.idx() * K * kTile + lane, kTile);
+            stage_mem<K, F>(col, NG, pos, fresh(tbl) + (size_t)st.idx() * K * kTile + lane, kTile);
             sq = st.nsq() + 1;
         } else {
-            stage_one<K>(col, NG, pos);
+            stage_one<K, F>(col, NG, pos);
             phase = 4;
         }
     }

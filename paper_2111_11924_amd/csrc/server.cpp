@@ -13,11 +13,16 @@
 //      tiles and the descriptors uploaded.
 //   2. Launch the round (the batched launch sequence: encryption and
 //      decryption passes) on the compute stream.
-//   3. While it runs, admit queued requests in arrival order as long as the
-//      staging slab has room for their input and output (host-to-device copy
-//      on the copy stream).
-//   4. Wait for the round; copy the results of completed requests to their
-//      host buffers and release their staging.
+//   3. Admit queued requests in arrival order as long as the staging slab has
+//      room for their input and output: the input goes into a pinned host
+//      mirror of the slab and from there to the device on the copy stream,
+//      asynchronously; the next round's launch waits for those copies on the
+//      device, not on the host.
+//   4. Deliver what earlier rounds finished (their device-to-host copies ran
+//      on the copy stream beside the current round): results into the
+//      requests' host buffers, staging released.
+//   5. Wait for the round; queue the device-to-host copies of the requests it
+//      completed; release their input staging.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -145,8 +150,18 @@ struct Server {
     uint64_t next_ticket = 1;
     // device side (scheduler thread only)
     uint8_t *d_slab = nullptr;
+    uint8_t *h_slab = nullptr;  // pinned host mirror of d_slab (same offsets)
     Slab slab;
     hipStream_t stream = nullptr, copy_stream = nullptr;
+    hipEvent_t in_copied = nullptr;  // the latest admission copies
+    bool in_pending = false;         // admitted input the next round's launch must wait for
+    // completed requests whose results are on their way to h_slab
+    struct Delivery {
+        std::vector<Request *> reqs;
+        hipEvent_t ev;
+    };
+    std::deque<Delivery> deliveries;
+    std::vector<hipEvent_t> spare_events;
     // two round slots: with pipeline depth 2 the host builds and queues round
     // k+1 while round k runs
     RoundPlan rp[2][2];  // [slot][encrypt, decrypt]
@@ -272,6 +287,11 @@ int launch_round(Server *sv, RoundPlan &R, int decrypt, const std::vector<Taken>
                                sv->stream);
         if (e != hipSuccess) return (int)e;
     }
+    if (sv->in_pending) {  // admitted input still on its way to the device
+        const hipError_t we = hipStreamWaitEvent(sv->stream, sv->in_copied, 0);
+        if (we != hipSuccess) return (int)we;
+        sv->in_pending = false;
+    }
     int rc = batch_prepare(&R.pl);
     if (rc != PMK_OK) return (int)hipErrorOutOfMemory;
     R.pl.batch_slots = std::max<uint32_t>(1, std::min(batch_wave_slots(ctx->num_cus), units));
@@ -324,8 +344,15 @@ void admit(Server *sv) {
         q->in_off = in_off;
         q->out_off = out_off;
         hipError_t e = hipSuccess;
-        if (q->in_len) e = hipMemcpyAsync(sv->d_slab + in_off, q->in, q->in_len, hipMemcpyHostToDevice, sv->copy_stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(sv->copy_stream);
+        if (q->in_len) {
+            // the region's previous users are done with it (released only after
+            // their copies completed)
+            std::memcpy(sv->h_slab + in_off, q->in, q->in_len);
+            e = hipMemcpyAsync(sv->d_slab + in_off, sv->h_slab + in_off, q->in_len, hipMemcpyHostToDevice,
+                               sv->copy_stream);
+            if (e == hipSuccess) e = hipEventRecord(sv->in_copied, sv->copy_stream);
+            if (e == hipSuccess) sv->in_pending = true;
+        }
         {
             std::lock_guard<std::mutex> lk(sv->mu);
             sv->queue.pop_front();
@@ -383,6 +410,11 @@ void pick_round(Server *sv, std::vector<Taken> out[2]) {
 void fail_all(Server *sv, int status) {
     for (Request *q : sv->inflight) finish(sv, q, status);
     sv->inflight.clear();
+    for (auto &d : sv->deliveries) {
+        for (Request *q : d.reqs) finish(sv, q, status);
+        if (d.ev) sv->spare_events.push_back(d.ev);
+    }
+    sv->deliveries.clear();
     sv->flight.clear();
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->fatal = status;
@@ -414,21 +446,52 @@ int complete_round(Server *sv) {
         sv->stats.chunks += chunks;
         sv->stats.busy_ns += now_ns() - r.t0;
     }
-    // completed requests: results to the host, staging released
+    // completed requests: results queued for the host (copy stream), input
+    // staging released; the output staging goes with the delivery
     std::vector<Request *> still;
+    Server::Delivery d{{}, nullptr};
     for (Request *q : sv->inflight) {
         if (q->done_chunks < q->chunks.size()) {
             still.push_back(q);
             continue;
         }
-        hipError_t ce = hipSuccess;
-        if (q->out_len) ce = hipMemcpy(q->out, sv->d_slab + q->out_off, q->out_len, hipMemcpyDeviceToHost);
+        if (!e && q->out_len)
+            e = (int)hipMemcpyAsync(sv->h_slab + q->out_off, sv->d_slab + q->out_off, q->out_len,
+                                    hipMemcpyDeviceToHost, sv->copy_stream);
         sv->slab.release(q->in_off, std::max<uint64_t>(q->in_len, 4));
-        sv->slab.release(q->out_off, std::max<uint64_t>(q->out_len, 4));
-        finish(sv, q, ce != hipSuccess ? PMK_EDEVICE : q->status);
+        d.reqs.push_back(q);
     }
     sv->inflight.swap(still);
-    return 0;
+    if (!d.reqs.empty()) {
+        if (!sv->spare_events.empty()) {
+            d.ev = sv->spare_events.back();
+            sv->spare_events.pop_back();
+        } else if (!e) {
+            e = (int)hipEventCreateWithFlags(&d.ev, hipEventDisableTiming);
+        }
+        if (!e) e = (int)hipEventRecord(d.ev, sv->copy_stream);
+        sv->deliveries.push_back(std::move(d));
+    }
+    return e;
+}
+
+// Results of completed requests into their host buffers: each delivery waits
+// for its device-to-host copies, then copies out of the pinned mirror.
+// Returns whether anything was delivered.
+bool deliver(Server *sv) {
+    const bool any = !sv->deliveries.empty();
+    while (!sv->deliveries.empty()) {
+        Server::Delivery d = std::move(sv->deliveries.front());
+        sv->deliveries.pop_front();
+        const hipError_t e = d.ev ? hipEventSynchronize(d.ev) : hipErrorInvalidValue;
+        for (Request *q : d.reqs) {
+            if (e == hipSuccess && q->out_len) std::memcpy(q->out, sv->h_slab + q->out_off, q->out_len);
+            sv->slab.release(q->out_off, std::max<uint64_t>(q->out_len, 4));
+            finish(sv, q, e != hipSuccess ? PMK_EDEVICE : q->status);
+        }
+        if (d.ev) sv->spare_events.push_back(d.ev);
+    }
+    return any;
 }
 
 void run(Server *sv) {
@@ -439,9 +502,12 @@ void run(Server *sv) {
         {
             std::unique_lock<std::mutex> lk(sv->mu);
             sv->cv_work.wait(lk, [&] {
-                return sv->stopping || !sv->queue.empty() || !sv->inflight.empty() || !sv->flight.empty();
+                return sv->stopping || !sv->queue.empty() || !sv->inflight.empty() || !sv->flight.empty() ||
+                       !sv->deliveries.empty();
             });
-            if (sv->stopping && sv->queue.empty() && sv->inflight.empty() && sv->flight.empty()) break;
+            if (sv->stopping && sv->queue.empty() && sv->inflight.empty() && sv->flight.empty() &&
+                sv->deliveries.empty())
+                break;
         }
         admit(sv);
         bool launched = false;
@@ -465,10 +531,13 @@ void run(Server *sv) {
                 launched = true;
             }
         }
+        // results of earlier rounds while the new one runs (their staging frees up)
+        const bool delivered = deliver(sv);
         if (sv->flight.empty()) {
             // nothing runs and nothing can be picked: a queued request larger
-            // than the whole free slab can never be admitted
-            if (sv->inflight.empty()) {
+            // than the whole free slab can never be admitted (after what was
+            // just delivered has released its staging)
+            if (sv->inflight.empty() && !delivered) {
                 std::unique_lock<std::mutex> lk(sv->mu);
                 if (!sv->queue.empty()) {
                     Request *q = sv->queue.front();
@@ -490,6 +559,11 @@ void free_server(Server *sv) {
     for (auto &ev : sv->round_done)
         if (ev) (void)hipEventDestroy(ev);
     if (sv->d_slab) (void)hipFree(sv->d_slab);
+    if (sv->h_slab) (void)hipHostFree(sv->h_slab);
+    if (sv->in_copied) (void)hipEventDestroy(sv->in_copied);
+    for (auto &d : sv->deliveries)
+        if (d.ev) (void)hipEventDestroy(d.ev);
+    for (hipEvent_t ev : sv->spare_events) (void)hipEventDestroy(ev);
     if (sv->stream) (void)hipStreamDestroy(sv->stream);
     if (sv->copy_stream) (void)hipStreamDestroy(sv->copy_stream);
     for (auto &kv : sv->tickets) delete kv.second;
@@ -533,6 +607,8 @@ int pmk_server_start(pmk_ctx *ctx, const pmk_server_cfg *cfg) {
         sv->cfg.round_chunks = (uint64_t)wave_slots(4, 1, ctx->num_cus) * kTile;
     }
     hipError_t e = hipMalloc(&sv->d_slab, sv->cfg.staging_bytes);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&sv->h_slab, sv->cfg.staging_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->in_copied, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->copy_stream, hipStreamNonBlocking);
     for (int i = 0; i < 2 && e == hipSuccess; ++i)
