@@ -226,13 +226,15 @@ int pmk_get_window(const pmk_ctx *ctx, uint32_t bits);
 /*
  * Tuning: lanes per number of the CRT exponentiations (the parallel loops of
  * Algorithm 1 over the chunks) of the size class holding `bits`-bit moduli,
- * where a launch would leave the chip mostly idle.  A class whose CRT halves
- * run one lane per number (128- to 4096-bit keys) runs
- *   - a launch of at most one unit (64 numbers modulo one prime) per compute
- *     unit, and at most half of one round of resident waves, with
- *     `fill_lanes` lanes per number, and
- *   - the last partial round of a launch, when it holds at most half a round,
- *     with `tail_lanes` lanes per number,
+ * where a launch would leave SIMDs idle (one wave alone on a SIMD issues at
+ * about half the rate of several).  A class whose CRT halves run one lane per
+ * number (128- to 4096-bit keys) runs
+ *   - a launch under one round of resident waves with `fill_lanes` lanes per
+ *     number, or the largest smaller power of two for which every lane-group
+ *     wave still has a SIMD of its own (units of 64 numbers modulo one prime
+ *     times L at most 4 per compute unit), else one lane, and
+ *   - the partial round after full ones with `tail_lanes` lanes per number,
+ *     or the largest smaller power of two whose waves fit one round,
  * each 1, 2 or 4: L lanes per number give L times the waves, each with a
  * shorter chain per Montgomery product, for about twice the instructions per
  * number.  The 6144/8192-bit classes always use 4 lanes (PMK_EUNSUPPORTED for

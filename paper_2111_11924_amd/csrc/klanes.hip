@@ -59,6 +59,26 @@ int device_cus() {
     return cus[dev];
 }
 
+uint32_t lanes_resident(int cls, int L) {
+    switch (cls * 8 + L) {
+        case 0 * 8 + 2: return resident_of<128, 2>();
+        case 0 * 8 + 4: return resident_of<128, 4>();
+        case 1 * 8 + 2: return resident_of<256, 2>();
+        case 1 * 8 + 4: return resident_of<256, 4>();
+        case 2 * 8 + 2: return resident_of<512, 2>();
+        case 2 * 8 + 4: return resident_of<512, 4>();
+        case 3 * 8 + 2: return resident_of<1024, 2>();
+        case 3 * 8 + 4: return resident_of<1024, 4>();
+        case 4 * 8 + 2: return resident_of<2048, 2>();
+        case 4 * 8 + 4: return resident_of<2048, 4>();
+        case 5 * 8 + 2: return resident_of<3072, 2>();
+        case 5 * 8 + 4: return resident_of<3072, 4>();
+        case 6 * 8 + 2: return resident_of<4096, 2>();
+        case 6 * 8 + 4: return resident_of<4096, 4>();
+        default: return 0;
+    }
+}
+
 int launch_halves_lanes(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, void *stream) {
     if (jt_end <= jt_begin) return 0;
     hipStream_t s = (hipStream_t)stream;

@@ -1,11 +1,11 @@
 // Issue-rate probe of the VALU integer instructions the Montgomery kernels are
 // made of (gfx950, wave64).  Each wave runs CH independent chains of one
 // instruction; the grid puts W waves on every SIMD (one-wave blocks,
-// 4 W blocks per compute unit).  Every wave reads the shader cycle counter
-// (clock64, s_memtime) and the constant-rate wall counter around its timed
-// loop, so rates come out per shader cycle whatever clock the chip runs at,
-// and the clock itself is measured: lane-operations per cycle per compute
-// unit = (waves x 64 x operations) / (the longest wave's cycles) / CUs.
+// 4 W blocks per compute unit).  The launch is timed with events; every wave
+// also reads the shader cycle counter (clock64, s_memtime) and the
+// constant-rate wall counter around its timed loop, which gives the shader
+// clock the chip actually ran at under this load.  Lane-operations per cycle
+// per compute unit = (lane-operations per second) / (measured clock x CUs).
 // Register-only inline assembly: no memory access besides one store per wave.
 #include <hip/hip_runtime.h>
 
@@ -61,8 +61,7 @@ __global__ __launch_bounds__(64) void probe(unsigned long long *out, uint32_t se
 }
 
 struct Result {
-    double cu_rate;   // lane-ops per shader cycle per compute unit
-    double clk_mhz;   // shader clock measured by the waves
+    double clk_mhz;     // shader clock measured by the waves
     double event_rate;  // lane-ops per second from event timing
 };
 
@@ -84,17 +83,16 @@ Result run(unsigned long long *d, std::vector<unsigned long long> &h, int waves_
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipMemcpy(h.data(), d, (size_t)blocks * 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost);
-    unsigned long long cyc = 0, wall = 0;
     double clk = 0;
-    for (int i = 0; i < blocks; ++i) {
-        cyc = std::max(cyc, h[3 * i]);
-        wall = std::max(wall, h[3 * i + 1]);
-        if (h[3 * i + 1]) clk += (double)h[3 * i] / (double)h[3 * i + 1];
-    }
+    int n = 0;
+    for (int i = 0; i < blocks; ++i)
+        if (h[3 * i + 1]) {
+            clk += (double)h[3 * i] / (double)h[3 * i + 1];
+            ++n;
+        }
     const double ops = (double)blocks * 64 * kIters * CH;
     Result res;
-    res.cu_rate = ops / (double)cyc / prop.multiProcessorCount;
-    res.clk_mhz = clk / blocks * wall_khz / 1e3;
+    res.clk_mhz = n ? clk / n * wall_khz / 1e3 : 0.0;
     res.event_rate = ops / (ms * 1e-3);
     return res;
 }
@@ -103,8 +101,9 @@ template <int OP, int CH>
 void report(const char *name, unsigned long long *d, std::vector<unsigned long long> &h, int w,
             const hipDeviceProp_t &prop, int wall_khz) {
     const Result r = run<OP, CH>(d, h, w, prop, wall_khz);
-    std::printf("%-14s waves/SIMD %d chains %2d  %7.2f lane-ops/cycle/CU  clock %6.0f MHz  %.3e lane-ops/s (events)\n",
-                name, w, CH, r.cu_rate, r.clk_mhz, r.event_rate);
+    const double per_cycle = r.clk_mhz > 0 ? r.event_rate / (r.clk_mhz * 1e6) / prop.multiProcessorCount : 0.0;
+    std::printf("%-14s waves/SIMD %d chains %2d  %.3e lane-ops/s  clock %5.0f MHz  %6.2f lane-ops/cycle/CU\n", name, w,
+                CH, r.event_rate, r.clk_mhz, per_cycle);
 }
 
 }  // namespace

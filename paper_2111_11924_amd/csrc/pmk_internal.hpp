@@ -197,6 +197,8 @@ int launch_decrypt_joint(const ClassRun &r, void *stream);
 // CRT halves of job tiles [jt_begin, jt_end) of a one-lane class (128..4096
 // bits) in lane groups of L = 2 or 4 lanes per number (klanes.hip)
 int launch_halves_lanes(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, void *stream);
+// resident waves of that lane-group kernel on the current device (0: no such kernel)
+uint32_t lanes_resident(int cls, int L);
 // compute units of the current device
 int device_cus();
 // mode: 0 ciphertext blocks, 1 plaintext chunks (range-checked), 2 whole plaintext
