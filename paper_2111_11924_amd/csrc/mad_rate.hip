@@ -7,6 +7,9 @@
 // clock the chip actually ran at under this load.  Lane-operations per cycle
 // per compute unit = (lane-operations per second) / (measured clock x CUs).
 // Register-only inline assembly: no memory access besides one store per wave.
+// v_mad_u64_u32 writes a carry-out SGPR pair that nothing here reads: the
+// plain form sends every chain's to VCC, the "own pairs" form gives each chain
+// a pair of its own.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,11 +25,13 @@ template <int OP, int CH>
 __global__ __launch_bounds__(64) void probe(unsigned long long *out, uint32_t seed) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t acc[CH];
+    uint64_t cs[CH];  // carry-out pairs (OP 5); nothing reads them
     uint32_t r[CH];
     const uint32_t a = tid * 2654435761u + seed, b = a ^ 0x9e3779b9u;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
         acc[c] = tid + c;
+        cs[c] = 0;
         r[c] = tid * 7 + c;
     }
     long long t0 = 0, w0 = 0;
@@ -47,6 +52,8 @@ __global__ __launch_bounds__(64) void probe(unsigned long long *out, uint32_t se
                 asm volatile("v_lshrrev_b64 %0, 28, %0" : "+v"(acc[c]));
             if constexpr (OP == 4)
                 asm volatile("v_and_b32 %0, 0xfffffff, %0" : "+v"(r[c]));
+            if constexpr (OP == 5)  // the same multiply-add, each chain's carry-out in an SGPR pair of its own
+                asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc[c]), "+s"(cs[c]) : "v"(a), "v"(r[c]));
         }
     }
     const long long t1 = clock64(), w1 = wall_clock64();
@@ -102,7 +109,7 @@ void report(const char *name, unsigned long long *d, std::vector<unsigned long l
             const hipDeviceProp_t &prop, int wall_khz) {
     const Result r = run<OP, CH>(d, h, w, prop, wall_khz);
     const double per_cycle = r.clk_mhz > 0 ? r.event_rate / (r.clk_mhz * 1e6) / prop.multiProcessorCount : 0.0;
-    std::printf("%-14s waves/SIMD %d chains %2d  %.3e lane-ops/s  clock %5.0f MHz  %6.2f lane-ops/cycle/CU\n", name, w,
+    std::printf("%-16s waves/SIMD %d chains %2d  %.3e lane-ops/s  clock %5.0f MHz  %6.2f lane-ops/cycle/CU\n", name, w,
                 CH, r.event_rate, r.clk_mhz, per_cycle);
 }
 
@@ -131,6 +138,11 @@ int main() {
         report<0, 4>("v_mad_u64_u32", d, h, w, prop, wall_khz);
         report<0, 8>("v_mad_u64_u32", d, h, w, prop, wall_khz);
         report<0, 16>("v_mad_u64_u32", d, h, w, prop, wall_khz);
+    }
+    for (int w : {1, 2, 3, 4, 8}) {
+        report<5, 2>("mad, own pairs", d, h, w, prop, wall_khz);
+        report<5, 4>("mad, own pairs", d, h, w, prop, wall_khz);
+        report<5, 8>("mad, own pairs", d, h, w, prop, wall_khz);
     }
     for (int w : {1, 4, 8}) {
         report<1, 8>("v_mul_lo_u32", d, h, w, prop, wall_khz);
