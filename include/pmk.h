@@ -225,7 +225,8 @@ int pmk_get_window(const pmk_ctx *ctx, uint32_t bits);
 
 /*
  * Tuning: lanes per number of the CRT exponentiations (the parallel loops of
- * Algorithm 1 over the chunks) of the size class holding `bits`-bit moduli,
+ * Algorithm 1 over the chunks; plain and blinded decryption alike) of the size
+ * class holding `bits`-bit moduli,
  * where a launch would leave SIMDs idle (one wave alone on a SIMD issues at
  * about half the rate of several).  A class whose CRT halves run one lane per
  * number (128- to 4096-bit keys) runs

@@ -24,7 +24,7 @@ LIB = os.path.join(PKG, "libpmk.so")
 PROBE = os.path.join(ROOT, "_build", "mad_rate")  # VALU issue-rate probe (python -m paper_2111_11924_amd.peak)
 
 SOURCES = ["k8192.hip", "k6144.hip", "kbatch.hip", "k4096.hip", "k3072.hip", "k2048.hip", "k1024.hip", "k512.hip", "k256.hip", "k128.hip",
-           "kprime.hip", "kmp.hip", "kjoint.hip", "klanes.hip", "noalloc.hip", "dispatch.cpp", "pmk_api.cpp", "mp_api.cpp", "keyprep.cpp", "server.cpp"]
+           "kprime.hip", "kmp.hip", "kjoint.hip", "klanes.hip", "kjlanes.hip", "noalloc.hip", "dispatch.cpp", "pmk_api.cpp", "mp_api.cpp", "keyprep.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1131,13 +1131,17 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
         if (NLT == G.nlh || pos * K + j < G.nlh) dst[(size_t)j * kTile] = acc[j];
 }
 
-// Blinded decryption in one pass per prime for the lane-group classes (CRT
-// halves spread over L lanes): the chain of halves_joint_unit, with each
-// product's multiplier staged in LDS as in halves_lanes_unit.
-template <int CB>
+// Blinded decryption in one pass per prime with each CRT half spread over a
+// group of L lanes: the chain of halves_joint_unit, with each product's
+// multiplier staged in LDS as in halves_lanes_unit.  The lane-group classes
+// (L = lanes_half) always run it; the one-lane classes run it with L = 2 or 4
+// in nla limbs (R_A = 2^(lbh nla), the constants at h_rra, h_rrra, h_onea)
+// for launches that leave SIMDs idle.
+template <int CB, int L = lanes_half(CB)>
 PMK_DEV void halves_lanes_joint_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint32_t *lds) {
     constexpr Geom G = make_geom(CB);
-    constexpr int L = lanes_half(CB), NLT = G.nlh, K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
+    constexpr int NLT = G.nla, K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
+    static_assert(K * L == NLT, "lane-group limbs must split evenly");
     constexpr int NG = 64 / L;  // groups (chunks) per wavefront
     const int win = r.win, TH = 1 << (win - 1);  // T1 = entries [0, TH), T2 = [TH, 2 TH)
     const uint32_t jt = u / L, tile = jt >> 1;
@@ -1169,7 +1173,7 @@ PMK_DEV void halves_lanes_joint_unit(const ClassRun r, uint32_t u, uint32_t *tbl
         limbs_from_words<K, LB>(acc, col, NG, S, NLT + pos * K);
         store_entry(tbl, base, lane, acc);
         limbs_from_words<K, LB>(acc, col, NG, S, pos * K);
-        stage_mem<K>(col, NG, pos, hr + G.h_rr + pos * K, 1);
+        stage_mem<K>(col, NG, pos, hr + G.h_rra + pos * K, 1);
     };
     take_input(r.x32, 0);
     // phases as in halves_joint_unit: 0 lo R, 1 hi R^2 and x~ (entry base),
@@ -1186,7 +1190,7 @@ PMK_DEV void halves_lanes_joint_unit(const ClassRun r, uint32_t u, uint32_t *tbl
         if (phase == 0) {
             store_entry(tbl, base + 1, lane, acc);
             load_entry(acc, tbl, base, lane);
-            stage_mem<K>(col, NG, pos, hr + G.h_rrr + pos * K, 1);
+            stage_mem<K>(col, NG, pos, hr + G.h_rrra + pos * K, 1);
             phase = 1;
             continue;
         }
@@ -1260,7 +1264,7 @@ PMK_DEV void halves_lanes_joint_unit(const ClassRun r, uint32_t u, uint32_t *tbl
             }
             // tables complete: the chain starts from the Montgomery one above the
             // higher of the two top bits
-            load_limbs(acc, fresh_v(hr + G.h_one + pos * K));
+            load_limbs(acc, fresh_v(hr + G.h_onea + pos * K));
             const int t1 = exp_top_bit(d1, SH), t2 = exp_top_bit(d2, SH);
             if (t1 >= 0) s1 = win_first(nx1, d1, SH, t1, win);
             if (t2 >= 0) s2 = win_first(nx2, d2, SH, t2, win);
@@ -1299,9 +1303,11 @@ PMK_DEV void halves_lanes_joint_unit(const ClassRun r, uint32_t u, uint32_t *tbl
         }
     }
     canonicalize_lanes<K, LB, L>(acc, n, pos);
-    uint32_t *dst = r.half + ((size_t)(2 * tile + h) * NLT + pos * K) * kTile + c;
+    // below p: limbs from nlh up are zero and not stored (nlh limbs per number)
+    uint32_t *dst = r.half + ((size_t)(2 * tile + h) * G.nlh + pos * K) * kTile + c;
 #pragma unroll
-    for (int j = 0; j < K; ++j) dst[(size_t)j * kTile] = acc[j];
+    for (int j = 0; j < K; ++j)
+        if (NLT == G.nlh || pos * K + j < G.nlh) dst[(size_t)j * kTile] = acc[j];
 }
 
 // ------------------------------------------------------------------ per-class kernels
@@ -1330,16 +1336,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kEncWaves<CB
 // fit the three-wave budget
 template <int CB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void halves_joint_kernel(
-    ClassRun r, uint64_t slot_words) {
+    ClassRun r, uint64_t slot_words, uint32_t u_begin, uint32_t u_end) {
     uint32_t *tbl = r.table + (size_t)blockIdx.x * slot_words;
     __shared__ uint32_t lds[lds_words_dec<CB>()];
-    const uint32_t units = 2 * r.ntiles * lanes_half(CB);
-    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+    for (uint32_t u = u_begin + blockIdx.x; u < u_end; u += gridDim.x) {
         if constexpr (lanes_half(CB) > 1)
             halves_lanes_joint_unit<CB>(r, u, tbl, lds);
         else
             halves_joint_unit<CB>(r, u, tbl, lds);
     }
+}
+
+// blinded decryption of a one-lane class in lane groups of L lanes: lane-group
+// units [u_begin, u_end) (u = job tile x L + part)
+template <int CB, int L>
+__global__ __launch_bounds__(64) void halves_lanes_joint_kernel(ClassRun r, uint64_t slot_words, uint32_t u_begin,
+                                                                uint32_t u_end) {
+    uint32_t *tbl = r.table + (size_t)blockIdx.x * slot_words;
+    __shared__ uint32_t lds[lds_words_lanes<CB, L>()];
+    for (uint32_t u = u_begin + blockIdx.x; u < u_end; u += gridDim.x) halves_lanes_joint_unit<CB, L>(r, u, tbl, lds);
 }
 
 template <int CB>

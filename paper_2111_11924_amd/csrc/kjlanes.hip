@@ -1,0 +1,85 @@
+// Blinded decryption (one pass per prime, Sec. 3.1) of the one-lane classes
+// (128- to 4096-bit keys) in lane groups of 2 or 4 lanes per number
+// (halves_lanes_joint_kernel), for the part of a launch that leaves SIMDs idle,
+// as lanes_for_launch decides.  A translation unit of its own, so the other
+// objects stay as they are and the classes compile in parallel with them.
+#include "kernels_impl.hpp"
+
+namespace pmk {
+
+namespace {
+
+template <int CB, int L>
+uint32_t resident_of() {
+    static const uint32_t nb = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)halves_lanes_joint_kernel<CB, L>, 64, 0) !=
+                hipSuccess ||
+            n < 1)
+            n = 1;
+        return (uint32_t)n;
+    }();
+    return nb * (uint32_t)device_cus();
+}
+
+template <int CB, int L>
+int launch_class(const ClassRun &r, uint32_t jt_begin, uint32_t jt_end, hipStream_t s) {
+    constexpr Geom G = make_geom(CB);
+    constexpr uint64_t K = G.nla / L;
+    // two odd-power tables (T1 for c*, T2 for c_R), each lane's K limbs
+    const uint64_t slot = 2 * (uint64_t)(1u << (r.win - 1)) * K * kTile;
+    const uint32_t units = (jt_end - jt_begin) * L;
+    // L lane-group slots fit one one-lane slot of the blinded kernel (2 tables
+    // of at least 2^(win-1) entries of nla >= K L limbs)
+    uint32_t grid = persistent_grid(units, r.slots_dec * (uint32_t)L, r.grid_cap);
+    grid = std::min(grid, resident_of<CB, L>());
+    hipLaunchKernelGGL((halves_lanes_joint_kernel<CB, L>), dim3(grid), dim3(64), 0, s, r, slot, jt_begin * L,
+                       jt_end * L);
+    return (int)hipGetLastError();
+}
+
+template <int CB>
+int launch_L(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, hipStream_t s) {
+    if (L == 2) return launch_class<CB, 2>(r, jt_begin, jt_end, s);
+    if (L == 4) return launch_class<CB, 4>(r, jt_begin, jt_end, s);
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace
+
+uint32_t joint_lanes_resident(int cls, int L) {
+    switch (cls * 8 + L) {
+        case 0 * 8 + 2: return resident_of<128, 2>();
+        case 0 * 8 + 4: return resident_of<128, 4>();
+        case 1 * 8 + 2: return resident_of<256, 2>();
+        case 1 * 8 + 4: return resident_of<256, 4>();
+        case 2 * 8 + 2: return resident_of<512, 2>();
+        case 2 * 8 + 4: return resident_of<512, 4>();
+        case 3 * 8 + 2: return resident_of<1024, 2>();
+        case 3 * 8 + 4: return resident_of<1024, 4>();
+        case 4 * 8 + 2: return resident_of<2048, 2>();
+        case 4 * 8 + 4: return resident_of<2048, 4>();
+        case 5 * 8 + 2: return resident_of<3072, 2>();
+        case 5 * 8 + 4: return resident_of<3072, 4>();
+        case 6 * 8 + 2: return resident_of<4096, 2>();
+        case 6 * 8 + 4: return resident_of<4096, 4>();
+        default: return 0;
+    }
+}
+
+int launch_joint_lanes(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, void *stream) {
+    if (jt_end <= jt_begin) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    switch (r.cls) {
+        case 0: return launch_L<128>(r, L, jt_begin, jt_end, s);
+        case 1: return launch_L<256>(r, L, jt_begin, jt_end, s);
+        case 2: return launch_L<512>(r, L, jt_begin, jt_end, s);
+        case 3: return launch_L<1024>(r, L, jt_begin, jt_end, s);
+        case 4: return launch_L<2048>(r, L, jt_begin, jt_end, s);
+        case 5: return launch_L<3072>(r, L, jt_begin, jt_end, s);
+        case 6: return launch_L<4096>(r, L, jt_begin, jt_end, s);
+        default: return (int)hipErrorNotSupported;
+    }
+}
+
+}  // namespace pmk

@@ -1,6 +1,7 @@
 // Blinded decryption in one pass per prime (halves_joint_kernel) for every
-// size class.  A translation unit of its own, so the per-class objects stay as
-// they are.
+// size class; the one-lane classes hand the part of a launch that leaves SIMDs
+// idle to the lane-group form (kjlanes.hip).  A translation unit of its own,
+// so the per-class objects stay as they are.
 #include "kernels_impl.hpp"
 
 namespace pmk {
@@ -20,17 +21,31 @@ int launch_joint_class(const ClassRun &r, hipStream_t s) {
             nb = 1;
         return nb;
     }();
-    int dev = 0, ncu = 1;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
-        ncu = 1;
-    const uint64_t resident = (uint64_t)oj * (uint64_t)ncu;
+    const uint32_t ncu = (uint32_t)device_cus();
+    const uint32_t resident = (uint32_t)oj * ncu;
     const uint32_t units = 2 * r.ntiles * lanes_half(CB);
-    uint64_t grid = persistent_grid(units, r.slots_dec, r.grid_cap);
+    uint32_t grid = persistent_grid(units, r.slots_dec, r.grid_cap);
     if (grid > resident) grid = resident;
-    const uint64_t slot = 2 * table_words_per_slot(r.cls, 1, r.win);  // two odd-power tables
-    hipLaunchKernelGGL(halves_joint_kernel<CB>, dim3((uint32_t)grid), dim3(64), 0, s, r, slot);
-    return (int)hipGetLastError();
+    // the part of a launch that leaves SIMDs idle runs in lane groups (one-lane
+    // classes), as for the plain CRT halves
+    uint32_t main_end = units;
+    int L = 1;
+    if constexpr (lanes_half(CB) == 1) {
+        uint32_t res = resident;
+        if (r.grid_cap && r.grid_cap < res) res = r.grid_cap;
+        if (r.slots_dec < units && r.slots_dec < res) res = r.slots_dec;  // table room
+        uint32_t lane_units = 0;
+        L = lanes_for_launch(r, units, res, 4u * ncu, joint_lanes_resident, &lane_units);
+        main_end = units - lane_units;
+    }
+    if (main_end) {
+        const uint64_t slot = 2 * table_words_per_slot(r.cls, 1, r.win);  // two odd-power tables
+        hipLaunchKernelGGL(halves_joint_kernel<CB>, dim3(persistent_grid(main_end, grid, 0)), dim3(64), 0, s, r, slot,
+                           0u, main_end);
+        const int e = (int)hipGetLastError();
+        if (e) return e;
+    }
+    return main_end < units ? launch_joint_lanes(r, L, main_end, units, s) : 0;
 }
 
 }  // namespace

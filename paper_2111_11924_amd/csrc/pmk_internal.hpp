@@ -199,6 +199,46 @@ int launch_decrypt_joint(const ClassRun &r, void *stream);
 int launch_halves_lanes(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, void *stream);
 // resident waves of that lane-group kernel on the current device (0: no such kernel)
 uint32_t lanes_resident(int cls, int L);
+// Blinded decryption (one pass per prime) of job tiles [jt_begin, jt_end) of a
+// one-lane class in lane groups of L = 2 or 4 lanes, and that kernel's
+// resident waves (kjlanes.hip)
+int launch_joint_lanes(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, void *stream);
+uint32_t joint_lanes_resident(int cls, int L);
+
+// Lanes per number for the part of a one-lane class's CRT launch that leaves
+// SIMDs idle (one wave alone on a SIMD issues at about half the rate of
+// several).  units: job tiles of the launch; resident: waves of its one-lane
+// kernel that fit the chip (already capped by the table slots and grid cap);
+// simds: SIMDs of the device; room(cls, L): resident waves of the lane-group
+// kernel.  A launch under one round runs wholly in lane groups of r.fill_lanes
+// lanes, or of the largest smaller power of two that still gives every
+// lane-group wave a SIMD of its own; the partial round after full ones runs
+// with r.tail_lanes, or the largest smaller power of two whose waves fit one
+// round of the lane-group kernel.  Returns L (1: one lane per number) and sets
+// *lane_units to the job tiles that run in lane groups (the last ones).
+inline int lanes_for_launch(const ClassRun &r, uint32_t units, uint32_t resident, uint32_t simds,
+                            uint32_t (*room_of)(int, int), uint32_t *lane_units) {
+    *lane_units = 0;
+    if (resident == 0 || (r.fill_lanes <= 1 && r.tail_lanes <= 1)) return 1;
+    const uint32_t rem = units % resident;
+    auto fit = [&](int max_l, uint64_t limit) {
+        for (int l = max_l; l >= 2; l /= 2) {
+            uint64_t room = room_of(r.cls, l);
+            if (limit < room) room = limit;
+            if ((uint64_t)r.slots_dec * l < room) room = (uint64_t)r.slots_dec * l;  // table room
+            if (r.grid_cap && r.grid_cap < room) room = r.grid_cap;
+            if ((uint64_t)rem * l <= room) return l;
+        }
+        return 1;
+    };
+    int L = 1;
+    if (units < resident)
+        L = fit(r.fill_lanes, simds);
+    else if (rem)
+        L = fit(r.tail_lanes, UINT64_MAX);
+    if (L > 1) *lane_units = rem;
+    return L;
+}
 // compute units of the current device
 int device_cus();
 // mode: 0 ciphertext blocks, 1 plaintext chunks (range-checked), 2 whole plaintext

@@ -523,12 +523,15 @@ def test_unusual_crt_exponents(torch, ctx, bits, lanes):
         assert bytes(got[i * kb:(i + 1) * kb]) == m.to_bytes(kb, "big"), f"block {i} (key {km[i]})"
 
 
-@pytest.mark.parametrize("bits", [1024, 2048, 3072, 4096, 6144, 8192])
-def test_blinded_decryption_with_unusual_exponents(torch, ctx, bits):
+@pytest.mark.parametrize("bits,lanes", [(b, l) for b in (1024, 2048, 3072, 4096) for l in (1, 2, 4)]
+                         + [(6144, 4), (8192, 4)])
+def test_blinded_decryption_with_unusual_exponents(torch, ctx, bits, lanes):
     """Blinded decryption (c* and c_R in one squaring chain per prime) with
     private exponents of unusual shape: d below both primes, so dp = dq = d
     keeps the shape, and the second exponent p-1-d is dense.  Whole blocks
-    against the oracle's blinded route m = (c*)^d (c_R^d)^-1 mod N."""
+    against the oracle's blinded route m = (c*)^d (c_R^d)^-1 mod N, in every
+    lanes-per-number form (the launch is under one round, so all of it runs
+    in the form set)."""
     base = base_key(bits)
     h = bits // 2
     exps = [1, 3, (1 << 70) + 5, (1 << (h - 3)) - 1, (1 << (h - 2)) | 1, (1 << 100) | (1 << 37)]
@@ -547,16 +550,19 @@ def test_blinded_decryption_with_unusual_exponents(torch, ctx, bits):
     cs.reshape(-1, kb)[:, 0] = 0
     cr.reshape(-1, kb)[:, 0] = 0
     msg_len = len(km) * (kb - 4)
-    print(f"[gpu] blinded decryption, unusual exponents, {bits} bits, {len(km)} blocks", flush=True)
+    print(f"[gpu] blinded decryption, unusual exponents, {bits} bits, lanes {lanes}, {len(km)} blocks", flush=True)
     ctx.load_keys(keys)
     plan = ctx.plan(km, msg_len)
     T = oracle.KeyTable(keys)
+    default = ctx.lanes(bits)
     try:
+        ctx.set_lanes(bits, lanes, lanes)
         plan.set_decrypt_output(binding.PMK_DEC_BLOCKS)
         d_m = plan.decrypt_blinded(dev(torch, cs), dev(torch, cr))
         assert plan.check() == binding.PMK_OK
         got = host(d_m, plan.ct_len)
     finally:
+        ctx.set_lanes(bits, *default)
         plan.close()
     rows = [k * per_key + j for k in range(len(keys)) for j in (0, 1, 63, 64, per_key - 1)]
 

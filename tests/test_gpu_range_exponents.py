@@ -242,20 +242,24 @@ def test_lane_forms_give_identical_bytes(torch, ctx):
     """CRT halves of the one-lane classes with 1, 2 or 4 lanes per number in a
     launch's short last round: with the grids uncapped (every launch here is
     one short round) and capped at 8 waves (full rounds of one lane per number,
-    then a short round in lane groups), plain and batched, every form gives
-    the message back and the oracle's bytes on a whole-block check."""
+    then a short round in lane groups), plain, batched and blinded (the
+    one-chain blinded kernel and its lane-group form), every form gives the
+    message back."""
     bits = [128, 256, 512, 1024, 2048, 3072, 4096, 768]
     keys = inputs.make_keys(bits, 895)
     msg = inputs.make_message(120_000 + 5, 895)
     km = inputs.random_map(len(msg), bits, 895)
     T = oracle.KeyTable(keys)
     ct = oracle.encrypt(T, msg, km)
+    rblk = inputs.make_blinding(keys, km, 896)
     print(f"[gpu] lane forms, {len(km)} chunks", flush=True)
     ctx.load_keys(keys)
     classes = sorted(set(bits) - {768})
     default = {b: ctx.lanes(b) for b in classes}
     plan = ctx.plan(km, len(msg))
     try:
+        cs, cr = plan.encrypt_blinded(dev(torch, msg), dev(torch, rblk))
+        assert plan.check() == binding.PMK_OK
         for lanes in (1, 2, 4):
             for b in classes:
                 ctx.set_lanes(b, lanes, lanes)
@@ -265,6 +269,9 @@ def test_lane_forms_give_identical_bytes(torch, ctx):
                     pt = host(plan.decrypt(dev(torch, ct), batch=batch), len(msg))
                     assert plan.check() == binding.PMK_OK
                     assert (pt == msg).all(), f"lanes {lanes}, cap {cap}, batch {batch}"
+                pt = host(plan.decrypt_blinded(cs, cr), len(msg))
+                assert plan.check() == binding.PMK_OK
+                assert (pt == msg).all(), f"blinded, lanes {lanes}, cap {cap}"
         with pytest.raises(binding.PmkError) as ei:
             ctx.set_lanes(6144, 2)
         assert ei.value.status == binding.PMK_EUNSUPPORTED
