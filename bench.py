@@ -62,18 +62,20 @@ def joint_products(bits: int) -> int:
 # clock, 64 lanes per compute unit, 256 compute units, 2.4 GHz.
 PEAK_MAD_PER_S = 256 * 64 * 2.4e9
 
-# HBM traffic of one CRT-halves launch on the 100 MiB workload, from two
+# HBM traffic of the CRT-halves stage on the 100 MiB workload (halves_kernel
+# over four full rounds plus the lane-group tail, halves_lanes_kernel), from two
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) of
-# `bench.py --no-serve --steps 2 --warmup 1 --no-cpu-baseline`, each scaled by
-# what the counter reads for a plain 256 MiB device copy (bench.py
-# --copy-probe 256: FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of
-# them).  Valid only for the kernel sources it was measured on (hash below);
-# reported as null otherwise.
-HALVES_TRAFFIC = {"sources_sha256": "439380a8ac2b4c0256b782efefb76228eb7bea0b5260a9622bbca6896f41c982",
-                  "fetch_bytes": 20_126_950_058, "write_bytes": 2_556_861_269}
+# `bench.py --no-serve --no-cpu-baseline --no-e2e --no-blinded --steps 2
+# --warmup 1`, each scaled by what the counter reads for a plain 256 MiB device
+# copy (bench.py --copy-probe 256: FETCH_SIZE reads half the bytes moved,
+# WRITE_SIZE all of them).  Valid only for the kernel sources it was measured
+# on (hash below); reported as null otherwise.
+HALVES_TRAFFIC = {"sources_sha256": "21c6b76fb7cf88a35706b57489213df2db991b94b9a4517675d6184095d46700",
+                  "fetch_bytes": 20_048_678_282, "write_bytes": 2_572_764_160}
 KERNEL_SOURCES = ["paper_2111_11924_amd/csrc/kernels_impl.hpp", "paper_2111_11924_amd/csrc/mont.hpp",
                   "paper_2111_11924_amd/csrc/mont_lanes.hpp", "paper_2111_11924_amd/csrc/pmk_internal.hpp",
-                  "paper_2111_11924_amd/csrc/kernels_class.inc", "paper_2111_11924_amd/csrc/k2048.hip"]
+                  "paper_2111_11924_amd/csrc/kernels_class.inc", "paper_2111_11924_amd/csrc/k2048.hip",
+                  "paper_2111_11924_amd/csrc/klanes.hip"]
 
 
 def kernel_sources_sha256() -> str:

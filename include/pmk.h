@@ -238,9 +238,13 @@ int pmk_get_window(const pmk_ctx *ctx, uint32_t bits);
  *     or the largest smaller power of two whose waves fit one round,
  * each 1, 2 or 4: L lanes per number give L times the waves, each with a
  * shorter chain per Montgomery product, for about twice the instructions per
- * number.  The 6144/8192-bit classes always use 4 lanes (PMK_EUNSUPPORTED for
- * other values).  Results never change; graphs are recaptured; PMK_EBUSY
- * while a server runs.  pmk_get_lanes fills the current values.
+ * number.  The 6144/8192-bit classes run 4 lanes per number; their
+ * `fill_lanes` may be 8 (a launch whose 8-lane waves each get a SIMD of their
+ * own then runs with 8) and their `tail_lanes` must be 4; the one-lane classes
+ * take 1, 2 or 4 (PMK_EUNSUPPORTED for other supported counts, PMK_EINVAL for
+ * counts other than 1, 2, 4, 8).  Results never change; graphs are
+ * recaptured; PMK_EBUSY while a server runs.  pmk_get_lanes fills the current
+ * values.
  */
 int pmk_set_lanes(pmk_ctx *ctx, uint32_t bits, int fill_lanes, int tail_lanes);
 int pmk_get_lanes(const pmk_ctx *ctx, uint32_t bits, int *fill_lanes, int *tail_lanes);
@@ -264,14 +268,16 @@ int pmk_set_grid_limit(pmk_ctx *ctx, uint32_t waves);
  * same for any input) under the first key of that class -- four rounds of
  * resident waves at three window widths ({4,5,6} for 1024-bit classes and up,
  * {3,4,5} below), keeping the fastest (pmk_set_window); then, for the classes
- * with one lane per number, a quarter of a round and one and a third rounds
- * at 1, 2 and 4 lanes per number, keeping the fastest fill and tail forms
- * (pmk_set_lanes).  cache_path (may be NULL): a text file -- a signature line
- * (GPU architecture, compute units, HIP runtime version), then
- * "<class bits> <window> <fill lanes> <tail lanes> <ms>" lines.  When it exists and its signature
- * matches this device, its windows are applied without measuring, unless
- * flags has PMK_AUTOTUNE_FORCE; otherwise the measured choice is written
- * there.  Synchronous; allocates (and frees) its own device buffers; needs a
+ * with one lane per number, a launch of a quarter of the compute units' worth
+ * of job tiles and one of one and a third rounds at 1, 2 and 4 lanes per
+ * number, keeping the fastest fill and tail forms, and for the 6144/8192-bit
+ * classes the first of these at 4 and 8 lanes (pmk_set_lanes); a form with
+ * more lanes is kept only if it wins by 1 %.  cache_path (may be NULL): a
+ * text file -- a signature line (GPU architecture, compute units, HIP runtime
+ * version), then "<class bits> <window> <fill lanes> <tail lanes> <ms>"
+ * lines.  When it exists and its signature matches this device, its windows
+ * and lanes are applied without measuring, unless flags has
+ * PMK_AUTOTUNE_FORCE; otherwise the measured choice is written there.  Synchronous; allocates (and frees) its own device buffers; needs a
  * loaded key table (PMK_EINVAL otherwise).
  */
 enum { PMK_AUTOTUNE_FORCE = 1 };

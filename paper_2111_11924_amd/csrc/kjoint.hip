@@ -26,8 +26,8 @@ int launch_joint_class(const ClassRun &r, hipStream_t s) {
     const uint32_t units = 2 * r.ntiles * lanes_half(CB);
     uint32_t grid = persistent_grid(units, r.slots_dec, r.grid_cap);
     if (grid > resident) grid = resident;
-    // the part of a launch that leaves SIMDs idle runs in lane groups (one-lane
-    // classes), as for the plain CRT halves
+    // the part of a launch that leaves SIMDs idle runs in lane groups, as for
+    // the plain CRT halves
     uint32_t main_end = units;
     int L = 1;
     if constexpr (lanes_half(CB) == 1) {
@@ -37,6 +37,11 @@ int launch_joint_class(const ClassRun &r, hipStream_t s) {
         uint32_t lane_units = 0;
         L = lanes_for_launch(r, units, res, 4u * ncu, joint_lanes_resident, &lane_units);
         main_end = units - lane_units;
+    } else {
+        if (wide_fill(r, 2 * r.ntiles, lanes_half(CB), 4u * ncu, joint_lanes_resident(r.cls, 2 * lanes_half(CB)))) {
+            L = 2 * lanes_half(CB);
+            main_end = 0;
+        }
     }
     if (main_end) {
         const uint64_t slot = 2 * table_words_per_slot(r.cls, 1, r.win);  // two odd-power tables
@@ -45,7 +50,7 @@ int launch_joint_class(const ClassRun &r, hipStream_t s) {
         const int e = (int)hipGetLastError();
         if (e) return e;
     }
-    return main_end < units ? launch_joint_lanes(r, L, main_end, units, s) : 0;
+    return main_end < units ? launch_joint_lanes(r, L, main_end / lanes_half(CB), 2 * r.ntiles, s) : 0;
 }
 
 }  // namespace

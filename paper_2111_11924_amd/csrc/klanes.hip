@@ -1,9 +1,10 @@
-// CRT halves of the one-lane classes (128- to 4096-bit keys) in lane groups
-// of 2 or 4 lanes per number (halves_lanes_kernel), for the last partial round
-// of a CRT-halves launch and for launches too small to fill the chip: there a
-// wave per 64 numbers leaves most SIMDs with one wave or none, while a group
-// of L lanes per number gives L times the waves, each with a shorter
-// dependency chain per product.  A translation unit of its own, so the
+// CRT halves in lane groups (halves_lanes_kernel) for the part of a launch
+// that leaves SIMDs idle: the one-lane classes (128- to 4096-bit keys) with 2
+// or 4 lanes per number for the last partial round of a launch and for
+// launches too small to fill the chip, the lane-group classes (6144/8192) with
+// 8 instead of 4 for small launches.  There a wave per 64 (or 16) numbers
+// leaves most SIMDs with one wave or none, while L lanes per number give more
+// waves, each with a shorter dependency chain per product.  A translation unit of its own, so the
 // per-class objects stay as they are.
 #include "kernels_impl.hpp"
 
@@ -30,9 +31,9 @@ int launch_class(const ClassRun &r, uint32_t jt_begin, uint32_t jt_end, hipStrea
     constexpr uint64_t K = G.nla / L;
     const uint64_t slot = (uint64_t)(1u << (r.win - 1)) * K * kTile;  // odd powers, each lane's K limbs
     const uint32_t units = (jt_end - jt_begin) * L;
-    // at most the table's room (L lane-group slots per one-lane slot), the
-    // kernel's residency and the context's cap
-    uint32_t grid = persistent_grid(units, r.slots_dec * (uint32_t)L, r.grid_cap);
+    // at most the table's room (L / lanes_half lane-group slots per slot of
+    // the class's own form), the kernel's residency and the context's cap
+    uint32_t grid = persistent_grid(units, r.slots_dec * (uint32_t)(L / lanes_half(CB)), r.grid_cap);
     grid = std::min(grid, resident_of<CB, L>());
     hipLaunchKernelGGL((halves_lanes_kernel<CB, L>), dim3(grid), dim3(64), 0, s, r, slot, jt_begin * L, jt_end * L);
     return (int)hipGetLastError();
@@ -40,8 +41,12 @@ int launch_class(const ClassRun &r, uint32_t jt_begin, uint32_t jt_end, hipStrea
 
 template <int CB>
 int launch_L(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, hipStream_t s) {
-    if (L == 2) return launch_class<CB, 2>(r, jt_begin, jt_end, s);
-    if (L == 4) return launch_class<CB, 4>(r, jt_begin, jt_end, s);
+    if constexpr (lanes_half(CB) == 1) {
+        if (L == 2) return launch_class<CB, 2>(r, jt_begin, jt_end, s);
+        if (L == 4) return launch_class<CB, 4>(r, jt_begin, jt_end, s);
+    } else {
+        if (L == 2 * lanes_half(CB)) return launch_class<CB, 2 * lanes_half(CB)>(r, jt_begin, jt_end, s);
+    }
     return (int)hipErrorInvalidValue;
 }
 
@@ -75,6 +80,8 @@ uint32_t lanes_resident(int cls, int L) {
         case 5 * 8 + 4: return resident_of<3072, 4>();
         case 6 * 8 + 2: return resident_of<4096, 2>();
         case 6 * 8 + 4: return resident_of<4096, 4>();
+        case 7 * 8 + 2 * lanes_half(6144): return resident_of<6144, 2 * lanes_half(6144)>();
+        case 8 * 8 + 2 * lanes_half(8192): return resident_of<8192, 2 * lanes_half(8192)>();
         default: return 0;
     }
 }
@@ -90,6 +97,8 @@ int launch_halves_lanes(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt
         case 4: return launch_L<2048>(r, L, jt_begin, jt_end, s);
         case 5: return launch_L<3072>(r, L, jt_begin, jt_end, s);
         case 6: return launch_L<4096>(r, L, jt_begin, jt_end, s);
+        case 7: return launch_L<6144>(r, L, jt_begin, jt_end, s);
+        case 8: return launch_L<8192>(r, L, jt_begin, jt_end, s);
         default: return (int)hipErrorNotSupported;
     }
 }

@@ -140,9 +140,8 @@ int pmk_create(int device, pmk_ctx **out) {
     ctx->device_name = prop.gcnArchName;
     for (int c = 0; c < kNumClasses; ++c) {
         ctx->win[c] = window_for(kClassBits[c] / 2);
-        const int fixed = lanes_half(kClassBits[c]);
-        ctx->fill_lanes[c] = fixed > 1 ? fixed : default_fill_lanes(kClassBits[c]);
-        ctx->tail_lanes[c] = fixed > 1 ? fixed : default_tail_lanes(kClassBits[c]);
+        ctx->fill_lanes[c] = default_fill_lanes(kClassBits[c]);
+        ctx->tail_lanes[c] = default_tail_lanes(kClassBits[c]);
     }
     ctx->err.reserve(600);  // messages (below 512 bytes) are then stored without allocating
     // the allocation-free entry point reports it if its scratch is unavailable
@@ -707,12 +706,16 @@ int pmk_set_lanes(pmk_ctx *ctx, uint32_t bits, int fill_lanes, int tail_lanes) {
     if (!ctx) return PMK_EINVAL;
     const int c = class_for_bits(bits);
     if (c < 0) return set_err(ctx, PMK_EUNSUPPORTED, "no size class for %u bits", bits);
-    auto ok = [](int l) { return l == 1 || l == 2 || l == 4; };
-    if (!ok(fill_lanes) || !ok(tail_lanes)) return set_err(ctx, PMK_EINVAL, "lanes per number must be 1, 2 or 4");
-    const int fixed = lanes_half(kClassBits[c]);
-    if (fixed > 1 && (fill_lanes != fixed || tail_lanes != fixed))
-        return set_err(ctx, PMK_EUNSUPPORTED, "the %d-bit class always runs its CRT halves in groups of %d lanes",
-                       kClassBits[c], fixed);
+    auto ok = [](int l) { return l == 1 || l == 2 || l == 4 || l == 8; };
+    if (!ok(fill_lanes) || !ok(tail_lanes)) return set_err(ctx, PMK_EINVAL, "lanes per number must be 1, 2, 4 or 8");
+    if (!lanes_valid(kClassBits[c], fill_lanes, tail_lanes)) {
+        const int fixed = lanes_half(kClassBits[c]);
+        if (fixed == 1)
+            return set_err(ctx, PMK_EUNSUPPORTED, "the %d-bit class takes 1, 2 or 4 lanes per number", kClassBits[c]);
+        return set_err(ctx, PMK_EUNSUPPORTED,
+                       "the %d-bit class runs its CRT halves in groups of %d lanes (small launches %d or %d)",
+                       kClassBits[c], fixed, fixed, 2 * fixed);
+    }
     if (ctx->server) return set_err(ctx, PMK_EBUSY, "lane settings are fixed while a server runs");
     if (ctx->fill_lanes[c] != fill_lanes || ctx->tail_lanes[c] != tail_lanes) {
         ctx->fill_lanes[c] = fill_lanes;
@@ -775,8 +778,7 @@ bool tune_load(pmk_ctx *ctx, const char *path) {
     while (ok && std::fgets(line, sizeof line, f)) {
         if (std::sscanf(line, "%u %d %d %d", &bits, &win, &fl, &tl) != 4) continue;
         const int c = class_for_bits(bits);
-        auto lanes_ok = [](int l) { return l == 1 || l == 2 || l == 4; };
-        if (c < 0 || kClassBits[c] != (int)bits || win < 2 || win > kMaxWin || !lanes_ok(fl) || !lanes_ok(tl)) {
+        if (c < 0 || kClassBits[c] != (int)bits || win < 2 || win > kMaxWin || !lanes_valid(kClassBits[c], fl, tl)) {
             ok = false;
             break;
         }
@@ -894,11 +896,28 @@ int pmk_autotune(pmk_ctx *ctx, const char *cache_path, int flags) {
         if (ct) (void)hipFree(ct);
         if (out) (void)hipFree(out);
         pmk_plan_destroy(pl);
-        // lanes per number where a launch leaves the chip idle (one-lane
-        // classes): one unit per two compute units (fill), then one and a
-        // third rounds of resident waves (the last third is the tail); a lane
-        // form must win by 1 %
+        // lanes per number where a launch leaves the chip idle: one-lane
+        // classes: one unit per two compute units (fill), then one and a third
+        // rounds of resident waves (the last third is the tail); lane-group
+        // classes: the fill form only (their own or twice as many lanes); a
+        // wider form must win by 1 %
         int best_fill = ctx->fill_lanes[c], best_tail = ctx->tail_lanes[c];
+        if (rc == PMK_OK && lanes_half(cb) > 1) {
+            const int L0 = lanes_half(cb);
+            const uint64_t size = std::max<uint64_t>(1, (uint64_t)ctx->num_cus / 4);
+            float lbest = 1e30f;
+            for (int L : {L0, 2 * L0}) {
+                (void)pmk_set_lanes(ctx, (uint32_t)cb, L, L0);
+                float ms = 0.f;
+                rc = tune_batch(ctx, k0, size, st, 3, &ms);
+                if (rc != PMK_OK) break;
+                if (ms < (L == L0 ? 1.0f : 0.99f) * lbest) {
+                    lbest = ms;
+                    best_fill = L;
+                }
+            }
+            (void)pmk_set_lanes(ctx, (uint32_t)cb, best_fill, L0);
+        }
         if (rc == PMK_OK && lanes_half(cb) == 1) {
             const uint64_t resident = wave_slots(c, 1, ctx->num_cus);  // one-lane waves, 2 per tile
             const uint64_t sizes[2] = {std::max<uint64_t>(1, (uint64_t)ctx->num_cus / 4),

@@ -149,9 +149,9 @@ struct ClassRun {
     uint8_t *slot_err;         // optional, per descriptor slot: 1 where unpacking rejected the chunk
     uint32_t grid_cap;         // 0, or the most resident waves a persistent launch may use
     int win;                   // window width of the CRT-halves exponentiation (3..6)
-    int fill_lanes;            // one-lane classes: lanes per number (1, 2 or 4) of the CRT halves of a
-                               // launch that fills at most half of one round of resident waves
-    int tail_lanes;            // the same for the last partial round (at most half a round) after full ones
+    int fill_lanes;            // lanes per number of the CRT halves of a launch under one round
+                               // (one-lane classes 1, 2 or 4; lane-group classes lanes_half or twice it)
+    int tail_lanes;            // one-lane classes: the same for the partial round after full ones
     // blinded PMKRSA (Sec. 3.1, Algorithm 1)
     const uint32_t *fin32;     // encryption: words of a factor v < N the result is multiplied by
                                // (x^e v mod N; tile layout of y32), nullptr = 1; blinded decryption:
@@ -163,8 +163,18 @@ constexpr int kMaxWin = 6;
 // fills at most half a round, and in a short last round after full ones
 // (measured: 4 lanes cut a 1 MiB 2048-bit decryption by a fifth; a 2-lane
 // last round of the 100 MiB one is about even)
-PMK_HD constexpr int default_fill_lanes(int bits) { return bits >= 1024 && lanes_half(bits) == 1 ? 4 : 1; }
-PMK_HD constexpr int default_tail_lanes(int bits) { return bits == 2048 ? 2 : 1; }
+// Lanes-per-number settings a class takes: a one-lane class 1, 2 or 4 for
+// both forms; a lane-group class its own count L0 or 2 L0 for small launches,
+// L0 for the tail form.
+PMK_HD constexpr bool lanes_valid(int bits, int fill, int tail) {
+    return lanes_half(bits) == 1
+               ? ((fill == 1 || fill == 2 || fill == 4) && (tail == 1 || tail == 2 || tail == 4))
+               : ((fill == lanes_half(bits) || fill == 2 * lanes_half(bits)) && tail == lanes_half(bits));
+}
+PMK_HD constexpr int default_fill_lanes(int bits) {
+    return lanes_half(bits) > 1 ? 2 * lanes_half(bits) : (bits >= 1024 ? 4 : 1);
+}
+PMK_HD constexpr int default_tail_lanes(int bits) { return lanes_half(bits) > 1 ? lanes_half(bits) : (bits == 2048 ? 2 : 1); }
 
 // One persistent launch over the exponentiation work of the 1024- to 4096-bit
 // classes of a plan: units (tiles, or job tiles of CRT halves) are numbered
@@ -194,14 +204,15 @@ int launch_garner(const ClassRun &r, void *stream);
 // with c* at r.x32 and c_R at r.fin32; tables need 2 table_words_per_slot(cls, 1, win)
 // words per slot
 int launch_decrypt_joint(const ClassRun &r, void *stream);
-// CRT halves of job tiles [jt_begin, jt_end) of a one-lane class (128..4096
-// bits) in lane groups of L = 2 or 4 lanes per number (klanes.hip)
+// CRT halves of job tiles [jt_begin, jt_end) in lane groups of L lanes per
+// number: a one-lane class (128..4096 bits) with L = 2 or 4, a lane-group class
+// (6144/8192 bits) with twice its own L (klanes.hip)
 int launch_halves_lanes(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, void *stream);
 // resident waves of that lane-group kernel on the current device (0: no such kernel)
 uint32_t lanes_resident(int cls, int L);
-// Blinded decryption (one pass per prime) of job tiles [jt_begin, jt_end) of a
-// one-lane class in lane groups of L = 2 or 4 lanes, and that kernel's
-// resident waves (kjlanes.hip)
+// Blinded decryption (one pass per prime) of job tiles [jt_begin, jt_end) in
+// lane groups of L lanes (a one-lane class: 2 or 4; a lane-group class: twice
+// its own), and that kernel's resident waves (kjlanes.hip)
 int launch_joint_lanes(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, void *stream);
 uint32_t joint_lanes_resident(int cls, int L);
 
@@ -238,6 +249,19 @@ inline int lanes_for_launch(const ClassRun &r, uint32_t units, uint32_t resident
         L = fit(r.tail_lanes, UINT64_MAX);
     if (L > 1) *lane_units = rem;
     return L;
+}
+
+// The lane-group classes (6144/8192-bit keys, L0 = lanes_half lanes per
+// number): a launch of jt job tiles runs with r.fill_lanes = 2 L0 lanes per
+// number when every such wave has a SIMD of its own and fits one round of
+// that kernel (room: its resident waves) and the table (two such slots per
+// slot of the L0 form).
+inline bool wide_fill(const ClassRun &r, uint32_t jt, int L0, uint32_t simds, uint32_t room) {
+    if (r.fill_lanes != 2 * L0) return false;
+    uint64_t lim = simds < room ? simds : room;
+    if ((uint64_t)r.slots_dec * 2 < lim) lim = (uint64_t)r.slots_dec * 2;
+    if (r.grid_cap && r.grid_cap < lim) lim = r.grid_cap;
+    return (uint64_t)jt * (uint64_t)r.fill_lanes <= lim;
 }
 // compute units of the current device
 int device_cus();

@@ -349,7 +349,7 @@ def test_window_width_never_changes_results(torch, ctx, win):
 
 
 def test_autotune_cache_and_results(torch, ctx, tmp_path):
-    bits = [2048, 1024, 512]
+    bits = [2048, 1024, 512, 6144]
     keys = inputs.make_keys(bits, 840)
     ctx.load_keys(keys)
     default = {b: ctx.window(b) for b in bits}
@@ -365,11 +365,14 @@ def test_autotune_cache_and_results(torch, ctx, tmp_path):
             w, fill, tail = chosen[b]
             assert ctx.window(b) == w and ctx.lanes(b) == (fill, tail)
             assert w in ((4, 5, 6) if b >= 1024 else (3, 4, 5))
-            assert fill in (1, 2, 4) and tail in (1, 2, 4)
+            if b >= 6144:  # lane-group class: its own 4 lanes, or 8 for small launches
+                assert fill in (4, 8) and tail == 4
+            else:
+                assert fill in (1, 2, 4) and tail in (1, 2, 4)
         # the cache is applied without measuring
         for b in bits:
             ctx.set_window(b, 2)
-            ctx.set_lanes(b, 1, 1)
+            ctx.set_lanes(b, *((4, 4) if b >= 6144 else (1, 1)))
         ctx.autotune(cache)
         assert all(ctx.window(b) == chosen[b][0] and ctx.lanes(b) == tuple(chosen[b][1:]) for b in bits)
         msg = inputs.make_message(30_000 + 3, 840)
@@ -481,10 +484,11 @@ def oracle_many(fn, jobs):
 
 
 @pytest.mark.parametrize("bits,lanes", [(b, l) for b in (1024, 2048, 3072, 4096) for l in (1, 2, 4)]
-                         + [(6144, 4), (8192, 4)])
+                         + [(6144, 4), (6144, 8), (8192, 4), (8192, 8)])
 def test_unusual_crt_exponents(torch, ctx, bits, lanes):
     """(lanes: lanes per number of the CRT halves where the launch leaves the
-    chip mostly idle -- here every launch, 6 keys x 70 chunks.)"""
+    chip mostly idle -- here every launch, 6 keys x 70 chunks; the 6144/8192-bit
+    classes take 4, or 8 for such launches.)"""
     base = base_key(bits)
     h = bits // 2
     keys = []
@@ -505,7 +509,7 @@ def test_unusual_crt_exponents(torch, ctx, bits, lanes):
     plan = ctx.plan(km, msg_len)
     T = oracle.KeyTable(keys)
     try:
-        ctx.set_lanes(bits, lanes, lanes)
+        ctx.set_lanes(bits, lanes, min(lanes, 4))
         plan.set_decrypt_output(binding.PMK_DEC_BLOCKS)
         d_m = plan.decrypt(dev(torch, ct))
         assert plan.check() == binding.PMK_OK
@@ -524,7 +528,7 @@ def test_unusual_crt_exponents(torch, ctx, bits, lanes):
 
 
 @pytest.mark.parametrize("bits,lanes", [(b, l) for b in (1024, 2048, 3072, 4096) for l in (1, 2, 4)]
-                         + [(6144, 4), (8192, 4)])
+                         + [(6144, 4), (6144, 8), (8192, 4), (8192, 8)])
 def test_blinded_decryption_with_unusual_exponents(torch, ctx, bits, lanes):
     """Blinded decryption (c* and c_R in one squaring chain per prime) with
     private exponents of unusual shape: d below both primes, so dp = dq = d
@@ -556,7 +560,7 @@ def test_blinded_decryption_with_unusual_exponents(torch, ctx, bits, lanes):
     T = oracle.KeyTable(keys)
     default = ctx.lanes(bits)
     try:
-        ctx.set_lanes(bits, lanes, lanes)
+        ctx.set_lanes(bits, lanes, min(lanes, 4))
         plan.set_decrypt_output(binding.PMK_DEC_BLOCKS)
         d_m = plan.decrypt_blinded(dev(torch, cs), dev(torch, cr))
         assert plan.check() == binding.PMK_OK

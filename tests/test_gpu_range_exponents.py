@@ -275,7 +275,15 @@ def test_lane_forms_give_identical_bytes(torch, ctx):
         with pytest.raises(binding.PmkError) as ei:
             ctx.set_lanes(6144, 2)
         assert ei.value.status == binding.PMK_EUNSUPPORTED
-        ctx.set_lanes(8192, 4)  # its fixed form is accepted
+        ctx.set_lanes(8192, 4)  # its own form is accepted, and 8 lanes for small launches
+        ctx.set_lanes(8192, 8, 4)
+        with pytest.raises(binding.PmkError) as ei:
+            ctx.set_lanes(8192, 8, 8)  # the tail form stays at 4
+        assert ei.value.status == binding.PMK_EUNSUPPORTED
+        with pytest.raises(binding.PmkError) as ei:
+            ctx.set_lanes(2048, 8)  # one-lane classes take 1, 2 or 4
+        assert ei.value.status == binding.PMK_EUNSUPPORTED
+        ctx.set_lanes(8192, 4, 4)
         with pytest.raises(binding.PmkError) as ei:
             ctx.set_lanes(2048, 3)
         assert ei.value.status == binding.PMK_EINVAL
