@@ -1440,89 +1440,112 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(make_geom(CB
 }
 
 // The CRT recombination of the 6144/8192-bit classes (CRT halves of 112/152
-// limbs, kept per lane): the same steps with rolled loops over arrays the
-// compiler places in scratch memory -- the halves are spread over lane groups
-// for the exponentiation, but this once-per-chunk step does not need it.
-template <int NL, int LB>
-PMK_DEV void mont_mul_rolled(uint32_t *r, const uint32_t *a, const uint32_t *b, const uint32_t *n, uint32_t n0) {
-    constexpr uint32_t MASK = Radix<LB>::MASK;
-    static_assert((2.0 * NL + 1) * (double)(1ull << LB) * (double)(1ull << LB) < 18446744073709551615.0,
-                  "column sums may overflow 64 bits");
-    uint64_t t[NL];
-#pragma unroll 1
-    for (int j = 0; j < NL; ++j) t[j] = 0;
-#pragma unroll 1
-    for (int i = 0; i < NL; ++i) {  // operand scanning: t = (t + a b_i + m_i n) / 2^LB
-        const uint64_t bi = b[i];
-#pragma unroll 1
-        for (int j = 0; j < NL; ++j) t[j] += (uint64_t)a[j] * bi;
-        const uint64_t m = ((uint32_t)t[0] * n0) & MASK;
-#pragma unroll 1
-        for (int j = 0; j < NL; ++j) t[j] += m * n[j];
-        const uint64_t c = t[0] >> LB;
-#pragma unroll 1
-        for (int j = 0; j + 1 < NL; ++j) t[j] = t[j + 1];
-        t[NL - 1] = 0;
-        t[0] += c;
-    }
-    uint64_t c = 0;
-#pragma unroll 1
-    for (int j = 0; j < NL; ++j) {
-        const uint64_t v = t[j] + c;
-        r[j] = (uint32_t)v & MASK;
-        c = v >> LB;
-    }
-}
-// x < 2m -> x mod m (rolled)
-template <int NL, int LB>
-PMK_DEV void canonicalize_rolled(uint32_t *x, const uint32_t *n) {
-    constexpr uint32_t MASK = Radix<LB>::MASK;
-    uint32_t d[NL];
-    int32_t borrow = 0;
-#pragma unroll 1
-    for (int j = 0; j < NL; ++j) {
-        const int32_t v = (int32_t)x[j] - (int32_t)n[j] - borrow;
-        d[j] = (uint32_t)v & MASK;
-        borrow = v < 0 ? 1 : 0;
-    }
-    if (!borrow) {
-#pragma unroll 1
-        for (int j = 0; j < NL; ++j) x[j] = d[j];
-    }
-}
+// limbs, one lane per chunk slot): the numbers do not fit a lane's registers,
+// so each lane keeps them in LDS, [limb][lane] rows that 32 lanes read without
+// bank conflicts (32 slots per block: a block never spans two tiles, so p, q
+// and the constants are the block's, staged once).  Operand-scanning
+// Montgomery product over a circular accumulator (no shifting: at step i
+// logical limb j of t sits in row (i + j) mod (NL + 1)), then the schoolbook
+// product h q column by column, written out word by word.
+constexpr int kGarnerLdsSlots = 32;
 
 template <int CB>
-__global__ __launch_bounds__(64) void garner_rolled_kernel(const uint32_t *__restrict__ keys,
-                                                           const ChunkDesc *__restrict__ desc, uint32_t nslots,
-                                                           const uint32_t *__restrict__ half,
-                                                           uint32_t *__restrict__ y32) {
+__global__ __launch_bounds__(kGarnerLdsSlots) void garner_lds_kernel(const uint32_t *__restrict__ keys,
+                                                                     const ChunkDesc *__restrict__ desc,
+                                                                     uint32_t nslots,
+                                                                     const uint32_t *__restrict__ half,
+                                                                     uint32_t *__restrict__ y32) {
     constexpr Geom G = make_geom(CB);
-    constexpr int NL = G.nlh, LB = G.lbh, S = G.S, CPT = chunks_per_tile(CB);
+    constexpr int NL = G.nlh, LB = G.lbh, S = G.S, CPT = chunks_per_tile(CB), B = kGarnerLdsSlots, M = NL + 1;
     constexpr uint32_t MASK = Radix<LB>::MASK;
-    const uint32_t slot0 = blockIdx.x * 64 + threadIdx.x;
+    static_assert(CPT % B == 0, "a block must lie within one tile");
+    static_assert((2.0 * NL + 1) * (double)(1ull << LB) * (double)(1ull << LB) < 18446744073709551615.0,
+                  "column sums may overflow 64 bits");
+    __shared__ uint64_t t[M][B];      // the product's accumulator (circular)
+    __shared__ uint32_t a[NL][B];     // m_p + p - m_q, then h
+    __shared__ uint32_t pn[NL], qinv[NL], qn[NL];
+    const int lane = threadIdx.x;
+    const uint32_t slot0 = blockIdx.x * B + lane;
     const uint32_t slot = slot0 < nslots ? slot0 : nslots - 1;
     const uint32_t tile = slot / CPT, c = slot % CPT;
-    const uint32_t *kr = keys + (size_t)desc[slot].key * G.stride;
+    // the block's key (every slot of a tile, padding included, carries it)
+    const uint32_t *kr = keys + (size_t)desc[(size_t)blockIdx.x * B].key * G.stride;
     const uint32_t *hp = kr + G.off_half[0];
     const uint32_t *hq = kr + G.off_half[1];
+    for (int j = lane; j < NL; j += B) {
+        pn[j] = hp[G.h_m + j];
+        qinv[j] = kr[G.off_qinvr + j];
+        qn[j] = hq[G.h_m + j];
+    }
+    const uint32_t n0 = hp[G.h_m0];
+    __syncthreads();
     const uint32_t *mp_src = half + ((size_t)(2 * tile) * NL) * CPT + c;
     const uint32_t *mq_src = half + ((size_t)(2 * tile + 1) * NL) * CPT + c;
-    uint32_t a[NL], q[NL];
     {
         // a = m_p + p - m_q, in (0, 2p)
         int32_t cy = 0;
-#pragma unroll 1
+#pragma unroll 4
         for (int j = 0; j < NL; ++j) {
-            const int32_t v = (int32_t)mp_src[(size_t)j * CPT] + (int32_t)hp[G.h_m + j] -
-                              (int32_t)mq_src[(size_t)j * CPT] + cy;
-            a[j] = (uint32_t)v & MASK;
+            const int32_t v = (int32_t)mp_src[(size_t)j * CPT] + (int32_t)pn[j] - (int32_t)mq_src[(size_t)j * CPT] + cy;
+            a[j][lane] = (uint32_t)v & MASK;
             cy = v >> LB;
         }
     }
-    mont_mul_rolled<NL, LB>(a, a, kr + G.off_qinvr, hp + G.h_m, hp[G.h_m0]);
-    canonicalize_rolled<NL, LB>(a, hp + G.h_m);  // h
+#pragma unroll 4
+    for (int j = 0; j < M; ++j) t[j][lane] = 0;
+    // t = a qinv R^-1 (mod p) by operand scanning: at step i, t += a qinv_i,
+    // then + m_i p, then divide by 2^LB; logical limb j of t in row (i + j) mod M
 #pragma unroll 1
-    for (int j = 0; j < NL; ++j) q[j] = hq[G.h_m + j];
+    for (int i = 0; i < NL; ++i) {
+        const uint64_t bi = qinv[i];
+        int r = i;
+#pragma unroll 4
+        for (int j = 0; j < NL; ++j) {
+            t[r][lane] += (uint64_t)a[j][lane] * bi;
+            r = r + 1 == M ? 0 : r + 1;
+        }
+        const uint64_t t0 = t[i][lane];
+        const uint64_t m = ((uint32_t)t0 * n0) & MASK;
+        r = i;
+#pragma unroll 4
+        for (int j = 0; j < NL; ++j) {
+            t[r][lane] += m * pn[j];
+            r = r + 1 == M ? 0 : r + 1;
+        }
+        // the lowest limb is now a multiple of 2^LB: its carry moves up, its row
+        // becomes the spare row (logical limb NL) of the next step
+        const uint64_t carry = t[i][lane] >> LB;
+        t[i][lane] = 0;
+        const int r1 = i + 1 == M ? 0 : i + 1;
+        t[r1][lane] += carry;
+    }
+    // settle the carries of the result (logical limb j in row (NL + j) mod M)
+    {
+        uint64_t cy = 0;
+        int r = NL % M;
+#pragma unroll 4
+        for (int j = 0; j < NL; ++j) {
+            const uint64_t v = t[r][lane] + cy;
+            a[j][lane] = (uint32_t)v & MASK;
+            cy = v >> LB;
+            r = r + 1 == M ? 0 : r + 1;
+        }
+    }
+    // a < 2p -> h = a mod p: keep a - p when it does not borrow
+    {
+        int32_t borrow = 0;
+#pragma unroll 4
+        for (int j = 0; j < NL; ++j) borrow = ((int32_t)a[j][lane] - (int32_t)pn[j] - borrow) < 0 ? 1 : 0;
+        if (!borrow) {
+            borrow = 0;
+#pragma unroll 4
+            for (int j = 0; j < NL; ++j) {
+                const int32_t v = (int32_t)a[j][lane] - (int32_t)pn[j] - borrow;
+                a[j][lane] = (uint32_t)v & MASK;
+                borrow = v < 0 ? 1 : 0;
+            }
+        }
+    }
     // m = m_q + h q, column by column, written out word by word as columns complete
     uint64_t cy = 0, wacc = 0;
     int wbits = 0, k32 = 0;
@@ -1530,8 +1553,8 @@ __global__ __launch_bounds__(64) void garner_rolled_kernel(const uint32_t *__res
     for (int k = 0; k < 2 * NL && k32 < S; ++k) {
         uint64_t acc = cy + (k < NL ? mq_src[(size_t)k * CPT] : 0u);
         const int lo = k - NL + 1 > 0 ? k - NL + 1 : 0, hi = k < NL ? k : NL - 1;
-#pragma unroll 1
-        for (int i = lo; i <= hi; ++i) acc += (uint64_t)a[i] * q[k - i];
+#pragma unroll 4
+        for (int i = lo; i <= hi; ++i) acc += (uint64_t)a[i][lane] * qn[k - i];
         wacc |= (uint64_t)((uint32_t)acc & MASK) << wbits;
         wbits += LB;
         cy = acc >> LB;
