@@ -322,19 +322,24 @@ int pmk_decrypt(pmk_ctx *ctx, const uint8_t *d_ct, uint64_t ct_len, const uint32
 
 /*
  * Host-buffer forms (the paper's transfer / compute / merge pipeline of its
- * CPU+GPU implementation, Sec. 3.3): msg and ct are HOST memory (pinned -- hipHostMalloc, or a torch
- * tensor with pin_memory -- for asynchronous copies; pageable memory works,
- * with copies the runtime stages itself).  The plan's chunk range is cut into
- * `slices` runs of chunks of about equal bytes; slice s is copied to the
- * device, encrypted or decrypted, and copied back on three streams, so the
- * copies of one slice overlap the computation of the others.  slices = 0
- * picks one slice for decryption (its copies are a tiny part of its time) and
- * up to four, of at least 65,536 chunks each, for encryption.  Sizes as
- * pmk_encrypt_plan / pmk_decrypt_plan (the decryption output form of the plan
- * applies).  Synchronous: returns once the output is in host memory, with the
- * device-detected status (PMK_ERANGE as pmk_plan_check).  The first call with
- * a slice count plans its slices and allocates device copies of the whole
- * input and output (kept with the plan); calls on one plan must not overlap.
+ * CPU+GPU implementation, Sec. 3.3): msg and ct are HOST memory (pinned --
+ * hipHostMalloc, or a torch tensor with pin_memory -- for asynchronous copies;
+ * pageable memory works, with copies the runtime stages itself).  The plan's
+ * chunk range is cut into `slices` runs of chunks of about equal bytes; slice
+ * s is copied to the device, encrypted or decrypted, and copied back on three
+ * streams, so the copies of one slice overlap the computation of the others.
+ * slices = 0 picks, for encryption, up to four slices of at least 65,536
+ * chunks each; for decryption, slices that each end on a whole round of CRT
+ * work (1, 2, 4, ... rounds of resident waves) where the key map allows it (a
+ * plan of one size class up to 4096 bits whose slices give every key only full
+ * tiles, as a round-robin map does), else one slice -- so slicing adds no
+ * partial round.  Sizes as pmk_encrypt_plan / pmk_decrypt_plan (the
+ * decryption output form of the plan applies).  Synchronous: returns once the
+ * output is in host memory, with the device-detected status (PMK_ERANGE as
+ * pmk_plan_check).  The first call of a direction with a slicing plans its
+ * slices (kept per direction) and the first call allocates device copies of
+ * the whole input and output (kept with the plan); calls on one plan must not
+ * overlap.
  */
 int pmk_encrypt_host(pmk_plan *plan, const uint8_t *msg, uint8_t *ct, uint32_t slices);
 int pmk_decrypt_host(pmk_plan *plan, const uint8_t *ct, uint8_t *msg, uint32_t slices);

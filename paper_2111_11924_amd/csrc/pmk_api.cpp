@@ -56,14 +56,15 @@ void drop_graphs(pmk_plan *pl) {
 void free_plan_memory(pmk_plan *pl) {
     drop_timings(pl);
     drop_graphs(pl);
-    for (pmk_plan *s : pl->hp_sub) pmk_plan_destroy(s);
-    pl->hp_sub.clear();
+    for (auto &h : pl->hp) {
+        for (pmk_plan *s : h.sub) pmk_plan_destroy(s);
+        for (hipEvent_t ev : h.ev) (void)hipEventDestroy(ev);
+        h = pmk_plan::HostSlices{};
+    }
     for (int i = 0; i < pmk_plan::kPipe; ++i) {
         if (pl->hp_stream[i]) (void)hipStreamDestroy(pl->hp_stream[i]);
         pl->hp_stream[i] = nullptr;
     }
-    for (hipEvent_t ev : pl->hp_ev) (void)hipEventDestroy(ev);
-    pl->hp_ev.clear();
     if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
     for (int i = 0; i < pmk_plan::kSide; ++i) {
         if (pl->side_stream[i]) (void)hipStreamDestroy(pl->side_stream[i]);
@@ -1059,7 +1060,45 @@ namespace {
 // runs of chunks of about equal message bytes, each planned on its own (its
 // offsets relative to the slice), device copies of the whole input and output,
 // and the pipeline's streams and events.
-int host_prepare(pmk_plan *pl, uint32_t n) {
+// Cuts of a decryption into slices that each end on a whole round of CRT
+// work: a plan of one one-lane class whose slices [0, c_1), [c_1, c_2), ...
+// give every key only full tiles and 1, 2, 4, ... rounds of job tiles (one
+// job tile per resident wave) -- so slicing adds no partial round, and the
+// copies of one slice overlap the kernels of its neighbours.  Empty when the
+// key map has no such cuts (then one slice).
+std::vector<uint64_t> round_cuts(const pmk_plan *pl) {
+    const pmk_ctx *ctx = pl->ctx;
+    std::vector<uint64_t> cuts;
+    if (pl->nchunks == 0) return cuts;
+    const int c = ctx->keys[pl->key_map[0]].cls;
+    if (lanes_half(kClassBits[c]) != 1) return cuts;
+    for (uint64_t i = 0; i < pl->nchunks; ++i)
+        if (ctx->keys[pl->key_map[i]].cls != c) return cuts;
+    const uint64_t tiles_per_round = std::max<uint32_t>(1, wave_slots(c, 1, ctx->num_cus) / 2);
+    std::vector<uint32_t> cnt(ctx->keys.size(), 0);
+    uint64_t tiles = 0, ragged = 0, want = tiles_per_round;
+    for (uint64_t i = 0; i < pl->nchunks; ++i) {
+        uint32_t &n = cnt[pl->key_map[i]];
+        if (n % kTile == 0) {
+            ++tiles;
+            ++ragged;
+        }
+        if (++n % kTile == 0) --ragged;
+        if (ragged == 0 && tiles == want && i + 1 < pl->nchunks) {
+            cuts.push_back(i + 1);
+            want = 2 * want + tiles_per_round;  // next slice twice as long
+        } else if (tiles > want) {
+            want = (tiles / tiles_per_round + 1) * tiles_per_round;  // no cut there: the next round end
+        }
+    }
+    return cuts;
+}
+
+// Host pipeline of a plan: its chunks cut into slices -- n slices of about
+// equal message bytes, or (n = 0) the round cuts of a decryption -- each
+// planned on its own (offsets relative to the slice), per direction; device
+// copies of the whole input and output, and the pipeline's streams.
+int host_prepare(pmk_plan *pl, int decrypt, uint32_t n) {
     pmk_ctx *ctx = pl->ctx;
     if (!pl->hp_in) {
         hipError_t e = dev_alloc(pl, &pl->hp_in, pl->ct_len);  // ct_len >= msg_len
@@ -1068,48 +1107,57 @@ int host_prepare(pmk_plan *pl, uint32_t n) {
             e = hipStreamCreateWithFlags(&pl->hp_stream[i], hipStreamNonBlocking);
         if (e != hipSuccess) return hip_err(ctx, e, "host pipeline setup");
     }
-    if (pl->hp_n == n) return PMK_OK;
+    pmk_plan::HostSlices &h = pl->hp[decrypt ? 1 : 0];
+    const uint32_t key = n ? n : UINT32_MAX;  // n of the round cuts
+    if (h.n == key) return PMK_OK;
     (void)hipDeviceSynchronize();
-    for (pmk_plan *s : pl->hp_sub) pmk_plan_destroy(s);
-    pl->hp_sub.clear();
-    for (hipEvent_t ev : pl->hp_ev) (void)hipEventDestroy(ev);
-    pl->hp_ev.clear();
-    pl->hp_chunk.assign(1, 0);
-    pl->hp_msg.assign(1, 0);
-    pl->hp_ct.assign(1, 0);
+    for (pmk_plan *s : h.sub) pmk_plan_destroy(s);
+    for (hipEvent_t ev : h.ev) (void)hipEventDestroy(ev);
+    h = pmk_plan::HostSlices{};
+    h.chunk.assign(1, 0);
+    h.msg.assign(1, 0);
+    h.ct.assign(1, 0);
+    const std::vector<uint64_t> cuts = n ? std::vector<uint64_t>() : round_cuts(pl);
+    size_t next_cut = 0;
     uint64_t off = 0, ct = 0;
     for (uint64_t i = 0; i < pl->nchunks; ++i) {
         const uint32_t kb = ctx->keys[pl->key_map[i]].bits / 8;
         off += std::min<uint64_t>(kb - 4, pl->msg_len - off);
         ct += kb;
-        const uint64_t s = pl->hp_chunk.size();  // next cut: s / n of the message
-        if (s < n && off * n >= s * pl->msg_len) {
-            pl->hp_chunk.push_back(i + 1);
-            pl->hp_msg.push_back(off);
-            pl->hp_ct.push_back(ct);
+        bool cut = false;
+        if (n) {
+            const uint64_t s = h.chunk.size();  // next cut: s / n of the message
+            cut = s < n && off * n >= s * pl->msg_len;
+        } else {
+            cut = next_cut < cuts.size() && cuts[next_cut] == i + 1;
+            if (cut) ++next_cut;
+        }
+        if (cut) {
+            h.chunk.push_back(i + 1);
+            h.msg.push_back(off);
+            h.ct.push_back(ct);
         }
     }
-    if (pl->hp_chunk.back() != pl->nchunks) {
-        pl->hp_chunk.push_back(pl->nchunks);
-        pl->hp_msg.push_back(off);
-        pl->hp_ct.push_back(ct);
+    if (h.chunk.back() != pl->nchunks) {
+        h.chunk.push_back(pl->nchunks);
+        h.msg.push_back(off);
+        h.ct.push_back(ct);
     }
-    const size_t ns = pl->hp_chunk.size() - 1;
-    pl->hp_n = 0;
+    const size_t ns = h.chunk.size() - 1;
     for (size_t s = 0; s < ns; ++s) {
         pmk_plan *sub = nullptr;
-        const int rc = pmk_plan_create(ctx, pl->key_map.data() + pl->hp_chunk[s], pl->hp_chunk[s + 1] - pl->hp_chunk[s],
-                                       pl->hp_msg[s + 1] - pl->hp_msg[s], &sub, nullptr);
+        const int rc = pmk_plan_create(ctx, pl->key_map.data() + h.chunk[s], h.chunk[s + 1] - h.chunk[s],
+                                       h.msg[s + 1] - h.msg[s], &sub, nullptr);
         if (rc != PMK_OK) return rc;
-        pl->hp_sub.push_back(sub);
+        h.sub.push_back(sub);
         for (int k = 0; k < 2; ++k) {
             hipEvent_t ev = nullptr;
             const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
             if (e != hipSuccess) return hip_err(ctx, e, "host pipeline events");
-            pl->hp_ev.push_back(ev);
+            h.ev.push_back(ev);
         }
     }
-    pl->hp_n = n;
+    h.n = key;
     return PMK_OK;
 }
 
@@ -1122,30 +1170,32 @@ int host_run(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, uint32_
     if (pl->msg_len == 0) return PMK_OK;
     if (!in || !out) return set_err(ctx, PMK_EINVAL, "NULL buffer");
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, PMK_EDEVICE, "hipSetDevice failed");
-    // default: one slice for decryption (its copies are a tiny share of its
-    // time), up to four for encryption, each large enough to fill the chip
-    uint32_t n = slices ? slices : (decrypt ? 1u : (uint32_t)std::min<uint64_t>(4, std::max<uint64_t>(1, pl->nchunks / 65536)));
+    // default: decryption cut at whole rounds of CRT work (round_cuts; one
+    // slice when the key map has no such cuts), encryption in up to four
+    // slices of equal bytes, each large enough to fill the chip
+    uint32_t n = slices ? slices : (decrypt ? 0u : (uint32_t)std::min<uint64_t>(4, std::max<uint64_t>(1, pl->nchunks / 65536)));
     n = (uint32_t)std::min<uint64_t>(n, pl->nchunks);
-    int rc = host_prepare(pl, n);
+    int rc = host_prepare(pl, decrypt, n);
     if (rc != PMK_OK) return rc;
+    pmk_plan::HostSlices &h = pl->hp[decrypt ? 1 : 0];
     const bool blocks = decrypt && pl->dec_mode == 2;
-    const std::vector<uint64_t> &in_off = decrypt ? pl->hp_ct : pl->hp_msg;
-    const std::vector<uint64_t> &out_off = (decrypt && !blocks) ? pl->hp_msg : pl->hp_ct;
+    const std::vector<uint64_t> &in_off = decrypt ? h.ct : h.msg;
+    const std::vector<uint64_t> &out_off = (decrypt && !blocks) ? h.msg : h.ct;
     hipStream_t cin = pl->hp_stream[0], comp = pl->hp_stream[1], cout = pl->hp_stream[2];
     hipError_t e = hipSuccess;
-    for (size_t s = 0; s < pl->hp_sub.size() && rc == PMK_OK && e == hipSuccess; ++s) {
-        pmk_plan *sub = pl->hp_sub[s];
+    for (size_t s = 0; s < h.sub.size() && rc == PMK_OK && e == hipSuccess; ++s) {
+        pmk_plan *sub = h.sub[s];
         sub->dec_mode = pl->dec_mode;
         const uint64_t ib = in_off[s], il = in_off[s + 1] - ib, ob = out_off[s], ol = out_off[s + 1] - ob;
         e = hipMemcpyAsync(pl->hp_in + ib, in + ib, il, hipMemcpyHostToDevice, cin);
-        if (e == hipSuccess) e = hipEventRecord(pl->hp_ev[2 * s], cin);
-        if (e == hipSuccess) e = hipStreamWaitEvent(comp, pl->hp_ev[2 * s], 0);
+        if (e == hipSuccess) e = hipEventRecord(h.ev[2 * s], cin);
+        if (e == hipSuccess) e = hipStreamWaitEvent(comp, h.ev[2 * s], 0);
         if (e != hipSuccess) break;
         rc = decrypt ? pmk_decrypt_plan(sub, pl->hp_in + ib, pl->hp_out + ob, comp)
                      : pmk_encrypt_plan(sub, pl->hp_in + ib, pl->hp_out + ob, comp);
         if (rc != PMK_OK) break;
-        e = hipEventRecord(pl->hp_ev[2 * s + 1], comp);
-        if (e == hipSuccess) e = hipStreamWaitEvent(cout, pl->hp_ev[2 * s + 1], 0);
+        e = hipEventRecord(h.ev[2 * s + 1], comp);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cout, h.ev[2 * s + 1], 0);
         if (e == hipSuccess) e = hipMemcpyAsync(out + ob, pl->hp_out + ob, ol, hipMemcpyDeviceToHost, cout);
     }
     const hipError_t e1 = hipStreamSynchronize(cin), e2 = hipStreamSynchronize(comp), e3 = hipStreamSynchronize(cout);
@@ -1153,7 +1203,7 @@ int host_run(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, uint32_
     if (e == hipSuccess) e = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
     if (e != hipSuccess) return hip_err(ctx, e, "host pipeline");
     // device-detected errors of every slice (PMK_EBLIND cannot occur here)
-    for (pmk_plan *sub : pl->hp_sub) {
+    for (pmk_plan *sub : h.sub) {
         const int c = pmk_plan_check(sub, comp);
         if (c != PMK_OK) rc = rc == PMK_OK ? c : rc;
     }

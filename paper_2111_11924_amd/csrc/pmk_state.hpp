@@ -99,12 +99,17 @@ struct pmk_plan {
     // host-buffer forms (pmk_encrypt_host / pmk_decrypt_host), made on first use
     std::vector<uint32_t> key_map;      // the chunk-to-key map the plan was made from
     uint8_t *hp_in = nullptr, *hp_out = nullptr;  // device copies of the whole input / output
-    std::vector<pmk_plan *> hp_sub;     // one plan per slice of the chunk range
-    uint32_t hp_n = 0;                  // slice count hp_sub was made for
-    std::vector<uint64_t> hp_chunk, hp_msg, hp_ct;  // slice boundaries: chunk, message and ciphertext offsets
+    // the slices of one direction (kept apart, so alternating encryption and
+    // decryption does not re-plan)
+    struct HostSlices {
+        std::vector<pmk_plan *> sub;         // one plan per slice of the chunk range
+        uint32_t n = 0;                      // slicing they were made for (0: none yet)
+        std::vector<uint64_t> chunk, msg, ct;  // slice boundaries: chunk, message and ciphertext offsets
+        std::vector<hipEvent_t> ev;          // per slice: input copied, slice computed
+    };
+    HostSlices hp[2];                   // [0] encryption, [1] decryption
     static constexpr int kPipe = 3;     // streams: host-to-device copies, compute, device-to-host copies
     hipStream_t hp_stream[kPipe] = {};
-    std::vector<hipEvent_t> hp_ev;      // per slice: input copied, slice computed
 };
 
 namespace pmk {

@@ -76,6 +76,44 @@ def test_host_forms_match_oracle(torch, ctx, slices):
         ct += kb
 
 
+def test_host_decryption_cut_at_whole_rounds(torch, ctx):
+    """Default slicing of a decryption whose key map allows cuts at whole rounds
+    of CRT work (one size class, round-robin over 16 keys: every slice gives
+    each key full tiles): 1 and 2 rounds then the rest -- the same bytes as
+    one slice and as the device form, a block of every slice against the oracle,
+    and an out-of-range block in the last slice flagged."""
+    keys = [k for k in inputs.make_keys([2048] * 16, 962)]
+    nch = 3 * 98_304 + 5_000  # slices of 1 and 2 rounds of the 3,072-wave chip, then the rest
+    kb = 256
+    msg = inputs.make_message((nch - 1) * (kb - 4) + 17, 962)
+    km = inputs.round_robin_map(len(msg), [2048] * 16)
+    assert len(km) == nch
+    T = oracle.KeyTable(keys)
+    print(f"[gpu] host decryption at whole rounds, {nch} chunks", flush=True)
+    ctx.load_keys(keys)
+    plan = ctx.plan(km, len(msg))
+    try:
+        d_ct = plan.encrypt(torch.from_numpy(msg).to("cuda"))
+        ct = d_ct[: plan.ct_len].cpu().numpy()
+        pt0 = np.zeros(len(msg), np.uint8)
+        pt1 = np.zeros(len(msg), np.uint8)
+        assert plan.decrypt_host(ct, pt0, 0) == binding.PMK_OK
+        assert plan.decrypt_host(ct, pt1, 1) == binding.PMK_OK
+        assert (pt0 == msg).all() and (pt1 == msg).all()
+        bad = ct.copy()
+        bad[-kb:] = np.frombuffer(keys[int(km[-1])].n.to_bytes(kb, "big"), np.uint8)
+        pt2 = np.zeros(len(msg), np.uint8)
+        assert plan.decrypt_host(bad, pt2, 0) == binding.PMK_ERANGE
+        assert (pt2[:-17] == msg[:-17]).all() and (pt2[-17:] == 0).all()
+    finally:
+        plan.close()
+    # a chunk on each side of the slice boundaries (1 and 3 rounds) against the oracle's encryption
+    for i in (0, 98_303, 98_304, 294_911, 294_912, nch - 1):
+        k = int(km[i])
+        m = int.from_bytes(bytes(msg[i * (kb - 4):min((i + 1) * (kb - 4), len(msg))]), "big")
+        assert int.from_bytes(bytes(ct[i * kb:(i + 1) * kb]), "big") == oracle.rsa_int(T, k, "enc", m)
+
+
 def test_host_forms_empty_and_errors(torch, ctx):
     keys = inputs.make_keys([512], 961)
     ctx.load_keys(keys)
