@@ -44,6 +44,8 @@ int launch_L(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, hipSt
     if constexpr (lanes_half(CB) == 1) {
         if (L == 2) return launch_class<CB, 2>(r, jt_begin, jt_end, s);
         if (L == 4) return launch_class<CB, 4>(r, jt_begin, jt_end, s);
+        if constexpr (eight_lanes(CB))
+            if (L == 8) return launch_class<CB, 8>(r, jt_begin, jt_end, s);
     } else {
         if (L == 2 * lanes_half(CB)) return launch_class<CB, 2 * lanes_half(CB)>(r, jt_begin, jt_end, s);
     }
@@ -53,23 +55,25 @@ int launch_L(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_end, hipSt
 }  // namespace
 
 uint32_t joint_lanes_resident(int cls, int L) {
-    switch (cls * 8 + L) {
-        case 0 * 8 + 2: return resident_of<128, 2>();
-        case 0 * 8 + 4: return resident_of<128, 4>();
-        case 1 * 8 + 2: return resident_of<256, 2>();
-        case 1 * 8 + 4: return resident_of<256, 4>();
-        case 2 * 8 + 2: return resident_of<512, 2>();
-        case 2 * 8 + 4: return resident_of<512, 4>();
-        case 3 * 8 + 2: return resident_of<1024, 2>();
-        case 3 * 8 + 4: return resident_of<1024, 4>();
-        case 4 * 8 + 2: return resident_of<2048, 2>();
-        case 4 * 8 + 4: return resident_of<2048, 4>();
-        case 5 * 8 + 2: return resident_of<3072, 2>();
-        case 5 * 8 + 4: return resident_of<3072, 4>();
-        case 6 * 8 + 2: return resident_of<4096, 2>();
-        case 6 * 8 + 4: return resident_of<4096, 4>();
-        case 7 * 8 + 2 * lanes_half(6144): return resident_of<6144, 2 * lanes_half(6144)>();
-        case 8 * 8 + 2 * lanes_half(8192): return resident_of<8192, 2 * lanes_half(8192)>();
+    switch (cls * 16 + L) {
+        case 0 * 16 + 2: return resident_of<128, 2>();
+        case 0 * 16 + 4: return resident_of<128, 4>();
+        case 1 * 16 + 2: return resident_of<256, 2>();
+        case 1 * 16 + 4: return resident_of<256, 4>();
+        case 2 * 16 + 2: return resident_of<512, 2>();
+        case 2 * 16 + 4: return resident_of<512, 4>();
+        case 3 * 16 + 2: return resident_of<1024, 2>();
+        case 3 * 16 + 4: return resident_of<1024, 4>();
+        case 4 * 16 + 2: return resident_of<2048, 2>();
+        case 4 * 16 + 4: return resident_of<2048, 4>();
+        case 4 * 16 + 8: return resident_of<2048, 8>();
+        case 5 * 16 + 2: return resident_of<3072, 2>();
+        case 5 * 16 + 4: return resident_of<3072, 4>();
+        case 5 * 16 + 8: return resident_of<3072, 8>();
+        case 6 * 16 + 2: return resident_of<4096, 2>();
+        case 6 * 16 + 4: return resident_of<4096, 4>();
+        case 7 * 16 + 2 * lanes_half(6144): return resident_of<6144, 2 * lanes_half(6144)>();
+        case 8 * 16 + 2 * lanes_half(8192): return resident_of<8192, 2 * lanes_half(8192)>();
         default: return 0;
     }
 }

@@ -712,7 +712,9 @@ int pmk_set_lanes(pmk_ctx *ctx, uint32_t bits, int fill_lanes, int tail_lanes) {
     if (!lanes_valid(kClassBits[c], fill_lanes, tail_lanes)) {
         const int fixed = lanes_half(kClassBits[c]);
         if (fixed == 1)
-            return set_err(ctx, PMK_EUNSUPPORTED, "the %d-bit class takes 1, 2 or 4 lanes per number", kClassBits[c]);
+            return set_err(ctx, PMK_EUNSUPPORTED,
+                           "the %d-bit class takes 1, 2 or 4 lanes per number (fill 8 at 2048 and 3072 bits)",
+                           kClassBits[c]);
         return set_err(ctx, PMK_EUNSUPPORTED,
                        "the %d-bit class runs its CRT halves in groups of %d lanes (small launches %d or %d)",
                        kClassBits[c], fixed, fixed, 2 * fixed);
@@ -926,7 +928,8 @@ int pmk_autotune(pmk_ctx *ctx, const char *cache_path, int flags) {
             for (int which = 0; which < 2 && rc == PMK_OK; ++which) {
                 float lbest = 1e30f;
                 int lpick = 1;
-                for (int L : {1, 2, 4}) {
+                for (int L : {1, 2, 4, 8}) {
+                    if (L == 8 && (which == 1 || !eight_lanes(cb))) continue;  // fill only, where supported
                     (void)pmk_set_lanes(ctx, (uint32_t)cb, which == 0 ? L : best_fill, which == 0 ? best_tail : L);
                     float ms = 0.f;
                     rc = tune_batch(ctx, k0, sizes[which], st, 3, &ms);

@@ -163,16 +163,22 @@ constexpr int kMaxWin = 6;
 // fills at most half a round, and in a short last round after full ones
 // (measured: 4 lanes cut a 1 MiB 2048-bit decryption by a fifth; a 2-lane
 // last round of the 100 MiB one is about even)
+// One-lane classes whose CRT halves also run in groups of 8 lanes (nla a
+// multiple of 8: 2048- and 3072-bit keys), for small launches.
+PMK_HD constexpr bool eight_lanes(int bits) {
+    return lanes_half(bits) == 1 && bits >= 2048 && make_geom(bits).nla % 8 == 0;
+}
 // Lanes-per-number settings a class takes: a one-lane class 1, 2 or 4 for
-// both forms; a lane-group class its own count L0 or 2 L0 for small launches,
-// L0 for the tail form.
+// both forms, and 8 for small launches where eight_lanes; a lane-group class
+// its own count L0, or 2 L0 for small launches, and L0 for the tail form.
 PMK_HD constexpr bool lanes_valid(int bits, int fill, int tail) {
     return lanes_half(bits) == 1
-               ? ((fill == 1 || fill == 2 || fill == 4) && (tail == 1 || tail == 2 || tail == 4))
+               ? ((fill == 1 || fill == 2 || fill == 4 || (fill == 8 && eight_lanes(bits))) &&
+                  (tail == 1 || tail == 2 || tail == 4))
                : ((fill == lanes_half(bits) || fill == 2 * lanes_half(bits)) && tail == lanes_half(bits));
 }
 PMK_HD constexpr int default_fill_lanes(int bits) {
-    return lanes_half(bits) > 1 ? 2 * lanes_half(bits) : (bits >= 1024 ? 4 : 1);
+    return lanes_half(bits) > 1 ? 2 * lanes_half(bits) : (eight_lanes(bits) ? 8 : (bits >= 1024 ? 4 : 1));
 }
 PMK_HD constexpr int default_tail_lanes(int bits) { return lanes_half(bits) > 1 ? lanes_half(bits) : (bits == 2048 ? 2 : 1); }
 

@@ -255,7 +255,7 @@ def test_lane_forms_give_identical_bytes(torch, ctx):
     print(f"[gpu] lane forms, {len(km)} chunks", flush=True)
     ctx.load_keys(keys)
     classes = sorted(set(bits) - {768})
-    default = {b: ctx.lanes(b) for b in classes}
+    default = {b: ctx.lanes(b) for b in classes + [8192]}
     plan = ctx.plan(km, len(msg))
     try:
         cs, cr = plan.encrypt_blinded(dev(torch, msg), dev(torch, rblk))
@@ -281,15 +281,19 @@ def test_lane_forms_give_identical_bytes(torch, ctx):
             ctx.set_lanes(8192, 8, 8)  # the tail form stays at 4
         assert ei.value.status == binding.PMK_EUNSUPPORTED
         with pytest.raises(binding.PmkError) as ei:
-            ctx.set_lanes(2048, 8)  # one-lane classes take 1, 2 or 4
+            ctx.set_lanes(1024, 8, 4)  # 8 only at 2048 and 3072 bits
         assert ei.value.status == binding.PMK_EUNSUPPORTED
+        with pytest.raises(binding.PmkError) as ei:
+            ctx.set_lanes(2048, 8, 8)  # and not for the tail form
+        assert ei.value.status == binding.PMK_EUNSUPPORTED
+        ctx.set_lanes(2048, 8, 2)
         ctx.set_lanes(8192, 4, 4)
         with pytest.raises(binding.PmkError) as ei:
             ctx.set_lanes(2048, 3)
         assert ei.value.status == binding.PMK_EINVAL
     finally:
         ctx.set_grid_limit(0)
-        for b in classes:
+        for b in default:
             ctx.set_lanes(b, *default[b])
         plan.close()
 
