@@ -241,7 +241,7 @@ int pmk_get_window(const pmk_ctx *ctx, uint32_t bits);
  * number.  The 6144/8192-bit classes run 4 lanes per number; their
  * `fill_lanes` may be 8 (a launch whose 8-lane waves each get a SIMD of their
  * own then runs with 8) and their `tail_lanes` must be 4; the one-lane classes
- * take 1, 2 or 4, and `fill_lanes` 8 at 2048 and 3072 bits (PMK_EUNSUPPORTED
+ * take 1, 2 or 4, and `fill_lanes` 8 at 2048, 3072 and 4096 bits (PMK_EUNSUPPORTED
  * for other supported counts, PMK_EINVAL for counts other than 1, 2, 4, 8).  Results never change; graphs are
  * recaptured; PMK_EBUSY while a server runs.  pmk_get_lanes fills the current
  * values.
@@ -270,7 +270,7 @@ int pmk_set_grid_limit(pmk_ctx *ctx, uint32_t waves);
  * {3,4,5} below), keeping the fastest (pmk_set_window); then, for the classes
  * with one lane per number, a launch of a quarter of the compute units' worth
  * of job tiles and one of one and a third rounds at 1, 2 and 4 lanes per
- * number (fill also 8 at 2048 and 3072 bits), keeping the fastest fill and
+ * number (fill also 8 at 2048-4096 bits), keeping the fastest fill and
  * tail forms, and for the 6144/8192-bit classes the first of these at 4 and 8
  * lanes (pmk_set_lanes); a form with more lanes is kept only if it wins by
  * 1 %.  cache_path (may be NULL): a

@@ -668,7 +668,7 @@ class Context:
     def set_lanes(self, bits: int, fill_lanes: int, tail_lanes: Optional[int] = None) -> None:
         """Lanes per number of the CRT halves of a launch under one round and of
         the partial round after full ones (default: the same): 1, 2 or 4 for the
-        one-lane classes (fill also 8 at 2048 and 3072 bits); 4, or 8 for small
+        one-lane classes (fill also 8 at 2048-4096 bits); 4, or 8 for small
         launches, for 6144/8192 bits."""
         pmk_set_lanes(self.handle, bits, fill_lanes, fill_lanes if tail_lanes is None else tail_lanes)
 

@@ -922,7 +922,8 @@ constexpr int lds_words_enc() {
 // group (of nla limbs, or of the S input words while they are staged)
 template <int CB, int L>
 constexpr int lds_words_lanes() {
-    return (make_geom(CB).nla > make_geom(CB).S ? make_geom(CB).nla : make_geom(CB).S) * (64 / L);
+    return (lane_limbs(make_geom(CB), L) > make_geom(CB).S ? lane_limbs(make_geom(CB), L) : make_geom(CB).S) *
+           (64 / L);
 }
 template <int CB>
 constexpr int lds_words_dec() {
@@ -1008,7 +1009,7 @@ PMK_DEV void encrypt_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uin
 template <int CB, int L = lanes_half(CB)>
 PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint32_t *lds) {
     constexpr Geom G = make_geom(CB);
-    constexpr int NLT = G.nla, K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
+    constexpr int NLT = lane_limbs(G, L), K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
     static_assert(K * L == NLT, "lane-group limbs must split evenly");
     constexpr bool F = CB == 8192;  // generic pointers into the multiplier column (measured faster here)
     constexpr int NG = 64 / L;  // groups (chunks) per wavefront
@@ -1040,7 +1041,7 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
     limbs_from_words<K, LB, F>(acc, col, NG, S, NLT + pos * K);  // c_hi
     store_entry(tbl, 0, lane, acc);
     limbs_from_words<K, LB, F>(acc, col, NG, S, pos * K);        // c_lo
-    stage_mem<K, F>(col, NG, pos, hr + G.h_rra + pos * K, 1);
+    stage_mem<K, F>(col, NG, pos, hr + lane_rr(G, L) + pos * K, 1);
 
     // phases as in halves_unit: 0 c_lo R, 1 c_hi R^2 and x~ (entry 0), 2 x~^2,
     // 5 odd powers (entry e = x~^(2e+1)), 3 sliding-window steps (squarings,
@@ -1054,7 +1055,7 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
         if (phase == 0) {
             store_entry(tbl, 1, lane, acc);
             load_entry(acc, tbl, 0, lane);
-            stage_mem<K, F>(col, NG, pos, hr + G.h_rrra + pos * K, 1);
+            stage_mem<K, F>(col, NG, pos, hr + lane_rrr(G, L) + pos * K, 1);
             phase = 1;
             continue;
         }
@@ -1097,7 +1098,7 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
             // table complete: the first window starts at the top set bit
             const int top = exp_top_bit(dexp, SH);
             if (top < 0) {
-                load_limbs(acc, fresh_v(hr + G.h_onea + pos * K));
+                load_limbs(acc, fresh_v(hr + lane_one(G, L) + pos * K));
                 st = WinStep::make(0, 0u, false, -1);
             } else {
                 st = win_first(nx, dexp, SH, top, win);
@@ -1140,7 +1141,7 @@ PMK_DEV void halves_lanes_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint
 template <int CB, int L = lanes_half(CB)>
 PMK_DEV void halves_lanes_joint_unit(const ClassRun r, uint32_t u, uint32_t *tbl, uint32_t *lds) {
     constexpr Geom G = make_geom(CB);
-    constexpr int NLT = G.nla, K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
+    constexpr int NLT = lane_limbs(G, L), K = NLT / L, LB = G.lbh, S = G.S, SH = G.SH;
     static_assert(K * L == NLT, "lane-group limbs must split evenly");
     constexpr int NG = 64 / L;  // groups (chunks) per wavefront
     const int win = r.win, TH = 1 << (win - 1);  // T1 = entries [0, TH), T2 = [TH, 2 TH)
@@ -1173,7 +1174,7 @@ PMK_DEV void halves_lanes_joint_unit(const ClassRun r, uint32_t u, uint32_t *tbl
         limbs_from_words<K, LB>(acc, col, NG, S, NLT + pos * K);
         store_entry(tbl, base, lane, acc);
         limbs_from_words<K, LB>(acc, col, NG, S, pos * K);
-        stage_mem<K>(col, NG, pos, hr + G.h_rra + pos * K, 1);
+        stage_mem<K>(col, NG, pos, hr + lane_rr(G, L) + pos * K, 1);
     };
     take_input(r.x32, 0);
     // phases as in halves_joint_unit: 0 lo R, 1 hi R^2 and x~ (entry base),
@@ -1190,7 +1191,7 @@ PMK_DEV void halves_lanes_joint_unit(const ClassRun r, uint32_t u, uint32_t *tbl
         if (phase == 0) {
             store_entry(tbl, base + 1, lane, acc);
             load_entry(acc, tbl, base, lane);
-            stage_mem<K>(col, NG, pos, hr + G.h_rrra + pos * K, 1);
+            stage_mem<K>(col, NG, pos, hr + lane_rrr(G, L) + pos * K, 1);
             phase = 1;
             continue;
         }
@@ -1264,7 +1265,7 @@ PMK_DEV void halves_lanes_joint_unit(const ClassRun r, uint32_t u, uint32_t *tbl
             }
             // tables complete: the chain starts from the Montgomery one above the
             // higher of the two top bits
-            load_limbs(acc, fresh_v(hr + G.h_onea + pos * K));
+            load_limbs(acc, fresh_v(hr + lane_one(G, L) + pos * K));
             const int t1 = exp_top_bit(d1, SH), t2 = exp_top_bit(d2, SH);
             if (t1 >= 0) s1 = win_first(nx1, d1, SH, t1, win);
             if (t2 >= 0) s2 = win_first(nx2, d2, SH, t2, win);

@@ -265,6 +265,7 @@ void build_record(const pmk_key &k, int cls, uint32_t *rec) {
         hr[g.h_m0] = (0u - inv32(m[0])) & ((1u << g.lbh) - 1u);
         mont_consts(m, g.lbh, g.nlh, hr + g.h_one, hr + g.h_rr, hr + g.h_rrr);
         if (g.nla != g.nlh) mont_consts(m, g.lbh, g.nla, hr + g.h_onea, hr + g.h_rra, hr + g.h_rrra);
+        if (g.nla8 != g.nla) mont_consts(m, g.lbh, g.nla8, hr + g.h_onea8, hr + g.h_rra8, hr + g.h_rrra8);
         const Words d = from(exps[h], SH, g.SH);
         for (int i = 0; i < g.SH; ++i) hr[g.h_d + i] = d[i];
         // d2 = m - 1 - d: (c^d)^-1 = c^d2 mod m for c not divisible by m (Fermat)

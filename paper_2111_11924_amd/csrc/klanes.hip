@@ -28,7 +28,7 @@ uint32_t resident_of() {
 template <int CB, int L>
 int launch_class(const ClassRun &r, uint32_t jt_begin, uint32_t jt_end, hipStream_t s) {
     constexpr Geom G = make_geom(CB);
-    constexpr uint64_t K = G.nla / L;
+    constexpr uint64_t K = lane_limbs(G, L) / L;
     const uint64_t slot = (uint64_t)(1u << (r.win - 1)) * K * kTile;  // odd powers, each lane's K limbs
     const uint32_t units = (jt_end - jt_begin) * L;
     // at most the table's room (L / lanes_half lane-group slots per slot of
@@ -84,6 +84,7 @@ uint32_t lanes_resident(int cls, int L) {
         case 5 * 16 + 8: return resident_of<3072, 8>();
         case 6 * 16 + 2: return resident_of<4096, 2>();
         case 6 * 16 + 4: return resident_of<4096, 4>();
+        case 6 * 16 + 8: return resident_of<4096, 8>();
         case 7 * 16 + 2 * lanes_half(6144): return resident_of<6144, 2 * lanes_half(6144)>();
         case 8 * 16 + 2 * lanes_half(8192): return resident_of<8192, 2 * lanes_half(8192)>();
         default: return 0;

@@ -713,7 +713,7 @@ int pmk_set_lanes(pmk_ctx *ctx, uint32_t bits, int fill_lanes, int tail_lanes) {
         const int fixed = lanes_half(kClassBits[c]);
         if (fixed == 1)
             return set_err(ctx, PMK_EUNSUPPORTED,
-                           "the %d-bit class takes 1, 2 or 4 lanes per number (fill 8 at 2048 and 3072 bits)",
+                           "the %d-bit class takes 1, 2 or 4 lanes per number (fill 8 at 2048-4096 bits)",
                            kClassBits[c]);
         return set_err(ctx, PMK_EUNSUPPORTED,
                        "the %d-bit class runs its CRT halves in groups of %d lanes (small launches %d or %d)",

@@ -49,9 +49,9 @@ PMK_HD constexpr int window_for(int bits) { return bits <= 256 ? 3 : (bits <= 51
 struct Geom {
     int bits, S, SH;
     int lbf, nlf, lbh, nlh;
-    // CRT halves spread over a lane group (2 or 4 lanes per number): nla limbs
-    // (a multiple of 4) and the constants of R_A = 2^(lbh nla); for the classes
-    // whose halves always run in lane groups these are the nlh-limb ones
+    // CRT halves spread over a lane group (2 or 4 lanes per number): nla
+    // limbs (a multiple of 4) and the constants of R_A = 2^(lbh nla); for the
+    // classes whose halves always run in lane groups these are the nlh-limb ones
     int nla;
     int ew;  // words of the public exponent
     // full-modulus part
@@ -61,6 +61,7 @@ struct Geom {
     // one, rr, rrr of the lane-group form
     int off_half[2];
     int h_m, h_m0, h_rr, h_rrr, h_one, h_d, h_d2, h_onea, h_rra, h_rrra, h_size;
+    int nla8, h_onea8, h_rra8, h_rrra8;  // the same for groups of 8 lanes (nla8 a multiple of 8)
     int off_qinvr;
     int stride;
 };
@@ -79,7 +80,12 @@ PMK_HD constexpr Geom make_geom(int bits) {
     g.lbh = lb_half(bits);
     g.nlh = round_up(nl_for(bits / 2, g.lbh), lanes_half(bits));
     g.ew = 2;
-    const int pf = pad4(g.nlf), ph = pad4(g.nlh);
+    // lane-group limb counts: nla (a multiple of 4: groups of 2 and 4 lanes)
+    // and nla8 (a multiple of 8: groups of 8); the half fields hold the larger,
+    // zero-padded, since a lane group reads its K limbs of every field at pos K
+    const int nla = lanes_half(bits) > 1 ? g.nlh : round_up(g.nlh, 4);
+    const int nla8 = lanes_half(bits) > 1 ? g.nlh : round_up(g.nlh, 8);
+    const int pf = pad4(g.nlf), ph = pad4(nla8);
     int o = 0;
     g.off_nf = o; o += pf;
     g.off_rrf = o; o += pf;
@@ -98,18 +104,28 @@ PMK_HD constexpr Geom make_geom(int bits) {
     g.h_m0 = 4 * ph;
     g.h_d = 4 * ph + 4;
     g.h_d2 = g.h_d + pad4(g.SH);
+    g.nla = nla;
+    g.nla8 = nla8;
     if (lanes_half(bits) > 1) {  // lane groups already: the same constants
-        g.nla = g.nlh;
-        g.h_onea = g.h_one;
-        g.h_rra = g.h_rr;
-        g.h_rrra = g.h_rrr;
+        g.h_onea = g.h_onea8 = g.h_one;
+        g.h_rra = g.h_rra8 = g.h_rr;
+        g.h_rrra = g.h_rrra8 = g.h_rrr;
         g.h_size = pad4(g.h_d2 + g.SH);
     } else {
-        g.nla = round_up(g.nlh, 4);
         g.h_onea = pad4(g.h_d2 + g.SH);
-        g.h_rra = g.h_onea + g.nla;
-        g.h_rrra = g.h_rra + g.nla;
-        g.h_size = g.h_rrra + g.nla;
+        g.h_rra = g.h_onea + nla;
+        g.h_rrra = g.h_rra + nla;
+        g.h_size = g.h_rrra + nla;
+        if (nla8 == nla) {
+            g.h_onea8 = g.h_onea;
+            g.h_rra8 = g.h_rra;
+            g.h_rrra8 = g.h_rrra;
+        } else {  // 4096 bits: 74 limbs, 76 for 2 and 4 lanes, 80 for 8
+            g.h_onea8 = g.h_size;
+            g.h_rra8 = g.h_onea8 + nla8;
+            g.h_rrra8 = g.h_rra8 + nla8;
+            g.h_size = g.h_rrra8 + nla8;
+        }
     }
     g.off_half[0] = o; o += g.h_size;
     g.off_half[1] = o; o += g.h_size;
@@ -163,11 +179,16 @@ constexpr int kMaxWin = 6;
 // fills at most half a round, and in a short last round after full ones
 // (measured: 4 lanes cut a 1 MiB 2048-bit decryption by a fifth; a 2-lane
 // last round of the 100 MiB one is about even)
-// One-lane classes whose CRT halves also run in groups of 8 lanes (nla a
-// multiple of 8: 2048- and 3072-bit keys), for small launches.
-PMK_HD constexpr bool eight_lanes(int bits) {
-    return lanes_half(bits) == 1 && bits >= 2048 && make_geom(bits).nla % 8 == 0;
-}
+// One-lane classes whose CRT halves also run in groups of 8 lanes (2048- to
+// 4096-bit keys), for small launches.
+PMK_HD constexpr bool eight_lanes(int bits) { return lanes_half(bits) == 1 && bits >= 2048; }
+
+// Limb count and constants (offsets in a half record) of the lane-group form
+// with L lanes per number: nla limbs for 2 and 4 lanes, nla8 for 8.
+PMK_HD constexpr int lane_limbs(const Geom &g, int L) { return L == 8 ? g.nla8 : g.nla; }
+PMK_HD constexpr int lane_one(const Geom &g, int L) { return L == 8 ? g.h_onea8 : g.h_onea; }
+PMK_HD constexpr int lane_rr(const Geom &g, int L) { return L == 8 ? g.h_rra8 : g.h_rra; }
+PMK_HD constexpr int lane_rrr(const Geom &g, int L) { return L == 8 ? g.h_rrra8 : g.h_rrra; }
 // Lanes-per-number settings a class takes: a one-lane class 1, 2 or 4 for
 // both forms, and 8 for small launches where eight_lanes; a lane-group class
 // its own count L0, or 2 L0 for small launches, and L0 for the tail form.

@@ -367,8 +367,8 @@ def test_autotune_cache_and_results(torch, ctx, tmp_path):
             assert w in ((4, 5, 6) if b >= 1024 else (3, 4, 5))
             if b >= 6144:  # lane-group class: its own 4 lanes, or 8 for small launches
                 assert fill in (4, 8) and tail == 4
-            else:
-                assert fill in (1, 2, 4) and tail in (1, 2, 4)
+            else:  # 8 lanes for small launches at 2048-4096 bits
+                assert fill in ((1, 2, 4, 8) if b >= 2048 else (1, 2, 4)) and tail in (1, 2, 4)
         # the cache is applied without measuring
         for b in bits:
             ctx.set_window(b, 2)
@@ -484,11 +484,11 @@ def oracle_many(fn, jobs):
 
 
 @pytest.mark.parametrize("bits,lanes", [(b, l) for b in (1024, 2048, 3072, 4096) for l in (1, 2, 4)]
-                         + [(2048, 8), (3072, 8), (6144, 4), (6144, 8), (8192, 4), (8192, 8)])
+                         + [(2048, 8), (3072, 8), (4096, 8), (6144, 4), (6144, 8), (8192, 4), (8192, 8)])
 def test_unusual_crt_exponents(torch, ctx, bits, lanes):
     """(lanes: lanes per number of the CRT halves where the launch leaves the
-    chip mostly idle -- here every launch, 6 keys x 70 chunks; 8 at 2048 and
-    3072 bits; the 6144/8192-bit classes take 4, or 8 for such launches.)"""
+    chip mostly idle -- here every launch, 6 keys x 70 chunks; 8 at 2048-4096
+    bits; the 6144/8192-bit classes take 4, or 8 for such launches.)"""
     base = base_key(bits)
     h = bits // 2
     keys = []
@@ -528,7 +528,7 @@ def test_unusual_crt_exponents(torch, ctx, bits, lanes):
 
 
 @pytest.mark.parametrize("bits,lanes", [(b, l) for b in (1024, 2048, 3072, 4096) for l in (1, 2, 4)]
-                         + [(2048, 8), (3072, 8), (6144, 4), (6144, 8), (8192, 4), (8192, 8)])
+                         + [(2048, 8), (3072, 8), (4096, 8), (6144, 4), (6144, 8), (8192, 4), (8192, 8)])
 def test_blinded_decryption_with_unusual_exponents(torch, ctx, bits, lanes):
     """Blinded decryption (c* and c_R in one squaring chain per prime) with
     private exponents of unusual shape: d below both primes, so dp = dq = d

@@ -281,7 +281,7 @@ def test_lane_forms_give_identical_bytes(torch, ctx):
             ctx.set_lanes(8192, 8, 8)  # the tail form stays at 4
         assert ei.value.status == binding.PMK_EUNSUPPORTED
         with pytest.raises(binding.PmkError) as ei:
-            ctx.set_lanes(1024, 8, 4)  # 8 only at 2048 and 3072 bits
+            ctx.set_lanes(1024, 8, 4)  # 8 only at 2048-4096 bits
         assert ei.value.status == binding.PMK_EUNSUPPORTED
         with pytest.raises(binding.PmkError) as ei:
             ctx.set_lanes(2048, 8, 8)  # and not for the tail form
