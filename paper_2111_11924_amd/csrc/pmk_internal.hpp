@@ -84,7 +84,7 @@ PMK_HD constexpr Geom make_geom(int bits) {
     // and nla8 (a multiple of 8: groups of 8); the half fields hold the larger,
     // zero-padded, since a lane group reads its K limbs of every field at pos K
     const int nla = lanes_half(bits) > 1 ? g.nlh : round_up(g.nlh, 4);
-    const int nla8 = lanes_half(bits) > 1 ? g.nlh : round_up(g.nlh, 8);
+    const int nla8 = lanes_half(bits) > 1 ? g.nlh : (bits >= 2048 ? round_up(g.nlh, 8) : nla);
     const int pf = pad4(g.nlf), ph = pad4(nla8);
     int o = 0;
     g.off_nf = o; o += pf;
@@ -180,7 +180,8 @@ constexpr int kMaxWin = 6;
 // (measured: 4 lanes cut a 1 MiB 2048-bit decryption by a fifth; a 2-lane
 // last round of the 100 MiB one is about even)
 // One-lane classes whose CRT halves also run in groups of 8 lanes (2048- to
-// 4096-bit keys), for small launches.
+// 4096-bit keys, the classes whose record holds the nla8-limb constants), for
+// small launches.
 PMK_HD constexpr bool eight_lanes(int bits) { return lanes_half(bits) == 1 && bits >= 2048; }
 
 // Limb count and constants (offsets in a half record) of the lane-group form
