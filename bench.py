@@ -70,8 +70,8 @@ PEAK_MAD_PER_S = 256 * 64 * 2.4e9
 # copy (bench.py --copy-probe 256: FETCH_SIZE reads half the bytes moved,
 # WRITE_SIZE all of them).  Valid only for the kernel sources it was measured
 # on (hash below); reported as null otherwise.
-HALVES_TRAFFIC = {"sources_sha256": "21c6b76fb7cf88a35706b57489213df2db991b94b9a4517675d6184095d46700",
-                  "fetch_bytes": 20_048_678_282, "write_bytes": 2_572_764_160}
+HALVES_TRAFFIC = {"sources_sha256": "546de287bb2996bd6b50ceaaa290670cf8a14ff2e7659d4844abbd3b668b95ba",
+                  "fetch_bytes": 20_049_222_988, "write_bytes": 2_572_749_824}
 KERNEL_SOURCES = ["paper_2111_11924_amd/csrc/kernels_impl.hpp", "paper_2111_11924_amd/csrc/mont.hpp",
                   "paper_2111_11924_amd/csrc/mont_lanes.hpp", "paper_2111_11924_amd/csrc/pmk_internal.hpp",
                   "paper_2111_11924_amd/csrc/kernels_class.inc", "paper_2111_11924_amd/csrc/k2048.hip",
