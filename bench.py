@@ -483,8 +483,9 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(chunks are independent; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (chunks are independent, so "
+              "each GPU would take its own slice of the chunk range with a copy of the key table)",
+              file=sys.stderr)
         return 2
 
     import numpy as np
