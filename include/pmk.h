@@ -234,8 +234,9 @@ int pmk_get_window(const pmk_ctx *ctx, uint32_t bits);
  *     number, or the largest smaller power of two for which every lane-group
  *     wave still has a SIMD of its own (units of 64 numbers modulo one prime
  *     times L at most 4 per compute unit), else one lane, and
- *   - the partial round after full ones with `tail_lanes` lanes per number,
- *     or the largest smaller power of two whose waves fit one round,
+ *   - the partial round after full ones as a launch of its own (its waves
+ *     then spread over the SIMDs) with `tail_lanes` lanes per number, or the
+ *     largest smaller power of two whose waves fit one round,
  * each 1, 2 or 4: L lanes per number give L times the waves, each with a
  * shorter chain per Montgomery product, for about twice the instructions per
  * number.  The 6144/8192-bit classes run 4 lanes per number; their

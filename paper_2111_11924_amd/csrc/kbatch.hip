@@ -17,6 +17,7 @@ PMK_DEV uint32_t next_unit(uint32_t *counter) {
 }
 
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void batch_wide_kernel(BatchArgs a) {
+    code_align<code_id(kCodeBatchWide, 0, 0)>();
     __shared__ uint32_t lds[kWideLdsEnc];
     uint32_t *tbl = a.table + (size_t)blockIdx.x * a.slot_words;
     const uint32_t total = a.start[kWideClasses];

@@ -1,7 +1,10 @@
 // Blinded decryption in one pass per prime (halves_joint_kernel) for every
 // size class; the one-lane classes hand the part of a launch that leaves SIMDs
 // idle to the lane-group form (kjlanes.hip).  A translation unit of its own,
-// so the per-class objects stay as they are.
+// so the per-class objects stay as they are.  Its Montgomery products align
+// each column (mont.hpp): measured on these kernels' code, that puts their
+// multiply-adds at addresses 0 modulo 8.
+#define PMK_COLUMN_ALIGN 1
 #include "kernels_impl.hpp"
 
 namespace pmk {
@@ -43,14 +46,20 @@ int launch_joint_class(const ClassRun &r, hipStream_t s) {
             main_end = 0;
         }
     }
+    const uint64_t slot = 2 * table_words_per_slot(r.cls, 1, r.win);  // two odd-power tables
     if (main_end) {
-        const uint64_t slot = 2 * table_words_per_slot(r.cls, 1, r.win);  // two odd-power tables
         hipLaunchKernelGGL(halves_joint_kernel<CB>, dim3(persistent_grid(main_end, grid, 0)), dim3(64), 0, s, r, slot,
                            0u, main_end);
         const int e = (int)hipGetLastError();
         if (e) return e;
     }
-    return main_end < units ? launch_joint_lanes(r, L, main_end / lanes_half(CB), 2 * r.ntiles, s) : 0;
+    if (main_end == units) return 0;
+    if (L == 1) {  // the partial round, one lane per number, in a launch of its own
+        hipLaunchKernelGGL(halves_joint_kernel<CB>, dim3(persistent_grid(units - main_end, grid, 0)), dim3(64), 0, s,
+                           r, slot, main_end, units);
+        return (int)hipGetLastError();
+    }
+    return launch_joint_lanes(r, L, main_end / lanes_half(CB), 2 * r.ntiles, s);
 }
 
 }  // namespace

@@ -17,6 +17,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void mp
     const uint32_t *__restrict__ keys, const uint32_t *__restrict__ tile_key, const ChunkDesc *__restrict__ desc,
     uint32_t ntiles, const uint32_t *__restrict__ x32, uint32_t *__restrict__ parts, uint32_t *table,
     uint64_t slot_words, int win, uint32_t *err) {
+    code_align<code_id(kCodeMpPart, K, 0)>();
     constexpr MpGeom G = make_mp_geom(K);
     constexpr int NL = kMpNL, LB = kMpLB, S = G.S, P = G.parts, SP = kMpSP, PL = pad4(kMpNL);
     constexpr uint32_t MASK = Radix<LB>::MASK;
@@ -137,6 +138,7 @@ template <int K>
 __global__ __launch_bounds__(64) void mp_garner_kernel(const uint32_t *__restrict__ keys,
                                                        const ChunkDesc *__restrict__ desc, uint32_t ntiles,
                                                        uint32_t *__restrict__ parts, uint32_t *__restrict__ y32) {
+    code_align<code_id(kCodeMpGarner, K, 0)>();
     constexpr MpGeom G = make_mp_geom(K);
     constexpr int NL = kMpNL, LB = kMpLB, S = G.S, P = G.parts, PL = pad4(kMpNL);
     constexpr uint32_t MASK = Radix<LB>::MASK;

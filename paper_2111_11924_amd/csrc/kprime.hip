@@ -96,6 +96,7 @@ template <int CB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void miller_rabin_kernel(
     const uint32_t *__restrict__ cand, uint32_t count, const uint32_t *__restrict__ bases, int rounds, int win,
     uint32_t *table, uint64_t slot_words, uint32_t *__restrict__ result) {
+    code_align<code_id(kCodeMillerRabin, CB, 0)>();
     constexpr Geom G = make_geom(CB);
     constexpr int NL = G.nlh, LB = G.lbh, SH = G.SH;
     constexpr uint32_t MASK = Radix<LB>::MASK;

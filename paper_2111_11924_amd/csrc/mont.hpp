@@ -29,6 +29,18 @@ constexpr int limbs_for(int bits, int lb) { return (bits + 2 + lb - 1) / lb; }
 // Number of 4-limb groups of an NL-limb number (multiplier staging unit).
 constexpr int groups_of(int nl) { return (nl + 3) / 4; }
 
+// Column alignment (a source that defines PMK_COLUMN_ALIGN to 1 before the
+// includes): each column of mont_mul / mont_sqr starts at an 8-byte boundary
+// (the assembler pads with s_nop), which keeps more of the 8-byte
+// v_mad_u64_u32 at addresses 0 modulo 8, where they issue faster, in kernels
+// whose code around the products would otherwise leave them at 4 modulo 8.
+#ifndef PMK_COLUMN_ALIGN
+#define PMK_COLUMN_ALIGN 0
+#endif
+__device__ __forceinline__ void column_align() {
+    if constexpr (PMK_COLUMN_ALIGN) asm volatile(".p2align 3");
+}
+
 // Product-scanning Montgomery multiplication (the "finely integrated product
 // scanning" order of Koc, Acar and Kaliski): column k of the double-length
 // result collects every a_i b_j and m_i n_j with i + j = k in one 64-bit
@@ -50,6 +62,7 @@ __device__ __forceinline__ void mont_mul(uint32_t (&r)[NL], const uint32_t (&a)[
     uint32_t m[NL];
     uint64_t carry = 0;
     __builtin_amdgcn_sched_barrier(0);
+    column_align();
 #pragma unroll
     for (int k = 0; k < 2 * NL - 1; ++k) {
         const int lo = k - NL + 1 > 0 ? k - NL + 1 : 0;
@@ -81,6 +94,7 @@ __device__ __forceinline__ void mont_mul(uint32_t (&r)[NL], const uint32_t (&a)[
         // keep the schedule column by column: interleaving columns only adds
         // live accumulators and pushes the register count past 3 waves per SIMD
         __builtin_amdgcn_sched_barrier(0);
+        column_align();
     }
     r[NL - 1] = (uint32_t)carry;
 }
@@ -95,6 +109,7 @@ __device__ __forceinline__ void mont_sqr(uint32_t (&r)[NL], const uint32_t (&a)[
     uint32_t m[NL];
     uint64_t carry = 0;
     __builtin_amdgcn_sched_barrier(0);
+    column_align();
 #pragma unroll
     for (int k = 0; k < 2 * NL - 1; ++k) {
         const int lo = k - NL + 1 > 0 ? k - NL + 1 : 0;
@@ -126,6 +141,7 @@ __device__ __forceinline__ void mont_sqr(uint32_t (&r)[NL], const uint32_t (&a)[
         }
         carry = acc >> LB;
         __builtin_amdgcn_sched_barrier(0);
+        column_align();
     }
     r[NL - 1] = (uint32_t)carry;
 }

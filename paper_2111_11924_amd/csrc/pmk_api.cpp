@@ -573,7 +573,10 @@ int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, v
             // classes side by side fill the chip together: no class's launch is
             // short of work on its own, so every number keeps one lane
             // (measured: lane groups here cost 47 % on the mixed 25 MiB workload)
-            r.fill_lanes = r.tail_lanes = lanes_half(kClassBits[order[i]]);
+            // and a class's last partial round stays in its launch, where its
+            // waves start as soon as waves of that launch finish
+            r.fill_lanes = lanes_half(kClassBits[order[i]]);
+            r.tail_lanes = lanes_half(kClassBits[order[i]]) > 1 ? r.fill_lanes : 0;
         }
         void *s = decrypt ? stream_of(i % lanes) : stream;
         e = timed_launch(pl, decrypt ? PMK_KERNEL_CRT_HALVES : PMK_KERNEL_ENCRYPT, s, [&] {

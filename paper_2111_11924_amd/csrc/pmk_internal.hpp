@@ -167,7 +167,8 @@ struct ClassRun {
     int win;                   // window width of the CRT-halves exponentiation (3..6)
     int fill_lanes;            // lanes per number of the CRT halves of a launch under one round
                                // (one-lane classes 1, 2 or 4; lane-group classes lanes_half or twice it)
-    int tail_lanes;            // one-lane classes: the same for the partial round after full ones
+    int tail_lanes;            // one-lane classes: the same for the partial round after full ones,
+                               // run as a launch of its own; 0: that round stays in the launch
     // blinded PMKRSA (Sec. 3.1, Algorithm 1)
     const uint32_t *fin32;     // encryption: words of a factor v < N the result is multiplied by
                                // (x^e v mod N; tile layout of y32), nullptr = 1; blinded decryption:
@@ -202,7 +203,7 @@ PMK_HD constexpr bool lanes_valid(int bits, int fill, int tail) {
 PMK_HD constexpr int default_fill_lanes(int bits) {
     return lanes_half(bits) > 1 ? 2 * lanes_half(bits) : (eight_lanes(bits) ? 8 : (bits >= 1024 ? 4 : 1));
 }
-PMK_HD constexpr int default_tail_lanes(int bits) { return lanes_half(bits) > 1 ? lanes_half(bits) : (bits == 2048 ? 2 : 1); }
+PMK_HD constexpr int default_tail_lanes(int bits) { return lanes_half(bits) > 1 ? lanes_half(bits) : 1; }
 
 // One persistent launch over the exponentiation work of the 1024- to 4096-bit
 // classes of a plan: units (tiles, or job tiles of CRT halves) are numbered
@@ -253,12 +254,13 @@ uint32_t joint_lanes_resident(int cls, int L);
 // lanes, or of the largest smaller power of two that still gives every
 // lane-group wave a SIMD of its own; the partial round after full ones runs
 // with r.tail_lanes, or the largest smaller power of two whose waves fit one
-// round of the lane-group kernel.  Returns L (1: one lane per number) and sets
-// *lane_units to the job tiles that run in lane groups (the last ones).
+// round of the lane-group kernel (1: one lane per number, still as a launch of
+// its own; r.tail_lanes 0: no launch of its own).  Returns L and sets
+// *lane_units to the job tiles of that last part (0: one launch).
 inline int lanes_for_launch(const ClassRun &r, uint32_t units, uint32_t resident, uint32_t simds,
                             uint32_t (*room_of)(int, int), uint32_t *lane_units) {
     *lane_units = 0;
-    if (resident == 0 || (r.fill_lanes <= 1 && r.tail_lanes <= 1)) return 1;
+    if (resident == 0) return 1;
     const uint32_t rem = units % resident;
     auto fit = [&](int max_l, uint64_t limit) {
         for (int l = max_l; l >= 2; l /= 2) {
@@ -271,11 +273,16 @@ inline int lanes_for_launch(const ClassRun &r, uint32_t units, uint32_t resident
         return 1;
     };
     int L = 1;
-    if (units < resident)
+    if (units < resident) {
         L = fit(r.fill_lanes, simds);
-    else if (rem)
+        if (L > 1) *lane_units = rem;
+    } else if (rem && r.tail_lanes > 0) {
+        // the partial round after full ones runs as a launch of its own: its
+        // waves then spread over the SIMDs, where the full rounds' last waves
+        // would share them
         L = fit(r.tail_lanes, UINT64_MAX);
-    if (L > 1) *lane_units = rem;
+        *lane_units = rem;
+    }
     return L;
 }
 
