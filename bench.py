@@ -63,15 +63,15 @@ def joint_products(bits: int) -> int:
 PEAK_MAD_PER_S = 256 * 64 * 2.4e9
 
 # HBM traffic of the CRT-halves stage on the 100 MiB workload (halves_kernel
-# over four full rounds plus the lane-group tail, halves_lanes_kernel), from two
+# over four full rounds, then the partial round as a launch of its own), from two
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) of
 # `bench.py --no-serve --no-cpu-baseline --no-e2e --no-blinded --steps 2
 # --warmup 1`, each scaled by what the counter reads for a plain 256 MiB device
 # copy (bench.py --copy-probe 256: FETCH_SIZE reads half the bytes moved,
 # WRITE_SIZE all of them).  Valid only for the kernel sources it was measured
 # on (hash below); reported as null otherwise.
-HALVES_TRAFFIC = {"sources_sha256": "546de287bb2996bd6b50ceaaa290670cf8a14ff2e7659d4844abbd3b668b95ba",
-                  "fetch_bytes": 20_049_222_988, "write_bytes": 2_572_749_824}
+HALVES_TRAFFIC = {"sources_sha256": "e501dfdd8dd987b5155865ebe49598ea1ac5426e040d3733544ff597f8520370",
+                  "fetch_bytes": 20_217_526_800, "write_bytes": 2_582_776_832}
 KERNEL_SOURCES = ["paper_2111_11924_amd/csrc/kernels_impl.hpp", "paper_2111_11924_amd/csrc/mont.hpp",
                   "paper_2111_11924_amd/csrc/mont_lanes.hpp", "paper_2111_11924_amd/csrc/pmk_internal.hpp",
                   "paper_2111_11924_amd/csrc/kernels_class.inc", "paper_2111_11924_amd/csrc/k2048.hip",

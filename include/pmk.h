@@ -227,8 +227,8 @@ int pmk_get_window(const pmk_ctx *ctx, uint32_t bits);
  * Tuning: lanes per number of the CRT exponentiations (the parallel loops of
  * Algorithm 1 over the chunks; plain and blinded decryption alike) of the size
  * class holding `bits`-bit moduli,
- * where a launch would leave SIMDs idle (one wave alone on a SIMD issues at
- * about half the rate of several).  A class whose CRT halves run one lane per
+ * where a launch would leave SIMDs idle (L lanes per number shorten each
+ * wave's chain about L times, for more instructions).  A class whose CRT halves run one lane per
  * number (128- to 4096-bit keys) runs
  *   - a launch under one round of resident waves with `fill_lanes` lanes per
  *     number, or the largest smaller power of two for which every lane-group

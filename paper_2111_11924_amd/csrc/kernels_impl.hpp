@@ -36,7 +36,7 @@ namespace pmk {
 // keys: 22.1 / 53.1 ms at 4 modulo 8, 18.0 / 43.7 ms at 0 modulo 8).  Where the
 // multiply-adds of a kernel land depends on all the code before them, so the
 // build reads them out of each compiled kernel and lists, in PMK_CODE_PAD, the
-// kernels (code_id) with most of them at 4 modulo 8; each of those starts with
+// kernels (code_id) with over 60 % of them at 4 modulo 8; each of those starts with
 // one 4-byte s_nop, which moves all its code by 4 bytes.  Kernel kinds, the
 // same numbers as the build's table:
 enum CodeKind : uint32_t {

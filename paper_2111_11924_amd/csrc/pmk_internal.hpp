@@ -246,8 +246,8 @@ int launch_joint_lanes(const ClassRun &r, int L, uint32_t jt_begin, uint32_t jt_
 uint32_t joint_lanes_resident(int cls, int L);
 
 // Lanes per number for the part of a one-lane class's CRT launch that leaves
-// SIMDs idle (one wave alone on a SIMD issues at about half the rate of
-// several).  units: job tiles of the launch; resident: waves of its one-lane
+// SIMDs idle (L lanes per number give L times the waves, each with a chain
+// about L times shorter).  units: job tiles of the launch; resident: waves of its one-lane
 // kernel that fit the chip (already capped by the table slots and grid cap);
 // simds: SIMDs of the device; room(cls, L): resident waves of the lane-group
 // kernel.  A launch under one round runs wholly in lane groups of r.fill_lanes
