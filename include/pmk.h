@@ -201,8 +201,8 @@ int pmk_decrypt_blinded_plan(pmk_plan *plan, const uint8_t *d_ct_star, const uin
  * it.  Encryption of the 3072- and 4096-bit classes is ONE persistent
  * work-queue launch whose waves take units (a quarter tile each) from a
  * device counter, 4096-bit units first; every other exponentiation is its
- * class's persistent kernel, CRT halves dealt over the streams largest work
- * first.  The whole sequence (packing, exponentiation, CRT recombination,
+ * class's persistent kernel; for the CRT halves the two classes with the most
+ * work get streams of their own and the others follow one another on a third.  The whole sequence (packing, exponentiation, CRT recombination,
  * unpacking) is captured once into a HIP graph per (input, output) buffer pair
  * and replayed on `stream`; a new buffer pair or window setting recaptures it.
  * Results are byte-identical to pmk_encrypt_plan / pmk_decrypt_plan.  With

@@ -520,8 +520,9 @@ namespace pmk {
 // classes too small to fill the chip share it:
 //   encryption: the 4096- and 3072-bit classes as one persistent work-queue
 //     launch on a side stream, the one-lane classes on `stream`, largest first;
-//   decryption: each class's CRT-halves kernel, classes ordered by their work
-//     and dealt round-robin over the streams (largest first on each).
+//   decryption: each class's CRT-halves kernel, classes ordered by their work:
+//     the two largest on streams of their own, the others in that order on a
+//     third.
 // Garner recombination and unpacking follow on `stream`.
 int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, void *stream) {
     pmk_ctx *ctx = pl->ctx;
@@ -555,7 +556,11 @@ int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, v
         };
         std::sort(order, order + nl, [&](int x, int y) { return work(x) > work(y); });
     }
-    const int lanes = decrypt ? std::min(nl, 1 + pmk_plan::kSide) : (total && nl ? 2 : 1);
+    // decryption: the two largest classes on streams of their own, the rest one
+    // after another on a third (measured on the mixed 25 MiB workload: 60.7
+    // against 61.8 ms with every class on a stream of its own, 65.0 ms with the
+    // largest class alone beside all others)
+    const int lanes = decrypt ? std::min(nl, 3) : (total && nl ? 2 : 1);
     if (!e && lanes > 1) {
         e = hipEventRecord(pl->fork_event, (hipStream_t)stream);
         for (int i = 0; i < lanes - 1 && !e; ++i) e = hipStreamWaitEvent(pl->side_stream[i], pl->fork_event, 0);
@@ -578,7 +583,7 @@ int batch_sequence(pmk_plan *pl, int decrypt, const uint8_t *in, uint8_t *out, v
             r.fill_lanes = lanes_half(kClassBits[order[i]]);
             r.tail_lanes = lanes_half(kClassBits[order[i]]) > 1 ? r.fill_lanes : 0;
         }
-        void *s = decrypt ? stream_of(i % lanes) : stream;
+        void *s = decrypt ? stream_of(i < lanes ? i : lanes - 1) : stream;
         e = timed_launch(pl, decrypt ? PMK_KERNEL_CRT_HALVES : PMK_KERNEL_ENCRYPT, s, [&] {
             return decrypt ? launch_decrypt_halves(r, s) : launch_encrypt(r, s);
         });
