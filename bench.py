@@ -70,7 +70,7 @@ PEAK_MAD_PER_S = 256 * 64 * 2.4e9
 # copy (bench.py --copy-probe 256: FETCH_SIZE reads half the bytes moved,
 # WRITE_SIZE all of them).  Valid only for the kernel sources it was measured
 # on (hash below); reported as null otherwise.
-HALVES_TRAFFIC = {"sources_sha256": "e501dfdd8dd987b5155865ebe49598ea1ac5426e040d3733544ff597f8520370",
+HALVES_TRAFFIC = {"sources_sha256": "6dc85095754025e0cb24fe72a1850cca3b276b2a4fd01d1f2a91e91903da5cc9",
                   "fetch_bytes": 20_217_526_800, "write_bytes": 2_582_776_832}
 KERNEL_SOURCES = ["paper_2111_11924_amd/csrc/kernels_impl.hpp", "paper_2111_11924_amd/csrc/mont.hpp",
                   "paper_2111_11924_amd/csrc/mont_lanes.hpp", "paper_2111_11924_amd/csrc/pmk_internal.hpp",

@@ -31,9 +31,10 @@ namespace pmk {
 #endif
 
 // ------------------------------------------------------------------ code alignment
-// v_mad_u64_u32 is an 8-byte instruction, and runs of it issue about 20 %
-// slower when they sit at addresses 4 modulo 8 (CRT halves of 3072/4096-bit
-// keys: 22.1 / 53.1 ms at 4 modulo 8, 18.0 / 43.7 ms at 0 modulo 8).  Where the
+// v_mad_u64_u32 is an 8-byte instruction.  In the long straight-line
+// Montgomery products, runs of it at addresses 4 modulo 8 ran about 20 %
+// slower than at 0 modulo 8 (CRT halves of 3072/4096-bit keys: 22.1 / 53.1 ms
+// against 18.0 / 43.7 ms); short loops of it measure the same either way.  Where the
 // multiply-adds of a kernel land depends on all the code before them, so the
 // build reads them out of each compiled kernel and lists, in PMK_CODE_PAD, the
 // kernels (code_id) with over 60 % of them at 4 modulo 8; each of those starts with

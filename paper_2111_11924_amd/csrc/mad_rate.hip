@@ -9,7 +9,9 @@
 // Register-only inline assembly: no memory access besides one store per wave.
 // v_mad_u64_u32 writes a carry-out SGPR pair that nothing here reads: the
 // plain form sends every chain's to VCC, the "own pairs" form gives each chain
-// a pair of its own.
+// a pair of its own.  AL places each iteration's multiply-adds: 0 where the
+// compiler puts them, 1 at addresses 0 modulo 8, 2 at 4 modulo 8 (an
+// alignment directive, plus one 4-byte s_nop for 2, ahead of the chains).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,7 +23,7 @@ namespace {
 
 constexpr int kIters = 4096;
 
-template <int OP, int CH>
+template <int OP, int CH, int AL = 0>
 __global__ __launch_bounds__(64) void probe(unsigned long long *out, uint32_t seed) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t acc[CH];
@@ -40,6 +42,8 @@ __global__ __launch_bounds__(64) void probe(unsigned long long *out, uint32_t se
             t0 = clock64();
             w0 = wall_clock64();
         }
+        if constexpr (AL == 1) asm volatile(".p2align 3");
+        if constexpr (AL == 2) asm volatile(".p2align 3\n\ts_nop 0");
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             if constexpr (OP == 0)  // 32x32 -> 64 multiply with 64-bit accumulate
@@ -72,17 +76,17 @@ struct Result {
     double event_rate;  // lane-ops per second from event timing
 };
 
-template <int OP, int CH>
+template <int OP, int CH, int AL = 0>
 Result run(unsigned long long *d, std::vector<unsigned long long> &h, int waves_per_simd, const hipDeviceProp_t &prop,
            int wall_khz) {
     const int blocks = prop.multiProcessorCount * 4 * waves_per_simd;
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    hipLaunchKernelGGL((probe<OP, CH>), dim3(blocks), dim3(64), 0, 0, d, 1u);  // warm-up
+    hipLaunchKernelGGL((probe<OP, CH, AL>), dim3(blocks), dim3(64), 0, 0, d, 1u);  // warm-up
     (void)hipDeviceSynchronize();
     (void)hipEventRecord(e0);
-    hipLaunchKernelGGL((probe<OP, CH>), dim3(blocks), dim3(64), 0, 0, d, 2u);
+    hipLaunchKernelGGL((probe<OP, CH, AL>), dim3(blocks), dim3(64), 0, 0, d, 2u);
     (void)hipEventRecord(e1);
     (void)hipEventSynchronize(e1);
     float ms = 0.f;
@@ -104,12 +108,12 @@ Result run(unsigned long long *d, std::vector<unsigned long long> &h, int waves_
     return res;
 }
 
-template <int OP, int CH>
+template <int OP, int CH, int AL = 0>
 void report(const char *name, unsigned long long *d, std::vector<unsigned long long> &h, int w,
             const hipDeviceProp_t &prop, int wall_khz) {
-    const Result r = run<OP, CH>(d, h, w, prop, wall_khz);
+    const Result r = run<OP, CH, AL>(d, h, w, prop, wall_khz);
     const double per_cycle = r.clk_mhz > 0 ? r.event_rate / (r.clk_mhz * 1e6) / prop.multiProcessorCount : 0.0;
-    std::printf("%-16s waves/SIMD %d chains %2d  %.3e lane-ops/s  clock %5.0f MHz  %6.2f lane-ops/cycle/CU\n", name, w,
+    std::printf("%-18s waves/SIMD %d chains %2d  %.3e lane-ops/s  clock %5.0f MHz  %6.2f lane-ops/cycle/CU\n", name, w,
                 CH, r.event_rate, r.clk_mhz, per_cycle);
 }
 
@@ -138,6 +142,12 @@ int main() {
         report<0, 4>("v_mad_u64_u32", d, h, w, prop, wall_khz);
         report<0, 8>("v_mad_u64_u32", d, h, w, prop, wall_khz);
         report<0, 16>("v_mad_u64_u32", d, h, w, prop, wall_khz);
+    }
+    for (int w : {1, 2, 3, 8}) {
+        report<5, 16, 1>("own pairs, 0 mod 8", d, h, w, prop, wall_khz);
+        report<5, 8, 1>("own pairs, 0 mod 8", d, h, w, prop, wall_khz);
+        report<5, 16, 2>("own pairs, 4 mod 8", d, h, w, prop, wall_khz);
+        report<5, 8, 2>("own pairs, 4 mod 8", d, h, w, prop, wall_khz);
     }
     for (int w : {1, 2, 3, 4, 8}) {
         report<5, 2>("mad, own pairs", d, h, w, prop, wall_khz);

@@ -32,8 +32,9 @@ constexpr int groups_of(int nl) { return (nl + 3) / 4; }
 // Column alignment (a source that defines PMK_COLUMN_ALIGN to 1 before the
 // includes): each column of mont_mul / mont_sqr starts at an 8-byte boundary
 // (the assembler pads with s_nop), which keeps more of the 8-byte
-// v_mad_u64_u32 at addresses 0 modulo 8, where they issue faster, in kernels
-// whose code around the products would otherwise leave them at 4 modulo 8.
+// v_mad_u64_u32 at addresses 0 modulo 8, where the unrolled products run
+// faster, in kernels whose code around the products would otherwise leave them
+// at 4 modulo 8.
 #ifndef PMK_COLUMN_ALIGN
 #define PMK_COLUMN_ALIGN 0
 #endif
