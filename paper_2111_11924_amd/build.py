@@ -12,8 +12,9 @@ Code alignment: after compiling, the build reads where each kernel's
 v_mad_u64_u32 instructions landed (llvm-objdump of the objects' own gfx950
 code) and recompiles a source whose kernels have more than 60 % of them at addresses
 4 modulo 8, with those kernels listed in PMK_CODE_PAD (kernels_impl.hpp: they
-then start with one 4-byte s_nop).  The chosen lists are kept in
-_build/code_pad.json for incremental builds.
+then start with one 4-byte s_nop).  The decisions are kept in
+csrc/code_pad.json, which every build starts from: with unchanged sources and
+compiler no kernel needs a second compile.
 """
 from __future__ import annotations
 
@@ -45,7 +46,10 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 
 
 LLVM = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm", "bin")
-PADS = os.path.join(ROOT, "_build", "code_pad.json")
+# the padding decisions, kept beside the sources so that a build starts from
+# them: {"pad": {source: [code_id, ...]}, "fixed": {source: [code_id, ...]}}
+# ("fixed": kernels the 4 bytes do not move)
+PADS = os.path.join(CSRC, "code_pad.json")
 # kernel kinds: the numbers of CodeKind in kernels_impl.hpp
 CODE_KIND = {"encrypt_kernel": 1, "halves_kernel": 2, "halves_joint_kernel": 3, "halves_lanes_kernel": 4,
              "halves_lanes_joint_kernel": 5, "garner_kernel": 6, "garner_lds_kernel": 7, "batch_wide_kernel": 8,
@@ -130,10 +134,13 @@ def build_probe() -> str:
 def build(jobs: int = 8, verbose: bool = True, incremental: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     hdr = _headers_mtime()
-    pads = {}
-    if incremental and os.path.exists(PADS):
+    pads, fixed = {}, {}
+    if os.path.exists(PADS):
         with open(PADS) as f:
-            pads = {k: set(v) for k, v in json.load(f).items()}
+            saved = json.load(f)
+        pads = {k: set(v) for k, v in saved.get("pad", {}).items()}
+        fixed = {k: set(v) for k, v in saved.get("fixed", {}).items()}
+    first = {k: set(v) for k, v in pads.items()}, {k: set(v) for k, v in fixed.items()}
     kernels = [s for s in SOURCES if s.endswith(".hip")]
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         probe = None
@@ -149,7 +156,8 @@ def build(jobs: int = 8, verbose: bool = True, incremental: bool = False) -> str
             # parity) is left as it is; moving such a kernel measured either way
             # (the 2048-bit encryption, 54 % -> 46 %, took 16 % longer per
             # launch in the 1 MiB workload)
-            flips = {s: {i for i, (n, odd) in before[s].items() if n >= 64 and 5 * odd > 3 * n} for s in kernels}
+            flips = {s: {i for i, (n, odd) in before[s].items()
+                         if n >= 64 and 5 * odd > 3 * n and i not in fixed.get(s, ())} for s in kernels}
             flips = {s: f for s, f in flips.items() if f}
             for s, f in flips.items():
                 pads[s] = pads.get(s, set()) ^ f
@@ -161,6 +169,7 @@ def build(jobs: int = 8, verbose: bool = True, incremental: bool = False) -> str
             back = {s: b for s, b in back.items() if b}
             for s, b in back.items():
                 pads[s] ^= b
+                fixed[s] = fixed.get(s, set()) | b
             list(ex.map(lambda s: _compile(s, False, hdr, pads.get(s, ())), back))
             if verbose:
                 for s in flips:
@@ -168,8 +177,11 @@ def build(jobs: int = 8, verbose: bool = True, incremental: bool = False) -> str
                     print(f"code alignment: {s}: {len(pads.get(s, ()))} kernel(s) padded, "
                           f"{sum(v[1] for v in res.values())} of {sum(v[0] for v in res.values())} "
                           f"multiply-adds at 4 modulo 8")
-            with open(PADS, "w") as f:
-                json.dump({k: sorted(v) for k, v in pads.items() if v}, f)
+            if (pads, fixed) != first:
+                with open(PADS, "w") as f:
+                    json.dump({"pad": {k: sorted(v) for k, v in sorted(pads.items()) if v},
+                               "fixed": {k: sorted(v) for k, v in sorted(fixed.items()) if v}}, f, indent=1)
+                    f.write("\n")
         elif verbose:
             print("code alignment: llvm tools not found, kernels left unpadded")
         if probe is not None:
