@@ -480,6 +480,8 @@ def main() -> int:
     ap.add_argument("--mode", choices=["plain", "batch"], default="plain",
                     help="plain: per-class launches, each timed with HIP events during the timed steps; "
                          "batch: graph-captured batched path (kernel times from one extra profiled step)")
+    ap.add_argument("--lib", default=None, metavar="PATH",
+                    help="load this build of libpmk.so instead of the package's own (A/B of two builds)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -493,6 +495,8 @@ def main() -> int:
 
     from paper_2111_11924_amd import binding, inputs
 
+    if args.lib:
+        binding.LIB_PATH = os.path.abspath(args.lib)
     if args.serve:
         res = serve_measure(args.serve_requests or 2000, [0.5, 0.8, 1.2], round_chunks=args.round_chunks,
                             pipeline_depth=args.pipeline_depth)
@@ -616,7 +620,7 @@ def main() -> int:
     achieved = halves_work / halves_avg_s
 
     traffic = None
-    if (args.config == 4 and args.window in (0, 5) and not args.autotune and HALVES_TRAFFIC["fetch_bytes"]
+    if (args.config == 4 and args.window in (0, 5) and not args.autotune and not args.lib and HALVES_TRAFFIC["fetch_bytes"]
             and HALVES_TRAFFIC["sources_sha256"] == kernel_sources_sha256()):
         traffic = HALVES_TRAFFIC["fetch_bytes"] + HALVES_TRAFFIC["write_bytes"]
     wall_s = t1 - t0
